@@ -1,0 +1,383 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test states the fact it checks.  None of them re-types the oracle's own
+formula: they use closed forms (cos n theta, exact cutoff values, affine
+compositions), invariances, finite differences, brute-force image sums and
+integrator identities.
+"""
+import numpy as np
+import pytest
+from numpy.polynomial import chebyshev as npcheb
+
+from paper_2107_11311_amd import inputs as I
+
+OPEN = np.zeros(3, dtype=np.uint8)
+BIG = np.array([100.0, 100.0, 100.0])
+
+
+def tiny_model(S=2, nr=5, rr=6.0, na=4, ra=4.0, hidden=(7, 5), tw=None, seed=3, act=I.ACT_TANH):
+    typed = nr + 1 + na + 1
+    D = 2 * typed if S > 1 else typed
+    nets = []
+    for t in range(S):
+        n = I.xavier_net([D, *hidden, 1], seed + 10 * t, act_hidden=act)
+        nets.append(n)
+    tw = I.default_type_weights(S) if tw is None else np.asarray(tw, float)
+    return I.ModelSpec(S, tw, np.ones(S), nr, rr, na, ra, nets)
+
+
+def normalised(model, seed=5):
+    g = np.random.default_rng(seed)
+    for n in model.nets:
+        n.shift = g.normal(size=model.D)
+        n.scale = g.uniform(0.2, 1.0, size=model.D)
+        n.e_offset = float(g.normal())
+    return model
+
+
+# ---------------------------------------------------------------- Eq. 4
+@pytest.mark.parametrize("order", [0, 1, 2, 8, 18])
+def test_chebyshev_closed_forms(orc, order):
+    for theta in np.linspace(0.05, np.pi - 0.05, 17):
+        T, dT = orc.chebyshev(order, np.cos(theta))
+        n = np.arange(order + 1)
+        # T_n(cos t) = cos(n t);  T_n'(cos t) = n sin(n t) / sin t
+        np.testing.assert_allclose(T, np.cos(n * theta), atol=1e-12)
+        np.testing.assert_allclose(dT, n * np.sin(n * theta) / np.sin(theta), atol=1e-10 * max(1, order ** 2))
+    for x in (1.0, -1.0):
+        T, dT = orc.chebyshev(order, x)
+        n = np.arange(order + 1)
+        np.testing.assert_array_equal(T, x ** n)
+        np.testing.assert_allclose(dT, n * n * x ** (n + 1), atol=1e-12)  # T_n'(+-1) = (+-1)^(n+1) n^2
+    # library special case
+    for x in np.linspace(-1.3, 1.3, 11):
+        T, dT = orc.chebyshev(order, x)
+        for a in range(order + 1):
+            c = np.zeros(a + 1)
+            c[a] = 1.0
+            assert abs(T[a] - npcheb.chebval(x, c)) <= 1e-11 * max(1.0, abs(T[a]))
+            assert abs(dT[a] - npcheb.chebval(x, npcheb.chebder(c))) <= 1e-10 * max(1.0, abs(dT[a]))
+
+
+# ---------------------------------------------------------------- Eq. 5
+def test_cutoff_values(orc):
+    R = 6.5
+    fc, dfc = orc.cutoff(0.0, R)
+    assert fc == 1.0 and dfc == 0.0
+    fc, dfc = orc.cutoff(R / 2, R)
+    assert abs(fc - 0.5) < 1e-15 and abs(dfc + np.pi / (2 * R)) < 1e-15
+    fc, dfc = orc.cutoff(R, R)
+    assert abs(fc) < 1e-15 and abs(dfc) < 1e-15
+    fc, dfc = orc.cutoff(R * 1.0001, R)
+    assert fc == 0.0 and dfc == 0.0
+    # monotone decreasing on [0, R]
+    vals = [orc.cutoff(r, R)[0] for r in np.linspace(0, R, 50)]
+    assert np.all(np.diff(vals) < 0)
+
+
+# ---------------------------------------------------------------- Eq. 3 (dimer)
+@pytest.mark.parametrize("tw", [None, (1.0, 2.0)])
+def test_dimer_radial_closed_form(orc, tw):
+    m = tiny_model(S=2, nr=9, rr=6.0, na=4, ra=2.0, tw=tw)
+    w = m.type_weight
+    r = 3.0  # = R/2: x = 0, f_c = 1/2, T_a(0) = cos(a pi/2)
+    pos = np.array([[10.0, 10.0, 10.0], [10.0 + r / np.sqrt(3), 10.0 + r / np.sqrt(3), 10.0 + r / np.sqrt(3)]])
+    sp = np.array([0, 1])
+    G = orc.descriptors(m, pos, sp, BIG, OPEN)
+    a = np.arange(10)
+    expect = 0.5 * np.round(np.cos(a * np.pi / 2))
+    D1 = 10 + 5
+    for i, other in ((0, 1), (1, 0)):
+        np.testing.assert_allclose(G[i, :10], expect, atol=1e-14)       # typed radial
+        np.testing.assert_array_equal(G[i, 10:15], 0.0)                 # no angular pairs
+        np.testing.assert_allclose(G[i, D1:D1 + 10], w[sp[other]] * expect, atol=1e-14)
+        np.testing.assert_array_equal(G[i, D1 + 10:], 0.0)
+    # a generic distance: T_a(2r/R - 1) = cos(a * arccos(2r/R - 1))
+    r = 4.1
+    pos[1] = pos[0] + np.array([r, 0.0, 0.0])
+    G = orc.descriptors(m, pos, sp, BIG, OPEN)
+    x = 2 * r / 6.0 - 1
+    fc = 0.5 * (np.cos(np.pi * r / 6.0) + 1)
+    np.testing.assert_allclose(G[0, :10], np.cos(a * np.arccos(x)) * fc, atol=1e-13)
+
+
+# ---------------------------------------------------------------- Eq. 6 (trimer)
+@pytest.mark.parametrize("theta_deg", [60.0, 90.0, 180.0, 37.0])
+def test_trimer_angular_closed_form(orc, theta_deg):
+    m = tiny_model(S=3, nr=3, rr=6.0, na=6, ra=4.0, tw=(1.0, 2.0, 3.0))
+    th = np.deg2rad(theta_deg)
+    a = b = 2.0  # R_a / 2  -> f_c = 1/2 each
+    c = np.array([20.0, 20.0, 20.0])
+    pos = np.array([c, c + [a, 0, 0], c + [b * np.cos(th), b * np.sin(th), 0.0]])
+    sp = np.array([0, 1, 2])
+    G = orc.descriptors(m, pos, sp, BIG * 0.5, OPEN)
+    al = np.arange(7)
+    # ordered pairs (j,k) and (k,j): 2 cos(a theta) f f
+    expect = 2.0 * np.cos(al * th) * 0.25
+    off_at = 4
+    off_aw = 2 * (4 + 7) - 7
+    np.testing.assert_allclose(G[0, off_at:off_at + 7], expect, atol=1e-13)
+    np.testing.assert_allclose(G[0, off_aw:off_aw + 7], 2.0 * 3.0 * expect, atol=1e-13)
+
+
+# ---------------------------------------------------------------- Eq. 1 closed form
+def test_linear_network_is_affine(orc):
+    g = np.random.default_rng(1)
+    D = 9
+    W = [g.normal(size=(6, D)), g.normal(size=(4, 6)), g.normal(size=(1, 4))]
+    b = [g.normal(size=6), g.normal(size=4), g.normal(size=1)]
+    net = I.NetSpec(W, b, [I.ACT_LINEAR] * 3, g.normal(size=D), g.uniform(0.5, 2, size=D), 0.7)
+    A = W[2] @ W[1] @ W[0]
+    c = W[2] @ (W[1] @ b[0] + b[1]) + b[2]
+    for _ in range(5):
+        G = g.normal(size=D)
+        E, grad = orc.net_eval(net, G)
+        x0 = (G - net.shift) * net.scale
+        assert abs(E - ((A @ x0)[0] + c[0] + 0.7)) < 1e-12
+        np.testing.assert_allclose(grad, A[0] * net.scale, atol=1e-12)
+
+
+def test_tanh_network_gradient_fd(orc):
+    g = np.random.default_rng(2)
+    net = I.xavier_net([11, 8, 6, 1], 99)
+    net.shift = g.normal(size=11)
+    net.scale = g.uniform(0.5, 2, size=11)
+    G = g.normal(size=11)
+    _, grad = orc.net_eval(net, G)
+    h = 1e-6
+    fd = np.array([(orc.net_eval(net, G + h * e)[0] - orc.net_eval(net, G - h * e)[0]) / (2 * h)
+                   for e in np.eye(11)])
+    np.testing.assert_allclose(grad, fd, atol=1e-9)
+
+
+def test_isolated_atom(orc):
+    m = normalised(tiny_model(S=2))
+    pos = np.array([[10.0, 10.0, 10.0], [40.0, 40.0, 40.0]])
+    sp = np.array([0, 1])
+    E, Ea, F, G = orc.energy_forces(m, pos, sp, BIG, OPEN, want_G=True)
+    assert np.all(G == 0.0) and np.all(F == 0.0)
+    for i in range(2):
+        assert Ea[i] == orc.net_eval(m.nets[sp[i]], np.zeros(m.D))[0]
+    assert E == Ea.sum()
+
+
+# ---------------------------------------------------------------- forces
+@pytest.fixture(scope="module")
+def water_small():
+    s = I.water_box(24, 777)
+    m = normalised(tiny_model(S=2, nr=8, rr=4.2, na=4, ra=3.5, hidden=(9, 7)), 11)
+    return m, s
+
+
+def test_forces_match_central_differences(orc, water_small):
+    m, s = water_small
+    _, _, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    g = np.random.default_rng(4)
+    h = 1e-5
+    for i in g.choice(len(s.pos), 8, replace=False):
+        for c in range(3):
+            p = s.pos.copy(); p[i, c] += h
+            Ep = orc.energy_forces(m, p, s.species, s.box, s.pbc)[0]
+            p = s.pos.copy(); p[i, c] -= h
+            Em = orc.energy_forces(m, p, s.species, s.box, s.pbc)[0]
+            fd = -(Ep - Em) / (2 * h)
+            assert abs(F[i, c] - fd) <= 1e-7 * max(1.0, abs(F[i, c])), (i, c, F[i, c], fd)
+
+
+def test_two_force_formulations_agree(orc, water_small):
+    m, s = water_small
+    _, _, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    Fd = orc.forces_dense(m, s.pos, s.species, s.box, s.pbc)
+    np.testing.assert_allclose(Fd, F, atol=1e-13 * max(1.0, np.abs(F).max()))
+
+
+def test_net_force_is_zero(orc, water_small):
+    m, s = water_small
+    _, _, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    assert np.abs(F.sum(0)).max() <= 1e-12 * np.abs(F).sum()
+
+
+# ---------------------------------------------------------------- symmetries (Sec. II B)
+def test_translation_invariance(orc, water_small):
+    m, s = water_small
+    E, Ea, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    shift = np.array([1.234, -3.21, 0.777])
+    E2, Ea2, F2 = orc.energy_forces(m, s.pos + shift, s.species, s.box, s.pbc)
+    assert abs(E2 - E) <= 1e-12 * abs(E)
+    np.testing.assert_allclose(F2, F, atol=1e-11)
+
+
+def test_cubic_point_group(orc, water_small):
+    m, s = water_small
+    L = s.box[0]
+    E, Ea, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    g = np.random.default_rng(6)
+    for _ in range(4):
+        P = np.eye(3)[g.permutation(3)] * g.choice([-1.0, 1.0], size=3)[:, None]
+        pos2 = (s.pos @ P.T) % L
+        E2, Ea2, F2 = orc.energy_forces(m, pos2, s.species, s.box, s.pbc)
+        assert abs(E2 - E) <= 1e-12 * abs(E)
+        np.testing.assert_allclose(Ea2, Ea, atol=1e-12)
+        np.testing.assert_allclose(F2, F @ P.T, atol=1e-11)
+
+
+def test_rotation_invariance_cluster(orc):
+    m = normalised(tiny_model(S=2, nr=6, rr=5.0, na=5, ra=4.0), 8)
+    s = I.water_box(8, 31)
+    pos = s.pos - s.pos.mean(0)
+    R = I.random_rotations(3, I.rng(5))
+    E, Ea, F = orc.energy_forces(m, pos + 50.0, s.species, BIG, OPEN)
+    for Rm in R:
+        E2, Ea2, F2 = orc.energy_forces(m, pos @ Rm.T + 50.0, s.species, BIG, OPEN)
+        assert abs(E2 - E) <= 1e-12 * abs(E)
+        np.testing.assert_allclose(Ea2, Ea, atol=1e-12)
+        np.testing.assert_allclose(F2, F @ Rm.T, atol=1e-11)
+
+
+def test_permutation_equivariance(orc, water_small):
+    m, s = water_small
+    E, Ea, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    p = np.random.default_rng(9).permutation(len(s.pos))
+    E2, Ea2, F2 = orc.energy_forces(m, s.pos[p], s.species[p], s.box, s.pbc)
+    assert abs(E2 - E) <= 1e-12 * abs(E)
+    np.testing.assert_allclose(Ea2, Ea[p], atol=1e-12)
+    np.testing.assert_allclose(F2, F[p], atol=1e-11)
+
+
+def test_small_box_images_equal_supercell(orc):
+    """A box smaller than twice the cutoff (several images of one atom are
+    neighbours) equals a 3x3x3 supercell evaluated with minimum images."""
+    m = normalised(tiny_model(S=2, nr=6, rr=6.0, na=4, ra=4.0), 12)
+    s = I.water_box(8, 55)
+    L = s.box[0]
+    assert L < 2 * 6.0
+    E, Ea, F = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    shifts = np.array([[a, b, c] for a in range(3) for b in range(3) for c in range(3)], float)
+    big = np.concatenate([s.pos + L * sh for sh in shifts])
+    spb = np.tile(s.species, 27)
+    Eb, Eab, Fb = orc.energy_forces(m, big, spb, s.box * 3, s.pbc)
+    assert abs(Eb - 27 * E) <= 1e-11 * abs(Eb)
+    np.testing.assert_allclose(Eab[: len(s.pos)], Ea, atol=1e-12)
+    np.testing.assert_allclose(Fb[: len(s.pos)], F, atol=1e-11)
+
+
+def test_neighbor_enumeration_images(orc):
+    s = I.water_box(8, 55)
+    nb = orc.neighbors(s.pos, s.box, s.pbc, 7.0)
+    # symmetry: (i -> j, s) present iff (j -> i, -s) present
+    sets = [set((int(j), tuple(sh)) for j, sh in zip(js, ss)) for js, ss in nb]
+    for i, st in enumerate(sets):
+        for j, sh in st:
+            assert (i, tuple(-np.array(sh))) in sets[j]
+    # every entry is within the cutoff and the count matches a density estimate
+    cnt = np.array([len(st) for st in sets])
+    assert abs(cnt.mean() - len(s.pos) / s.box.prod() * 4 / 3 * np.pi * 7.0 ** 3) < 0.3 * cnt.mean()
+
+
+def test_cutoff_continuity(orc):
+    """Crossing a cutoff changes E only at second order (f_c and f_c' vanish at R)."""
+    # radial cutoff: a dimer crossing R_r
+    m = normalised(tiny_model(S=2, nr=7, rr=5.0, na=4, ra=3.0), 13)
+    sp = np.array([0, 1])
+    out = []
+    for r in (5.0 - 1e-4, 5.0 + 1e-4):
+        pos = np.array([[10.0, 10.0, 10.0], [10.0 + r, 10.0, 10.0]])
+        out.append(orc.energy_forces(m, pos, sp, BIG, OPEN))
+    assert abs(out[0][0] - out[1][0]) < 1e-6
+    assert np.abs(out[0][2]).max() < 1e-2 and np.abs(out[1][2]).max() == 0.0
+    # angular cutoff (equal radii so both channels cross together): k leaves i's shell
+    m = normalised(tiny_model(S=2, nr=7, rr=3.0, na=4, ra=3.0), 14)
+    sp = np.array([0, 1, 0])
+    out = []
+    for r in (3.0 - 1e-4, 3.0 + 1e-4):
+        pos = np.array([[10.0, 10.0, 10.0], [8.0, 10.0, 10.0], [10.0 + r * 0.6, 10.0 + r * 0.8, 10.0]])
+        out.append(orc.energy_forces(m, pos, sp, BIG, OPEN))
+    assert abs(out[0][0] - out[1][0]) < 1e-6
+    assert np.abs(out[0][2][2]).max() < 1e-2 and np.abs(out[1][2][2]).max() == 0.0
+
+
+# ---------------------------------------------------------------- MD (Fig. 1 cycle)
+@pytest.fixture(scope="module")
+def md_setup():
+    s = I.water_box(16, 101)
+    m = normalised(tiny_model(S=2, nr=6, rr=4.0, na=3, ra=3.0, hidden=(8, 8)), 14)
+    masses = np.array([I.MASS["H"], I.MASS["O"]])
+    v = I.maxwell_boltzmann(masses[s.species], 300.0, 5)
+    return m, s, masses, v
+
+
+def test_velocity_verlet_reversible(orc, md_setup):
+    m, s, masses, v = md_setup
+    p1, v1, _, _, _ = orc.md_vv(m, s.pos, v, s.species, masses, s.box, s.pbc, 5e-4, 20)
+    p2, v2, _, _, _ = orc.md_vv(m, p1, -v1, s.species, masses, s.box, s.pbc, 5e-4, 20)
+    d = (p2 - s.pos + s.box / 2) % s.box - s.box / 2
+    assert np.abs(d).max() < 1e-10
+    np.testing.assert_allclose(-v2, v, atol=1e-9)
+
+
+def test_nve_energy_error_scales_dt2(orc, md_setup):
+    m, s, masses, v = md_setup
+
+    def max_dev(dt, nsteps):
+        p, vv = s.pos.copy(), v.copy()
+        e0 = None
+        dev = 0.0
+        for _ in range(nsteps):
+            p, vv, ep, ek, _ = orc.md_vv(m, p, vv, s.species, masses, s.box, s.pbc, dt, 1)
+            et = ep + ek
+            if e0 is None:
+                _, _, ep0, ek0, _ = orc.md_vv(m, s.pos, v, s.species, masses, s.box, s.pbc, dt, 0)
+                e0 = ep0 + ek0
+            dev = max(dev, abs(et - e0))
+        return dev
+
+    d1 = max_dev(1e-3, 20)
+    d2 = max_dev(5e-4, 40)
+    assert 2.5 < d1 / d2 < 5.5, (d1, d2)
+
+
+def test_maxwell_boltzmann_temperature():
+    masses = np.array([I.MASS["H"], I.MASS["O"]])[np.tile([1, 0, 0], 100)]
+    v = I.maxwell_boltzmann(masses, 300.0, 3)
+    ke = 0.5 * (masses[:, None] * v * v).sum() / I.KAPPA
+    assert abs(2 * ke / ((3 * len(masses) - 3) * I.KB_EV) - 300.0) < 1e-9
+    assert np.abs((masses[:, None] * v).sum(0)).max() < 1e-10
+
+
+# ---------------------------------------------------------------- training loss (Sec. II C)
+def test_loss_gradient_matches_central_differences(orc):
+    m = normalised(tiny_model(S=2, nr=5, rr=5.0, na=3, ra=3.5, hidden=(6, 5)), 21)
+    ref = normalised(tiny_model(S=2, nr=5, rr=5.0, na=3, ra=3.5, hidden=(6, 5), seed=77), 22)
+    boxes = [I.water_box(6, 41), I.water_box(10, 42)]
+    offs = [0]
+    for b in boxes:
+        offs.append(offs[-1] + len(b.pos))
+    pos = np.vstack([b.pos for b in boxes])
+    sp = np.concatenate([b.species for b in boxes])
+    bx = np.vstack([b.box for b in boxes])
+    er, fr = [], []
+    for b in boxes:
+        E, _, F = orc.energy_forces(ref, b.pos, b.species, b.box, b.pbc)
+        er.append(E); fr.append(F)
+    er = np.array(er); fr = np.vstack(fr)
+    L, grad = orc.loss_grad(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0)
+    assert L == pytest.approx(orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0), rel=1e-14)
+    p0 = orc.all_params(m)
+    h = 1e-5
+    for k in range(len(p0)):
+        if k % 7:
+            continue
+        pp = p0.copy(); pp[k] += h
+        Lp = orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, params=pp)
+        pp = p0.copy(); pp[k] -= h
+        Lm = orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, params=pp)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(grad[k] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(grad).max()), (k, grad[k], fd)
+
+
+def test_loss_zero_at_reference(orc):
+    m = normalised(tiny_model(S=2, nr=4, rr=4.0, na=2, ra=3.0), 23)
+    b = I.water_box(6, 43)
+    E, _, F = orc.energy_forces(m, b.pos, b.species, b.box, b.pbc)
+    L, grad = orc.loss_grad(m, [0, len(b.pos)], b.pos, b.species, b.box, [1, 1, 1], [E], F, 1.0)
+    assert L == 0.0 and np.all(grad == 0.0)
