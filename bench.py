@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of ANN-potential molecular dynamics on one MI355X.
+
+A step is one velocity-Verlet NVE step of the whole hot path (neighbour-list
+check/rebuild, Chebyshev descriptors, per-species networks, force
+back-propagation and gather, integration) over the water4096 workload:
+4096 rigid-geometry H2O (12,288 atoms) at 1.0 g/cm^3, radial order 16 within
+6.5 A, angular order 8 within 4.0 A (D = 52), 52-25-25-1 tanh networks,
+dt = 0.25 fs, Maxwell-Boltzmann velocities at 300 K, skin 0.5 A.  Inputs are
+seeded and synthetic (the paper's trained water potential is not available).
+
+Prints one JSON line: atom-steps/s of the FP64 path (value), the FP32 and BF16
+network modes beside it, force RMSE against the FP64 oracle on the final
+positions, the roofline position of the dominant kernel (timed with HIP events
+on the launch stream) and the oracle's own throughput on the host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK = 78.6e12     # MI355X vector FP64, FLOP/s
+FP32_VALU_PEAK = 157.3e12    # MI355X vector FP32 (packed), FLOP/s
+WORKLOAD = "water4096"
+KERNEL_SOURCES = {"desc_fwd": "desc.hip", "desc_bwd": "desc.hip", "network": "mlp.hip",
+                  "neighbor": "nbr.hip", "force_gather": "md.hip", "integrate": "md.hip"}
+
+
+def algorithmic_flops(kernel, nr_order, na_order, n_r, n_a, widths):
+    """Algorithmic floating-point operations per atom of one kernel launch (the
+    minimum the method needs: unordered angular pairs, no recomputation; a
+    transcendental counts as one operation).  n_r, n_a: mean neighbours within
+    the radial / angular cutoff; widths: network widths D, H1, ..., 1."""
+    pairs = n_a * (n_a - 1) / 2.0
+    if kernel == "desc_fwd":
+        radial = n_r * (6 * nr_order + 14)          # distance, x, f_c, recurrence, 2 channels
+        angular = pairs * (6 * na_order + 9) + 15 * n_a
+        return radial + angular
+    if kernel == "desc_bwd":
+        radial = n_r * (8 * nr_order + 20)          # T and U recurrences, 4 sums, f_c, f_c', vector
+        angular = pairs * (8 * na_order + 33) + 20 * n_a
+        return radial + angular
+    if kernel == "network":
+        mac = sum(widths[i] * widths[i + 1] for i in range(len(widths) - 1))
+        return 4.0 * mac + 4.0 * sum(widths[1:-1])  # forward + input gradient, tanh + derivative
+    if kernel == "force_gather":
+        return 3.0 * n_r * 1.0
+    return 0.0
+
+
+def mean_counts(pos, box, rr, ra):
+    from scipy.spatial import cKDTree
+    import numpy as np
+    t = cKDTree(pos, boxsize=box)
+    nr = np.array([len(x) - 1 for x in t.query_ball_point(pos, rr - 1e-12)]).mean()
+    na = np.array([len(x) - 1 for x in t.query_ball_point(pos, ra - 1e-12)]).mean()
+    return float(nr), float(na)
+
+
+def source_hash(name):
+    with open(os.path.join(ROOT, "paper_2107_11311_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload, precision):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None
+    if there are none or the kernel source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(f"{kernel}/{workload}/{precision}")
+    if not rec or rec.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_mode(A, model, sysm, vel0, precision, steps, warmup, dt, profile):
+    import torch
+    dev = torch.device("cuda:0")
+    ctx = A.Context(model, precision, skin=0.5, device=0)
+    pos = torch.from_numpy(sysm.pos.copy()).to(dev)
+    vel = torch.from_numpy(vel0.copy()).to(dev)
+    n = sysm.pos.shape[0]
+    ep = torch.zeros(1, dtype=torch.float64, device=dev)
+    ek = torch.zeros(1, dtype=torch.float64, device=dev)
+    F = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+    if warmup:
+        ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, warmup, ep, ek, F)
+    torch.cuda.synchronize()
+    e0 = (ep + ek).item()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, steps, ep, ek, F)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    e1 = (ep + ek).item()
+    out = dict(atom_steps_per_s=n * steps / wall, ms_per_step=1e3 * wall / steps,
+               gpu_ms_per_step=gpu_ms / steps, e_total_start=e0, e_total_end=e1,
+               rebuilds=ctx.stats()["n_rebuilds"])
+    if profile:
+        # timing pass: the same steps again, every kernel bracketed by HIP events
+        ctx.set_profiling(True)
+        ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, steps, ep, ek, F)
+        torch.cuda.synchronize()
+        out["kernel_times"] = ctx.kernel_times()
+        ctx.set_profiling(False)
+    # forces on the final positions, for the comparison with the oracle
+    pos_np = pos.cpu().numpy()
+    et = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.energy_forces_dev(pos, sysm.species, sysm.box, sysm.pbc, et, None, F)
+    torch.cuda.synchronize()
+    out["final_pos"] = pos_np
+    out["final_F"] = F.cpu().numpy()
+    out["final_E"] = et.item()
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--modes", default="fp64,fp32,bf16")
+    ap.add_argument("--cpu-sample-calls", type=int, default=2,
+                    help="oracle energy+force calls on the full box for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(DESIGN.md describes how the path would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2107_11311_amd import aenet as A
+    from paper_2107_11311_amd import inputs as I
+
+    cfg = I.CONFIGS[WORKLOAD]
+    model = I.load_model(WORKLOAD)
+    sysm = I.make_system(WORKLOAD)
+    n = sysm.pos.shape[0]
+    vel0 = I.maxwell_boltzmann(model.masses[sysm.species], cfg["T"], I.seed_for(cfg["cfg"], 2))
+    dt = cfg["dt_fs"] * 1e-3
+    A.load()
+
+    modes = [m for m in args.modes.split(",") if m]
+    res = {}
+    for m in modes:
+        res[m] = run_mode(A, model, sysm, vel0, m, args.steps, args.warmup, dt, profile=(m == "fp64"))
+    main_mode = "fp64" if "fp64" in res else modes[0]
+    r = res[main_mode]
+
+    # roofline of the dominant kernel of the FP64 path
+    roofline = None
+    if "kernel_times" in r:
+        kt = r["kernel_times"]
+        dom = max(kt, key=lambda k: kt[k][0])
+        ms, launches = kt[dom]
+        avg_s = ms / launches * 1e-3
+        n_r, n_a = mean_counts(sysm.pos, sysm.box, model.radial_cutoff, model.angular_cutoff)
+        widths = [model.D] + [w.shape[0] for w in model.nets[0].W]
+        fl = algorithmic_flops(dom, model.radial_order, model.angular_order, n_r, n_a, widths) * n
+        achieved = fl / avg_s
+        roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=FP64_VALU_PEAK / 1e12,
+                        unit="TFLOP/s", frac=achieved / FP64_VALU_PEAK,
+                        traffic=stored_traffic(dom, WORKLOAD, main_mode),
+                        avg_launch_ms=ms / launches, launches=launches,
+                        flops_per_launch=fl, mean_neighbors_radial=n_r, mean_neighbors_angular=n_a,
+                        kernel_ms_per_step={k: v[0] / max(v[1], 1) * (v[1] / args.steps)
+                                            for k, v in kt.items()})
+
+    # oracle on the host: its throughput, and the force RMSE of every mode
+    cpu = None
+    modes_out = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        times = []
+        ref = {}
+        for m in res:
+            t0 = time.perf_counter()
+            E0, _, F0 = oracle.energy_forces(model, res[m]["final_pos"], sysm.species, sysm.box, sysm.pbc)
+            times.append(time.perf_counter() - t0)
+            ref[m] = (E0, F0)
+        while len(times) < args.cpu_sample_calls:
+            t0 = time.perf_counter()
+            oracle.energy_forces(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
+            times.append(time.perf_counter() - t0)
+        t_call = float(np.mean(times))
+        cpu = dict(value=n / t_call, unit="atom-steps/s", cores=1, kind="oracle",
+                   sample=f"{len(times)} single-threaded FP64 oracle energy+force evaluations of the full "
+                          f"{n}-atom box (brute-force neighbours), {t_call:.2f} s each; one MD step = one "
+                          f"evaluation")
+        for m in res:
+            E0, F0 = ref[m]
+            dF = res[m]["final_F"] - F0
+            modes_out[m] = dict(atom_steps_per_s=res[m]["atom_steps_per_s"],
+                                ms_per_step=res[m]["ms_per_step"],
+                                force_rmse=float(np.sqrt(np.mean(dF ** 2))),
+                                force_rms=float(np.sqrt(np.mean(F0 ** 2))),
+                                energy_rel_err=abs(res[m]["final_E"] - E0) / abs(E0),
+                                nve_drift_ev_per_atom=(res[m]["e_total_end"] - res[m]["e_total_start"]) / n,
+                                rebuilds=res[m]["rebuilds"])
+    else:
+        for m in res:
+            modes_out[m] = dict(atom_steps_per_s=res[m]["atom_steps_per_s"], ms_per_step=res[m]["ms_per_step"])
+
+    line = {
+        "metric": "atom-steps/s (energy+forces) on 1 MI355X; force RMSE vs FP64 oracle",
+        "value": r["atom_steps_per_s"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_mode == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "water4096: 4096 rigid H2O (12288 atoms) at 1.0 g/cm3 in a 49.67 A periodic box; "
+                               "radial order 16 / 6.5 A, angular order 8 / 4.0 A (D=52); 52-25-25-1 tanh; "
+                               "NVE velocity Verlet, dt 0.25 fs, 300 K, skin 0.5 A",
+                   "atoms": n, "mode": main_mode},
+        "modes": modes_out,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

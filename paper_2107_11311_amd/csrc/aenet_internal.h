@@ -1,0 +1,169 @@
+// aenet_internal.h -- declarations shared by the translation units of the
+// GPU library (host runtime + kernels).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace aenet {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxLayers = 4;  // weight layers
+constexpr int kMaxWidth = 64;
+constexpr int kPad = 32;       // every network width is padded to a multiple of this
+
+// A neighbour entry packs the neighbour's internal atom index (low 27 bits)
+// with its periodic-image code (high 5 bits): code = (sx+1) + 3(sy+1) + 9(sz+1)
+// for an image shift s in {-1,0,1}^3, displacement d = r_j + s*L - r_i.
+constexpr int kImgBits = 27;
+constexpr uint32_t kAtomMask = (1u << kImgBits) - 1u;
+constexpr int64_t kMaxAtoms = (int64_t)kAtomMask;
+
+// device status flags (bitmask in ctx flags word)
+constexpr int kFlagOverflow = 1;   // a neighbour row exceeded its capacity
+constexpr int kFlagOverlap = 2;    // two distinct entries at distance 0
+constexpr int kFlagReverse = 4;    // reverse entry not found (asymmetric list)
+constexpr int kFlagNonFinite = 8;  // NaN/Inf in positions
+
+struct BoxInfo {
+  double L[3];
+  int nc[3];      // cells per axis
+  int cell_base;  // first global cell id of this structure
+};
+
+// ---------------------------------------------------------------- neighbour list
+struct NbrParams {
+  int n;                 // atoms
+  double* pos;           // [n*3] internal order (wrapped in place by k_bin)
+  double* pos_ref;       // [n*3] positions at the last build
+  const int* seg;        // [n] structure id
+  const BoxInfo* boxes;  // [n_struct]
+  int pbc[3];
+  int n_cells;
+  double r_list2;        // (max(R_r,R_a) + skin)^2
+  double r_ang2;         // (R_a + skin)^2
+  int cap, cap_ang;
+  int* cell_count;       // [n_cells]
+  int* cell_start;       // [n_cells+1]
+  int* cell_fill;        // [n_cells]
+  int* cell_atoms;       // [n]
+  int* atom_cell;        // [n]
+  uint32_t* nbr;         // [n*cap]
+  int* nnb;              // [n]
+  int* nang;             // [n]
+  int* rev;              // [n*cap] global index of the reverse entry
+  int* flags;
+  int* maxcnt;           // [2] largest row, largest angular prefix
+  const int* cond;       // build only if *cond != 0 (NULL = always)
+};
+void launch_build_neighbors(const NbrParams& p, hipStream_t s);
+void launch_set_int(int* dst, int value, hipStream_t s);
+
+// ---------------------------------------------------------------- descriptors
+struct DescParams {
+  int n;
+  const double* pos;
+  const int* species;
+  const int* seg;
+  const BoxInfo* boxes;
+  const uint32_t* nbr;
+  const int* nnb;
+  const int* nang;
+  int cap, cap_ang;
+  double rr, ra;
+  double tw[kMaxSpecies];
+  int weighted;          // n_species > 1
+  int ldG;               // row stride of G / dE/dG
+  void* G;               // [n x ldG] (float or double)
+  const void* gG;        // dE/dG [n x ldG]
+  void* pg;              // [n*cap*3] per-entry dE_i/dd
+  double* Fself;         // [n*3]  sum_e pg
+  const double* adj;     // [n*3] JVP direction (loss adjoint of the forces)
+  void* U;               // [n x ldG] JVP output
+  int* flags;
+};
+// prec: 0 = double arithmetic, 1 = float arithmetic
+bool desc_supported(int nr, int na);
+int desc_supported_list(int* orders, int max_pairs);
+void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s);
+void launch_desc_bwd(int prec, int nr, int na, const DescParams& p, hipStream_t s);
+void launch_desc_jvp(int prec, int nr, int na, const DescParams& p, hipStream_t s);
+
+// ---------------------------------------------------------------- networks
+struct MlpNet {          // device pointers of one species (compute type T = double/float)
+  const void* wf[kMaxLayers];   // packed forward B operands, hidden layers 1..L-1
+  const void* wb[kMaxLayers];   // packed backward B operands, layers 1..L-1
+  const void* bias[kMaxLayers]; // biases of layers 1..L-1 (compute type, padded)
+  const void* wlast;            // last layer weights (compute type, padded)
+  const void* shift;            // [ldG] compute type (zero padded)
+  const void* scale;            // [ldG] compute type (zero padded)
+  const void* wfull[kMaxLayers + 1];  // plain row-major W_l (compute type) for training
+  double blast;
+  double e_offset;
+};
+struct MlpParams {
+  int n_species;
+  int sp_off[kMaxSpecies + 1];    // internal atom ranges per species
+  int tile_off[kMaxSpecies + 1];  // tile ranges per species (16 atoms per tile)
+  int n_layers;                   // weight layers L (>= 1)
+  int w[kMaxLayers + 1];          // true widths
+  int wp[kMaxLayers + 1];         // padded widths (multiple of kPad)
+  int act[kMaxLayers];
+  int ldG;
+  MlpNet net[kMaxSpecies];
+  const void* G;
+  void* gG;                       // dE/dG output (NULL: energies only)
+  double* E;                      // [n] per-atom energies (internal order)
+  // training (double back-propagation)
+  const void* U;                  // [n x ldG] descriptor JVP u_i
+  const double* eps_atom;         // [n] dC/dE for each atom (its structure's value)
+  double* grad_part;              // [n_blocks x n_params_padded] per-block partial gradients
+  int n_params_pad;               // stride of grad_part
+  int param_off[kMaxSpecies];     // offset of each species inside a partial gradient row
+  int tiles_per_block;
+};
+// prec: 0 fp64 (MFMA f64), 1 fp32 (MFMA f32), 2 bf16 operands (MFMA bf16, fp32 acc)
+size_t mlp_lds_bytes(int prec, const MlpParams& p);
+void launch_mlp(int prec, const MlpParams& p, int n_tiles, hipStream_t s);
+size_t mlp_train_lds_bytes(int prec, const MlpParams& p);
+void launch_mlp_train(int prec, const MlpParams& p, int n_blocks, hipStream_t s);
+// packs B operands for the MFMA layouts; returns element count (host side)
+size_t pack_b_operand_count(int prec, int K, int N);
+void pack_b_operand(int prec, const double* B, int K, int N, int ldb, void* out);
+
+// ---------------------------------------------------------------- MD, reductions, gathers
+void launch_gather_in(int n, const int* perm, const double* src, double* dst, int* flags,
+                      hipStream_t s);
+void launch_scatter_out(int n, const int* perm, const double* src3, double* dst3,
+                        const double* src1, double* dst1, hipStream_t s);
+void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
+                             const BoxInfo* boxes, const int pbc[3], double* dst, hipStream_t s);
+// F = Fself - sum_e pg[rev[e]]; prec of pg: 0 double, 1 float.  If vel != NULL also v += c*F/m.
+void launch_force_gather(int prec, int n, int cap, const int* nnb, const int* rev, const void* pg,
+                         const double* Fself, double* F, double* vel, const double* inv_mass_k,
+                         const int* species, double half_dt, hipStream_t s);
+void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
+                     const double* inv_mass_k, const int* species, double half_dt, double dt,
+                     double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild,
+                     hipStream_t s);
+// deterministic sums: out[0] = sum x ; partials has >= reduce_blocks(n) doubles
+int reduce_blocks(int64_t n);
+void launch_sum(int64_t n, const double* x, double* partials, double* out, hipStream_t s);
+void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
+                    hipStream_t s);
+void launch_segment_sum(int n_seg, const int64_t* seg_off, const double* x, double* out,
+                        hipStream_t s);
+void launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_t s);
+void launch_check_finite(int64_t n, const double* x, int* flags, hipStream_t s);
+
+// training helpers
+void launch_loss_terms(int n, int n_struct, const int* seg, const int* perm, const double* F,
+                       const double* f_ref, const double* e_struct, const double* e_ref,
+                       const int64_t* seg_count, double lambda_f, double* adj, double* eps_atom,
+                       double* floss_atom, double* eloss_struct, hipStream_t s);
+void launch_grad_reduce(int n_blocks, int n_params_pad, const double* part, double* out,
+                        hipStream_t s);
+
+}  // namespace aenet

@@ -1,0 +1,687 @@
+// desc.hip -- Chebyshev descriptor kernels (Sec. II B): forward (Eqs. 3-6),
+// force back-propagation to per-entry displacement gradients, and the
+// Jacobian-vector product used by the training gradient.
+//
+// Mapping: a group of LPA lanes of one wavefront works on one centre atom.
+//   radial terms (Eq. 3): lanes stride over the atom's neighbour entries;
+//   angular terms (Eq. 6): the entries within R_a are compacted into LDS
+//     (unit vector, f_c, species weight, ...); the forward pass and the JVP
+//     stride lanes over the unordered pairs j < k (the ordered-pair sum of
+//     Eq. 6 is twice that), the force pass gives each lane one entry k and
+//     loops over all j != k, so every lane owns the gradient of its entry and
+//     no atomics are needed.
+// Accumulators live in registers (orders are compile-time) and are summed
+// over the group with cross-lane shuffles.  R is the arithmetic type
+// (double, or float with the displacement taken in double).
+#include "aenet_internal.h"
+
+namespace aenet {
+
+namespace {
+
+template <int LPA, typename T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+  for (int o = LPA / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPA);
+  return v;
+}
+
+template <int LPA>
+__device__ inline uint64_t group_ballot(bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (LPA == 64) return m;
+  const int g = (threadIdx.x & 63) / LPA;
+  return (m >> (g * LPA)) & ((1ull << LPA) - 1ull);
+}
+
+template <typename R>
+__device__ inline void sincos_r(R x, R* s, R* c);
+template <>
+__device__ inline void sincos_r<double>(double x, double* s, double* c) { sincos(x, s, c); }
+template <>
+__device__ inline void sincos_r<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+
+template <typename R>
+__device__ inline R sqrt_r(R x);
+template <>
+__device__ inline double sqrt_r<double>(double x) { return sqrt(x); }
+template <>
+__device__ inline float sqrt_r<float>(float x) { return sqrtf(x); }
+
+constexpr double kPi = 3.14159265358979323846;
+
+// displacement d = r_j + s L - r_i of a packed entry (always in double)
+__device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double xi0, double xi1,
+                                 double xi2, uint32_t en, double& d0, double& d1, double& d2) {
+  const int q = (int)(en & kAtomMask);
+  const int code = (int)(en >> kImgBits);
+  const double s0 = (double)(code % 3 - 1), s1 = (double)((code / 3) % 3 - 1), s2 = (double)(code / 9 - 1);
+  d0 = p.pos[3 * (size_t)q] + s0 * b.L[0] - xi0;
+  d1 = p.pos[3 * (size_t)q + 1] + s1 * b.L[1] - xi1;
+  d2 = p.pos[3 * (size_t)q + 2] + s2 * b.L[2] - xi2;
+  return q;
+}
+
+// ------------------------------------------------------------------ forward
+template <typename R, int NR, int NA, int LPA>
+__global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int apb = blockDim.x / LPA;
+  const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
+  const int i = blockIdx.x * apb + g;
+  const bool active = i < p.n;
+  R* ux = reinterpret_cast<R*>(smem) + (size_t)g * p.cap_ang * 5;
+  R* uy = ux + p.cap_ang;
+  R* uz = uy + p.cap_ang;
+  R* fs = uz + p.cap_ang;
+  R* ws = fs + p.cap_ang;
+
+  R rt[NR + 1], rw[NR + 1], at[NA + 1], aw[NA + 1];
+#pragma unroll
+  for (int a = 0; a <= NR; ++a) rt[a] = rw[a] = R(0);
+#pragma unroll
+  for (int a = 0; a <= NA; ++a) at[a] = aw[a] = R(0);
+
+  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
+  const double xi0 = active ? p.pos[3 * (size_t)i] : 0.0;
+  const double xi1 = active ? p.pos[3 * (size_t)i + 1] : 0.0;
+  const double xi2 = active ? p.pos[3 * (size_t)i + 2] : 0.0;
+  const uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
+  const int nn = active ? p.nnb[i] : 0;
+  const int na = active ? p.nang[i] : 0;
+  const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
+  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+
+  // radial terms, Eq. 3
+  for (int e = l; e < nn; e += LPA) {
+    double d0, d1, d2;
+    const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 < rr2) {
+      const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
+      const R x = r * inv_rr2 - R(1);
+      R sn, cs;
+      sincos_r<R>(r * pi_rr, &sn, &cs);
+      const R fc = R(0.5) * (cs + R(1));
+      const R wf = R(p.tw[p.species[q]]) * fc;
+      R t0 = R(1), t1 = x;
+      rt[0] += fc;
+      rw[0] += wf;
+#pragma unroll
+      for (int a = 1; a <= NR; ++a) {
+        rt[a] += t1 * fc;
+        rw[a] += t1 * wf;
+        const R t2 = R(2) * x * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+      }
+    }
+  }
+
+  // compact the angular entries into LDS
+  int nv = 0;
+  for (int base = 0; base < na; base += LPA) {
+    const int e = base + l;
+    bool valid = false;
+    R vx = 0, vy = 0, vz = 0, vf = 0, vw = 0;
+    if (e < na) {
+      double d0, d1, d2;
+      const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      if (r2 < ra2) {
+        valid = true;
+        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
+        const R ir = R(1) / r;
+        vx = R(d0) * ir;
+        vy = R(d1) * ir;
+        vz = R(d2) * ir;
+        R sn, cs;
+        sincos_r<R>(r * pi_ra, &sn, &cs);
+        vf = R(0.5) * (cs + R(1));
+        vw = R(p.tw[p.species[q]]);
+      }
+    }
+    const uint64_t m = group_ballot<LPA>(valid);
+    if (valid) {
+      const int at_ = nv + __popcll(m & ((1ull << l) - 1ull));
+      ux[at_] = vx;
+      uy[at_] = vy;
+      uz[at_] = vz;
+      fs[at_] = vf;
+      ws[at_] = vw;
+    }
+    nv += __popcll(m);
+  }
+  __syncthreads();
+
+  // angular terms, Eq. 6: unordered pairs j < k, lanes strided over the pair index
+  if (nv >= 2) {
+    int j = 0, rem = l;
+    while (j < nv - 1 && rem >= nv - 1 - j) {
+      rem -= nv - 1 - j;
+      ++j;
+    }
+    int k = j + 1 + rem;
+    while (j < nv - 1) {
+      const R c = ux[j] * ux[k] + uy[j] * uy[k] + uz[j] * uz[k];
+      const R ff = fs[j] * fs[k];
+      const R wf = ws[j] * ws[k] * ff;
+      R t0 = R(1), t1 = c;
+      at[0] += ff;
+      aw[0] += wf;
+#pragma unroll
+      for (int a = 1; a <= NA; ++a) {
+        at[a] += t1 * ff;
+        aw[a] += t1 * wf;
+        const R t2 = R(2) * c * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+      }
+      k += LPA;
+      while (j < nv - 1 && k >= nv) {
+        k = k - nv + j + 2;
+        ++j;
+      }
+    }
+  }
+
+#pragma unroll
+  for (int a = 0; a <= NR; ++a) {
+    rt[a] = group_sum<LPA>(rt[a]);
+    rw[a] = group_sum<LPA>(rw[a]);
+  }
+#pragma unroll
+  for (int a = 0; a <= NA; ++a) {
+    at[a] = group_sum<LPA>(at[a]) * R(2);
+    aw[a] = group_sum<LPA>(aw[a]) * R(2);
+  }
+  if (active) {
+    R* G = reinterpret_cast<R*>(p.G) + (size_t)i * p.ldG;
+    constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+#pragma unroll
+    for (int a = 0; a <= NR; ++a) {
+      if (a % LPA == l) G[a] = rt[a];
+      if (p.weighted && (T2 + a) % LPA == l) G[T2 + a] = rw[a];
+    }
+#pragma unroll
+    for (int a = 0; a <= NA; ++a) {
+      if ((T1 + a) % LPA == l) G[T1 + a] = at[a];
+      if (p.weighted && (T2 + T1 + a) % LPA == l) G[T2 + T1 + a] = aw[a];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ backward
+// pg[i, e] = dE_i / d d_e for every entry of atom i; Fself[i] = sum_e pg[i, e]
+template <typename R, int NR, int NA, int LPA>
+__global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int apb = blockDim.x / LPA;
+  const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
+  const int i = blockIdx.x * apb + g;
+  const bool active = i < p.n;
+  const int ca = p.cap_ang;
+  R* ux = reinterpret_cast<R*>(smem) + (size_t)g * ca * 10;
+  R* uy = ux + ca;
+  R* uz = uy + ca;
+  R* fs = uz + ca;
+  R* fp = fs + ca;
+  R* ws = fp + ca;
+  R* ri = ws + ca;
+  R* gx = ri + ca;
+  R* gy = gx + ca;
+  R* gz = gy + ca;
+  int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)apb * ca * 10) + (size_t)g * ca;
+
+  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
+  const double xi0 = active ? p.pos[3 * (size_t)i] : 0.0;
+  const double xi1 = active ? p.pos[3 * (size_t)i + 1] : 0.0;
+  const double xi2 = active ? p.pos[3 * (size_t)i + 2] : 0.0;
+  const uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
+  const int nn = active ? p.nnb[i] : 0;
+  const int na = active ? p.nang[i] : 0;
+  const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
+  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+  const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)(active ? i : 0) * p.ldG;
+  constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+
+  // compact the angular entries
+  int nv = 0;
+  for (int base = 0; base < na; base += LPA) {
+    const int e = base + l;
+    bool valid = false;
+    R vx = 0, vy = 0, vz = 0, vf = 0, vfp = 0, vw = 0, vri = 0;
+    if (e < na) {
+      double d0, d1, d2;
+      const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      if (r2 < ra2) {
+        valid = true;
+        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
+        vri = R(1) / r;
+        vx = R(d0) * vri;
+        vy = R(d1) * vri;
+        vz = R(d2) * vri;
+        R sn, cs;
+        sincos_r<R>(r * pi_ra, &sn, &cs);
+        vf = R(0.5) * (cs + R(1));
+        vfp = R(-0.5) * pi_ra * sn;
+        vw = R(p.tw[p.species[q]]);
+      }
+    }
+    const uint64_t m = group_ballot<LPA>(valid);
+    const int at_ = nv + __popcll(m & ((1ull << l) - 1ull));
+    if (valid) {
+      ux[at_] = vx;
+      uy[at_] = vy;
+      uz[at_] = vz;
+      fs[at_] = vf;
+      fp[at_] = vfp;
+      ws[at_] = vw;
+      ri[at_] = vri;
+    }
+    if (e < na) kidx[e] = valid ? at_ : -1;
+    nv += __popcll(m);
+  }
+  __syncthreads();
+
+  // angular: lane owns entry k, sums d/dd_k over all j != k (ordered pairs)
+  {
+    R ga[NA + 1], gw[NA + 1], da[NA + 1], dw[NA + 1];
+#pragma unroll
+    for (int a = 0; a <= NA; ++a) {
+      ga[a] = active ? gG[T1 + a] : R(0);
+      gw[a] = (active && p.weighted) ? gG[T2 + T1 + a] : R(0);
+      da[a] = R(a) * ga[a];
+      dw[a] = R(a) * gw[a];
+    }
+    for (int k = l; k < nv; k += LPA) {
+      const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
+      R ax = 0, ay = 0, az = 0;
+      for (int j = 0; j < nv; ++j) {
+        if (j == k) continue;
+        const R jx = ux[j], jy = uy[j], jz = uz[j];
+        const R c = jx * kx + jy * ky + jz * kz;
+        // sum_a coef_a T_a(c) and sum_a coef_a T_a'(c), T_a' = a U_{a-1}
+        R t0 = R(1), t1 = c, u0 = R(1), u1 = R(2) * c;
+        R At = ga[0], Aw = gw[0], Bt = R(0), Bw = R(0);
+#pragma unroll
+        for (int a = 1; a <= NA; ++a) {
+          At += ga[a] * t1;
+          Aw += gw[a] * t1;
+          Bt += da[a] * u0;
+          Bw += dw[a] * u0;
+          const R t2 = R(2) * c * t1 - t0;
+          t0 = t1;
+          t1 = t2;
+          const R u2 = R(2) * c * u1 - u0;
+          u0 = u1;
+          u1 = u2;
+        }
+        const R ww = ws[j] * wk;
+        const R A = At + ww * Aw, B = Bt + ww * Bw;
+        const R fj = fs[j];
+        const R cb = B * fj * fk * rik, ca_ = A * fj * fpk;
+        ax += cb * (jx - c * kx) + ca_ * kx;
+        ay += cb * (jy - c * ky) + ca_ * ky;
+        az += cb * (jz - c * kz) + ca_ * kz;
+      }
+      gx[k] = R(2) * ax;
+      gy[k] = R(2) * ay;
+      gz[k] = R(2) * az;
+    }
+  }
+  __syncthreads();
+
+  // radial terms, plus the angular part of each entry, written per entry
+  R grt[NR + 1], grw[NR + 1], drt[NR + 1], drw[NR + 1];
+#pragma unroll
+  for (int a = 0; a <= NR; ++a) {
+    grt[a] = active ? gG[a] : R(0);
+    grw[a] = (active && p.weighted) ? gG[T2 + a] : R(0);
+    drt[a] = R(a) * grt[a];
+    drw[a] = R(a) * grw[a];
+  }
+  R* pg = reinterpret_cast<R*>(p.pg) + (size_t)(active ? i : 0) * p.cap * 3;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int e = l; e < nn; e += LPA) {
+    double d0, d1, d2;
+    const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    R px = 0, py = 0, pz = 0;
+    if (r2 < rr2) {
+      const R dx = R(d0), dy = R(d1), dz = R(d2);
+      const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
+      const R x = r * inv_rr2 - R(1);
+      R sn, cs;
+      sincos_r<R>(r * pi_rr, &sn, &cs);
+      const R fc = R(0.5) * (cs + R(1));
+      const R fcp = R(-0.5) * pi_rr * sn;
+      R t0 = R(1), t1 = x, u0 = R(1), u1 = R(2) * x;
+      R St = grt[0], Sw = grw[0], Dt = R(0), Dw = R(0);
+#pragma unroll
+      for (int a = 1; a <= NR; ++a) {
+        St += grt[a] * t1;
+        Sw += grw[a] * t1;
+        Dt += drt[a] * u0;
+        Dw += drw[a] * u0;
+        const R t2 = R(2) * x * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+        const R u2 = R(2) * x * u1 - u0;
+        u0 = u1;
+        u1 = u2;
+      }
+      const R w = R(p.tw[p.species[q]]);
+      const R dEdr = (Dt + w * Dw) * inv_rr2 * fc + (St + w * Sw) * fcp;
+      const R s = dEdr / r;
+      px = s * dx;
+      py = s * dy;
+      pz = s * dz;
+    }
+    if (e < na) {
+      const int k = kidx[e];
+      if (k >= 0) {
+        px += gx[k];
+        py += gy[k];
+        pz += gz[k];
+      }
+    }
+    pg[3 * (size_t)e] = px;
+    pg[3 * (size_t)e + 1] = py;
+    pg[3 * (size_t)e + 2] = pz;
+    sx += (double)px;
+    sy += (double)py;
+    sz += (double)pz;
+  }
+  sx = group_sum<LPA>(sx);
+  sy = group_sum<LPA>(sy);
+  sz = group_sum<LPA>(sz);
+  if (active && l == 0) {
+    p.Fself[3 * (size_t)i] = sx;
+    p.Fself[3 * (size_t)i + 1] = sy;
+    p.Fself[3 * (size_t)i + 2] = sz;
+  }
+}
+
+// ------------------------------------------------------------------ JVP
+// U_i = sum_e dG_i/dd_e . (adj_j(e) - adj_i)
+template <typename R, int NR, int NA, int LPA>
+__global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int apb = blockDim.x / LPA;
+  const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
+  const int i = blockIdx.x * apb + g;
+  const bool active = i < p.n;
+  const int ca = p.cap_ang;
+  R* ux = reinterpret_cast<R*>(smem) + (size_t)g * ca * 11;
+  R* uy = ux + ca;
+  R* uz = uy + ca;
+  R* fs = uz + ca;   // f_c
+  R* fd = fs + ca;   // f_c' (u . dd)   (time derivative of f_c)
+  R* ws = fd + ca;
+  R* ri = ws + ca;
+  R* vx_ = ri + ca;  // dd
+  R* vy_ = vx_ + ca;
+  R* vz_ = vy_ + ca;
+  R* pa = vz_ + ca;  // u . dd
+
+  R rt[NR + 1], rw[NR + 1], at[NA + 1], aw[NA + 1];
+#pragma unroll
+  for (int a = 0; a <= NR; ++a) rt[a] = rw[a] = R(0);
+#pragma unroll
+  for (int a = 0; a <= NA; ++a) at[a] = aw[a] = R(0);
+
+  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
+  const double xi0 = active ? p.pos[3 * (size_t)i] : 0.0;
+  const double xi1 = active ? p.pos[3 * (size_t)i + 1] : 0.0;
+  const double xi2 = active ? p.pos[3 * (size_t)i + 2] : 0.0;
+  const double ai0 = active ? p.adj[3 * (size_t)i] : 0.0;
+  const double ai1 = active ? p.adj[3 * (size_t)i + 1] : 0.0;
+  const double ai2 = active ? p.adj[3 * (size_t)i + 2] : 0.0;
+  const uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
+  const int nn = active ? p.nnb[i] : 0;
+  const int na = active ? p.nang[i] : 0;
+  const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
+  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+
+  for (int e = l; e < nn; e += LPA) {
+    double d0, d1, d2;
+    const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 < rr2) {
+      const R dx = R(d0), dy = R(d1), dz = R(d2);
+      const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
+      const R proj = (dx * R(p.adj[3 * (size_t)q] - ai0) + dy * R(p.adj[3 * (size_t)q + 1] - ai1) +
+                      dz * R(p.adj[3 * (size_t)q + 2] - ai2)) / r;
+      const R x = r * inv_rr2 - R(1);
+      R sn, cs;
+      sincos_r<R>(r * pi_rr, &sn, &cs);
+      const R fc = R(0.5) * (cs + R(1));
+      const R fcp = R(-0.5) * pi_rr * sn;
+      const R w = R(p.tw[p.species[q]]);
+      R t0 = R(1), t1 = x, u0 = R(1), u1 = R(2) * x;
+      rt[0] += fcp * proj;
+      rw[0] += w * fcp * proj;
+#pragma unroll
+      for (int a = 1; a <= NR; ++a) {
+        const R dphi = (R(a) * u0 * inv_rr2 * fc + t1 * fcp) * proj;
+        rt[a] += dphi;
+        rw[a] += w * dphi;
+        const R t2 = R(2) * x * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+        const R u2 = R(2) * x * u1 - u0;
+        u0 = u1;
+        u1 = u2;
+      }
+    }
+  }
+
+  int nv = 0;
+  for (int base = 0; base < na; base += LPA) {
+    const int e = base + l;
+    bool valid = false;
+    R vx = 0, vy = 0, vz = 0, vf = 0, vfd = 0, vw = 0, vri = 0, dx_ = 0, dy_ = 0, dz_ = 0, vpa = 0;
+    if (e < na) {
+      double d0, d1, d2;
+      const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      if (r2 < ra2) {
+        valid = true;
+        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
+        vri = R(1) / r;
+        vx = R(d0) * vri;
+        vy = R(d1) * vri;
+        vz = R(d2) * vri;
+        dx_ = R(p.adj[3 * (size_t)q] - ai0);
+        dy_ = R(p.adj[3 * (size_t)q + 1] - ai1);
+        dz_ = R(p.adj[3 * (size_t)q + 2] - ai2);
+        vpa = vx * dx_ + vy * dy_ + vz * dz_;
+        R sn, cs;
+        sincos_r<R>(r * pi_ra, &sn, &cs);
+        vf = R(0.5) * (cs + R(1));
+        vfd = R(-0.5) * pi_ra * sn * vpa;
+        vw = R(p.tw[p.species[q]]);
+      }
+    }
+    const uint64_t m = group_ballot<LPA>(valid);
+    if (valid) {
+      const int at_ = nv + __popcll(m & ((1ull << l) - 1ull));
+      ux[at_] = vx;
+      uy[at_] = vy;
+      uz[at_] = vz;
+      fs[at_] = vf;
+      fd[at_] = vfd;
+      ws[at_] = vw;
+      ri[at_] = vri;
+      vx_[at_] = dx_;
+      vy_[at_] = dy_;
+      vz_[at_] = dz_;
+      pa[at_] = vpa;
+    }
+    nv += __popcll(m);
+  }
+  __syncthreads();
+
+  if (nv >= 2) {
+    int j = 0, rem = l;
+    while (j < nv - 1 && rem >= nv - 1 - j) {
+      rem -= nv - 1 - j;
+      ++j;
+    }
+    int k = j + 1 + rem;
+    while (j < nv - 1) {
+      const R c = ux[j] * ux[k] + uy[j] * uy[k] + uz[j] * uz[k];
+      // dc = (u_k . dd_j - c u_j . dd_j)/r_j + (u_j . dd_k - c u_k . dd_k)/r_k
+      const R dc = (ux[k] * vx_[j] + uy[k] * vy_[j] + uz[k] * vz_[j] - c * pa[j]) * ri[j] +
+                   (ux[j] * vx_[k] + uy[j] * vy_[k] + uz[j] * vz_[k] - c * pa[k]) * ri[k];
+      const R ff = fs[j] * fs[k];
+      const R dff = fd[j] * fs[k] + fs[j] * fd[k];
+      const R ww = ws[j] * ws[k];
+      R t0 = R(1), t1 = c, u0 = R(1), u1 = R(2) * c;
+      at[0] += dff;
+      aw[0] += ww * dff;
+#pragma unroll
+      for (int a = 1; a <= NA; ++a) {
+        const R v = R(a) * u0 * dc * ff + t1 * dff;
+        at[a] += v;
+        aw[a] += ww * v;
+        const R t2 = R(2) * c * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+        const R u2 = R(2) * c * u1 - u0;
+        u0 = u1;
+        u1 = u2;
+      }
+      k += LPA;
+      while (j < nv - 1 && k >= nv) {
+        k = k - nv + j + 2;
+        ++j;
+      }
+    }
+  }
+
+#pragma unroll
+  for (int a = 0; a <= NR; ++a) {
+    rt[a] = group_sum<LPA>(rt[a]);
+    rw[a] = group_sum<LPA>(rw[a]);
+  }
+#pragma unroll
+  for (int a = 0; a <= NA; ++a) {
+    at[a] = group_sum<LPA>(at[a]) * R(2);
+    aw[a] = group_sum<LPA>(aw[a]) * R(2);
+  }
+  if (active) {
+    R* U = reinterpret_cast<R*>(p.U) + (size_t)i * p.ldG;
+    constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+#pragma unroll
+    for (int a = 0; a <= NR; ++a) {
+      if (a % LPA == l) U[a] = rt[a];
+      if (p.weighted && (T2 + a) % LPA == l) U[T2 + a] = rw[a];
+    }
+#pragma unroll
+    for (int a = 0; a <= NA; ++a) {
+      if ((T1 + a) % LPA == l) U[T1 + a] = at[a];
+      if (p.weighted && (T2 + T1 + a) % LPA == l) U[T2 + T1 + a] = aw[a];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+enum Kind { FWD = 0, BWD = 1, JVP = 2 };
+
+// LDS words (of type R) per angular entry, plus int words
+constexpr int lds_words(int kind) { return kind == FWD ? 5 : (kind == BWD ? 10 : 11); }
+
+template <typename R, int NR, int NA, int LPA>
+void launch_kind(int kind, const DescParams& p, hipStream_t s) {
+  // atoms per block: as many as keep LDS <= 64 KiB and the block <= 256 lanes
+  const size_t per_atom = (size_t)p.cap_ang * (lds_words(kind) * sizeof(R) + (kind == BWD ? sizeof(int) : 0));
+  int apb = 256 / LPA;
+  while (apb > 1 && (size_t)apb * per_atom > 65536) apb >>= 1;
+  const size_t lds = (size_t)apb * per_atom;
+  const int blocks = (p.n + apb - 1) / apb;
+  const dim3 grid(blocks), block(apb * LPA);
+  if (kind == FWD)
+    hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA>), grid, block, lds, s, p);
+  else if (kind == BWD)
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, LPA>), grid, block, lds, s, p);
+  else
+    hipLaunchKernelGGL((k_desc_jvp<R, NR, NA, LPA>), grid, block, lds, s, p);
+}
+
+template <typename R, int NR, int NA>
+void launch_orders(int kind, const DescParams& p, hipStream_t s) {
+  // wide groups for crowded angular shells, narrow ones otherwise
+  if (p.cap_ang > 64) {
+    launch_kind<R, NR, NA, 64>(kind, p, s);
+  } else if (kind == BWD) {
+    launch_kind<R, NR, NA, 32>(kind, p, s);
+  } else {
+    launch_kind<R, NR, NA, 16>(kind, p, s);
+  }
+}
+
+#define AENET_ORDERS(X) \
+  X(10, 4)              \
+  X(16, 8)              \
+  X(18, 6)              \
+  X(6, 2)               \
+  X(5, 3)               \
+  X(4, 2)
+
+template <typename R>
+bool dispatch(int kind, int nr, int na, const DescParams& p, hipStream_t s) {
+#define AENET_CASE(A, B)                       \
+  if (nr == A && na == B) {                    \
+    launch_orders<R, A, B>(kind, p, s);        \
+    return true;                               \
+  }
+  AENET_ORDERS(AENET_CASE)
+#undef AENET_CASE
+  return false;
+}
+
+void launch_any(int kind, int prec, int nr, int na, const DescParams& p, hipStream_t s) {
+  if (p.n <= 0) return;
+  if (prec == 0)
+    dispatch<double>(kind, nr, na, p, s);
+  else
+    dispatch<float>(kind, nr, na, p, s);
+}
+
+}  // namespace
+
+bool desc_supported(int nr, int na) {
+#define AENET_CHECK(A, B) \
+  if (nr == A && na == B) return true;
+  AENET_ORDERS(AENET_CHECK)
+#undef AENET_CHECK
+  return false;
+}
+
+int desc_supported_list(int* orders, int max_pairs) {
+  int k = 0;
+#define AENET_LIST(A, B)          \
+  if (k < max_pairs && orders) {  \
+    orders[2 * k] = A;            \
+    orders[2 * k + 1] = B;        \
+  }                               \
+  ++k;
+  AENET_ORDERS(AENET_LIST)
+#undef AENET_LIST
+  return k;
+}
+
+void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s) {
+  launch_any(FWD, prec, nr, na, p, s);
+}
+void launch_desc_bwd(int prec, int nr, int na, const DescParams& p, hipStream_t s) {
+  launch_any(BWD, prec, nr, na, p, s);
+}
+void launch_desc_jvp(int prec, int nr, int na, const DescParams& p, hipStream_t s) {
+  launch_any(JVP, prec, nr, na, p, s);
+}
+
+}  // namespace aenet

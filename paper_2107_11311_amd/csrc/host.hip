@@ -1,0 +1,1086 @@
+// host.hip -- host runtime of the GPU library and the C ABI of
+// include/aenet_gpu.h: model validation and packing, device memory, the
+// caller-order <-> species-sorted internal order, neighbour-list capacity
+// management and retries, and the call sequences of energy/forces, MD and
+// the training-loss gradient.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/aenet_gpu.h"
+#include "aenet_internal.h"
+
+using namespace aenet;
+
+namespace {
+
+constexpr double kKappa = 9648.533215665;  // (eV/amu) in A^2/ps^2
+
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+int pad_to(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct aenet_ctx {
+  // model
+  int S = 0, nr = 0, na = 0, D = 0, ldG = 0, prec = 0, device = 0;
+  double rr = 0, ra = 0, skin = 0, rlist = 0;
+  double tw[kMaxSpecies] = {0}, mass[kMaxSpecies] = {0};
+  bool have_mass = false;
+  int L = 0;
+  int w[kMaxLayers + 1] = {0}, wp[kMaxLayers + 1] = {0}, act[kMaxLayers] = {0};
+  int64_t nps = 0;                         // parameters per species (API layout)
+  std::vector<double> params;              // [S * nps]
+  std::vector<double> shift, scale;        // [S * D]
+  double e_off[kMaxSpecies] = {0};
+  int npad_species = 0;                    // padded parameters per species (training layout)
+  hipStream_t stream = nullptr;
+  std::string err;
+  int rebuild_every = 50;
+  aenet_stats stats{};
+
+  DevMem netbuf;        // packed network operands
+  MlpParams mlp{};      // pointers into netbuf (species part); geometry filled per call
+  DevMem d_pidx;        // API parameter index -> padded index
+
+  // geometry
+  int64_t n = 0;
+  int n_struct = 0;
+  std::vector<int32_t> species_cache;
+  std::vector<int64_t> offsets_cache;
+  std::vector<int> perm;
+  int sp_off[kMaxSpecies + 1] = {0};
+  std::vector<BoxInfo> boxes;
+  int pbc[3] = {1, 1, 1};
+  int n_cells = 0;
+  int cap = 0, cap_ang = 0;
+  bool nbr_valid = false;
+
+  DevMem d_perm, d_species, d_seg, d_segoff, d_segcount, d_boxes;
+  DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
+      d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
+  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_nnb, d_nang, d_rev;
+  DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
+  DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
+
+  // kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_class;  // class of event pair k (events 2k, 2k+1)
+  double prof_ms[AENET_K_COUNT] = {0};
+  int64_t prof_n[AENET_K_COUNT] = {0};
+};
+
+namespace {
+
+aenet_status fail(aenet_ctx* c, aenet_status code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_TRY(c, expr)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(c, AENET_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define TRY(expr)                       \
+  do {                                  \
+    aenet_status st_ = (expr);          \
+    if (st_ != AENET_OK) return st_;    \
+  } while (0)
+
+aenet_status ensure(aenet_ctx* c, DevMem& m, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (m.bytes >= bytes) return AENET_OK;
+  if (m.p) {
+    (void)hipFree(m.p);
+    m.p = nullptr;
+    m.bytes = 0;
+  }
+  size_t b = (bytes + bytes / 8 + 255) / 256 * 256;
+  if (hipMalloc(&m.p, b) != hipSuccess) {
+    (void)hipGetLastError();
+    m.p = nullptr;
+    return fail(c, AENET_E_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+  }
+  m.bytes = b;
+  return AENET_OK;
+}
+
+size_t real_size(const aenet_ctx* c) { return c->prec == 0 ? sizeof(double) : sizeof(float); }
+int desc_prec(const aenet_ctx* c) { return c->prec == 0 ? 0 : 1; }
+
+// ------------------------------------------------------------------ network packing
+aenet_status pack_networks(aenet_ctx* c) {
+  const int S = c->S, L = c->L;
+  const int prec = c->prec;
+  const size_t el = real_size(c);
+  const size_t bel = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
+  // byte layout: per species, per hidden layer: wf, wb, bias; then wlast, shift, scale
+  std::vector<size_t> off;
+  size_t total = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = total;
+    total += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  struct SpOff {
+    size_t wf[kMaxLayers], wb[kMaxLayers], bias[kMaxLayers], wlast, shift, scale;
+  };
+  std::vector<SpOff> so(S);
+  for (int s = 0; s < S; ++s) {
+    for (int l = 1; l < L; ++l) {
+      so[s].wf[l] = take(pack_b_operand_count(prec, c->wp[l - 1], c->wp[l]) * bel);
+      so[s].wb[l] = take(pack_b_operand_count(prec, c->wp[l], c->wp[l - 1]) * bel);
+      so[s].bias[l] = take((size_t)c->wp[l] * el);
+    }
+    so[s].wlast = take((size_t)c->wp[L - 1] * el);
+    so[s].shift = take((size_t)c->ldG * el);
+    so[s].scale = take((size_t)c->ldG * el);
+  }
+  std::vector<unsigned char> host(total, 0);
+  auto put = [&](size_t o, int idx, double v) {
+    if (el == 8)
+      reinterpret_cast<double*>(host.data() + o)[idx] = v;
+    else
+      reinterpret_cast<float*>(host.data() + o)[idx] = (float)v;
+  };
+  for (int s = 0; s < S; ++s) {
+    const double* P = c->params.data() + (size_t)s * c->nps;
+    size_t po = 0;
+    for (int l = 1; l <= L; ++l) {
+      const int in = c->w[l - 1], out = c->w[l];
+      const double* W = P + po;
+      const double* b = W + (size_t)out * in;
+      po += (size_t)out * in + out;
+      if (l < L) {
+        const int Kp = c->wp[l - 1], Np = c->wp[l];
+        std::vector<double> Bf((size_t)Kp * Np, 0.0), Bb((size_t)Np * Kp, 0.0);
+        for (int q = 0; q < out; ++q)
+          for (int k = 0; k < in; ++k) {
+            Bf[(size_t)k * Np + q] = W[(size_t)q * in + k];  // forward: B[k][n] = W[n][k]
+            Bb[(size_t)q * Kp + k] = W[(size_t)q * in + k];  // backward: B[k][n] = W[k][n]
+          }
+        pack_b_operand(prec, Bf.data(), Kp, Np, Np, host.data() + so[s].wf[l]);
+        pack_b_operand(prec, Bb.data(), Np, Kp, Kp, host.data() + so[s].wb[l]);
+        for (int q = 0; q < out; ++q) put(so[s].bias[l], q, b[q]);
+      } else {
+        for (int k = 0; k < in; ++k) put(so[s].wlast, k, W[k]);
+        c->mlp.net[s].blast = b[0];
+      }
+    }
+    for (int k = 0; k < c->D; ++k) {
+      put(so[s].shift, k, c->shift[(size_t)s * c->D + k]);
+      put(so[s].scale, k, c->scale[(size_t)s * c->D + k]);
+    }
+    c->mlp.net[s].e_offset = c->e_off[s];
+  }
+  TRY(ensure(c, c->netbuf, total));
+  HIP_TRY(c, hipMemcpy(c->netbuf.p, host.data(), total, hipMemcpyHostToDevice));
+  unsigned char* base = c->netbuf.as<unsigned char>();
+  for (int s = 0; s < S; ++s) {
+    MlpNet& nt = c->mlp.net[s];
+    for (int l = 1; l < L; ++l) {
+      nt.wf[l] = base + so[s].wf[l];
+      nt.wb[l] = base + so[s].wb[l];
+      nt.bias[l] = base + so[s].bias[l];
+    }
+    nt.wlast = base + so[s].wlast;
+    nt.shift = base + so[s].shift;
+    nt.scale = base + so[s].scale;
+  }
+  return AENET_OK;
+}
+
+// ------------------------------------------------------------------ geometry
+aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const int32_t* species,
+                     const double* boxes, const uint8_t* pbc) {
+  if (n_struct < 1 || !offsets || offsets[0] != 0) return fail(c, AENET_E_INVALID, "bad structure offsets");
+  for (int s = 0; s < n_struct; ++s)
+    if (offsets[s + 1] < offsets[s]) return fail(c, AENET_E_INVALID, "structure offsets must not decrease");
+  const int64_t n = offsets[n_struct];
+  if (n > kMaxAtoms || n > (int64_t)INT32_MAX / 4) return fail(c, AENET_E_INVALID, "too many atoms");
+  if (n > 0 && !species) return fail(c, AENET_E_INVALID, "species is NULL");
+  for (int64_t i = 0; i < n; ++i)
+    if (species[i] < 0 || species[i] >= c->S)
+      return fail(c, AENET_E_SPECIES, "species id " + std::to_string(species[i]) + " of atom " +
+                                          std::to_string(i) + " outside 0.." + std::to_string(c->S - 1));
+  int pb[3];
+  for (int a = 0; a < 3; ++a) pb[a] = pbc ? (pbc[a] ? 1 : 0) : 1;
+  // cell grids
+  std::vector<BoxInfo> bx(n_struct);
+  int64_t cells = 0;
+  for (int s = 0; s < n_struct; ++s) {
+    BoxInfo& b = bx[s];
+    for (int a = 0; a < 3; ++a) {
+      const double L = boxes[3 * s + a];
+      if (!(L > 0.0) || !std::isfinite(L)) return fail(c, AENET_E_BOX, "box edges must be positive and finite");
+      if (pb[a] && L < c->rlist)
+        return fail(c, AENET_E_BOX, "periodic box edge " + std::to_string(L) +
+                                        " A is shorter than the neighbour-list radius " +
+                                        std::to_string(c->rlist) + " A");
+      int nc = (int)std::min<double>(std::floor(L / c->rlist), 1024.0);
+      while (nc > 1 && L / nc < c->rlist * (1.0 + 1e-12)) --nc;
+      if (nc < 1) nc = 1;
+      b.L[a] = L;
+      b.nc[a] = nc;
+    }
+    b.cell_base = (int)cells;
+    cells += (int64_t)b.nc[0] * b.nc[1] * b.nc[2];
+    if (cells > (1 << 28)) return fail(c, AENET_E_INVALID, "too many neighbour cells");
+  }
+  const bool same = (n == c->n && n_struct == c->n_struct &&
+                     c->offsets_cache.size() == (size_t)n_struct + 1 &&
+                     std::equal(offsets, offsets + n_struct + 1, c->offsets_cache.begin()) &&
+                     c->species_cache.size() == (size_t)n &&
+                     (n == 0 || std::memcmp(species, c->species_cache.data(), n * sizeof(int32_t)) == 0));
+  hipStream_t st = c->stream;
+  if (!same) {
+    c->n = n;
+    c->n_struct = n_struct;
+    c->offsets_cache.assign(offsets, offsets + n_struct + 1);
+    c->species_cache.assign(species, species + n);
+    // stable counting sort by species: internal position p holds caller atom perm[p]
+    std::vector<int> cnt(c->S + 1, 0);
+    for (int64_t i = 0; i < n; ++i) cnt[species[i] + 1]++;
+    for (int s = 0; s < c->S; ++s) cnt[s + 1] += cnt[s];
+    for (int s = 0; s <= c->S; ++s) c->sp_off[s] = cnt[s];
+    c->perm.assign(n, 0);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i) c->perm[fill[species[i]]++] = (int)i;
+    std::vector<int> sp_int(n), seg_int(n), seg_orig(n);
+    for (int s = 0; s < n_struct; ++s)
+      for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) seg_orig[i] = s;
+    for (int64_t p = 0; p < n; ++p) {
+      sp_int[p] = species[c->perm[p]];
+      seg_int[p] = seg_orig[c->perm[p]];
+    }
+    std::vector<int64_t> segcount(n_struct);
+    for (int s = 0; s < n_struct; ++s) segcount[s] = offsets[s + 1] - offsets[s];
+    const size_t nb = (size_t)std::max<int64_t>(n, 1);
+    TRY(ensure(c, c->d_perm, nb * 4));
+    TRY(ensure(c, c->d_species, nb * 4));
+    TRY(ensure(c, c->d_seg, nb * 4));
+    TRY(ensure(c, c->d_segoff, (n_struct + 1) * 8));
+    TRY(ensure(c, c->d_segcount, n_struct * 8));
+    if (n > 0) {
+      HIP_TRY(c, hipMemcpy(c->d_perm.p, c->perm.data(), n * 4, hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(c->d_species.p, sp_int.data(), n * 4, hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(c->d_seg.p, seg_int.data(), n * 4, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(c, hipMemcpy(c->d_segoff.p, offsets, (n_struct + 1) * 8, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_segcount.p, segcount.data(), n_struct * 8, hipMemcpyHostToDevice));
+    c->nbr_valid = false;
+    c->cap = 0;
+  }
+  for (int a = 0; a < 3; ++a) c->pbc[a] = pb[a];
+  c->boxes = bx;
+  c->n_cells = (int)cells;
+  TRY(ensure(c, c->d_boxes, n_struct * sizeof(BoxInfo)));
+  HIP_TRY(c, hipMemcpyAsync(c->d_boxes.p, bx.data(), n_struct * sizeof(BoxInfo), hipMemcpyHostToDevice, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  // per-atom buffers
+  const size_t nb = (size_t)std::max<int64_t>(n, 1);
+  const size_t el = real_size(c);
+  TRY(ensure(c, c->d_pos, nb * 24));
+  TRY(ensure(c, c->d_pos_ref, nb * 24));
+  TRY(ensure(c, c->d_vel, nb * 24));
+  TRY(ensure(c, c->d_F, nb * 24));
+  TRY(ensure(c, c->d_Fself, nb * 24));
+  TRY(ensure(c, c->d_E, nb * 8));
+  TRY(ensure(c, c->d_Eorig, nb * 8));
+  TRY(ensure(c, c->d_tmp, (nb + n_struct) * 8));
+  TRY(ensure(c, c->d_G, nb * c->ldG * el));
+  TRY(ensure(c, c->d_gG, nb * c->ldG * el));
+  TRY(ensure(c, c->d_red, (size_t)(reduce_blocks(n + n_struct) + 1) * 8));
+  TRY(ensure(c, c->d_scal, 8 * 8));
+  TRY(ensure(c, c->d_flags, 16 * 4));
+  TRY(ensure(c, c->d_cell_count, (size_t)std::max(cells, (int64_t)1) * 4));
+  TRY(ensure(c, c->d_cell_fill, (size_t)std::max(cells, (int64_t)1) * 4));
+  TRY(ensure(c, c->d_cell_start, (size_t)(cells + 1) * 4));
+  TRY(ensure(c, c->d_cell_atoms, nb * 4));
+  TRY(ensure(c, c->d_atom_cell, nb * 4));
+  TRY(ensure(c, c->d_nnb, nb * 4));
+  TRY(ensure(c, c->d_nang, nb * 4));
+  // initial row capacities from the density of the densest structure
+  if (c->cap == 0) {
+    double est = 0.0, est_a = 0.0;
+    const double ra = c->ra + c->skin;
+    for (int s = 0; s < n_struct; ++s) {
+      const double V = bx[s].L[0] * bx[s].L[1] * bx[s].L[2];
+      const double rho = (double)(offsets[s + 1] - offsets[s]) / V;
+      est = std::max(est, rho * 4.18879020478639 * c->rlist * c->rlist * c->rlist);
+      est_a = std::max(est_a, rho * 4.18879020478639 * ra * ra * ra);
+    }
+    c->cap = pad_to((int)(est * 1.35) + 24, 16);
+    c->cap_ang = std::min(c->cap, pad_to((int)(est_a * 1.6) + 16, 8));
+  }
+  return AENET_OK;
+}
+
+aenet_status ensure_rows(aenet_ctx* c) {
+  const size_t nb = (size_t)std::max<int64_t>(c->n, 1);
+  TRY(ensure(c, c->d_nbr, nb * c->cap * 4));
+  TRY(ensure(c, c->d_rev, nb * c->cap * 4));
+  TRY(ensure(c, c->d_pg, nb * c->cap * 3 * real_size(c)));
+  return AENET_OK;
+}
+
+NbrParams nbr_params(aenet_ctx* c, const int* cond) {
+  NbrParams p{};
+  p.n = (int)c->n;
+  p.pos = c->d_pos.as<double>();
+  p.pos_ref = c->d_pos_ref.as<double>();
+  p.seg = c->d_seg.as<int>();
+  p.boxes = c->d_boxes.as<BoxInfo>();
+  for (int a = 0; a < 3; ++a) p.pbc[a] = c->pbc[a];
+  p.n_cells = c->n_cells;
+  p.r_list2 = c->rlist * c->rlist;
+  p.r_ang2 = (c->ra + c->skin) * (c->ra + c->skin);
+  p.cap = c->cap;
+  p.cap_ang = c->cap_ang;
+  p.cell_count = c->d_cell_count.as<int>();
+  p.cell_start = c->d_cell_start.as<int>();
+  p.cell_fill = c->d_cell_fill.as<int>();
+  p.cell_atoms = c->d_cell_atoms.as<int>();
+  p.atom_cell = c->d_atom_cell.as<int>();
+  p.nbr = c->d_nbr.as<uint32_t>();
+  p.nnb = c->d_nnb.as<int>();
+  p.nang = c->d_nang.as<int>();
+  p.rev = c->d_rev.as<int>();
+  p.flags = c->d_flags.as<int>();
+  p.maxcnt = c->d_flags.as<int>() + 1;
+  p.cond = cond;
+  return p;
+}
+
+DescParams desc_params(aenet_ctx* c) {
+  DescParams p{};
+  p.n = (int)c->n;
+  p.pos = c->d_pos.as<double>();
+  p.species = c->d_species.as<int>();
+  p.seg = c->d_seg.as<int>();
+  p.boxes = c->d_boxes.as<BoxInfo>();
+  p.nbr = c->d_nbr.as<uint32_t>();
+  p.nnb = c->d_nnb.as<int>();
+  p.nang = c->d_nang.as<int>();
+  p.cap = c->cap;
+  p.cap_ang = c->cap_ang;
+  p.rr = c->rr;
+  p.ra = c->ra;
+  for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];
+  p.weighted = c->S > 1;
+  p.ldG = c->ldG;
+  p.G = c->d_G.p;
+  p.gG = c->d_gG.p;
+  p.pg = c->d_pg.p;
+  p.Fself = c->d_Fself.as<double>();
+  p.adj = c->d_adj.as<double>();
+  p.U = c->d_U.p;
+  p.flags = c->d_flags.as<int>();
+  return p;
+}
+
+MlpParams mlp_params(aenet_ctx* c, bool want_grad) {
+  MlpParams p = c->mlp;
+  p.n_species = c->S;
+  int t = 0;
+  for (int s = 0; s <= c->S; ++s) p.sp_off[s] = c->sp_off[s];
+  for (int s = 0; s < c->S; ++s) {
+    p.tile_off[s] = t;
+    t += (c->sp_off[s + 1] - c->sp_off[s] + 15) / 16;
+  }
+  p.tile_off[c->S] = t;
+  p.G = c->d_G.p;
+  p.gG = want_grad ? c->d_gG.p : nullptr;
+  p.E = c->d_E.as<double>();
+  return p;
+}
+
+int n_tiles(const MlpParams& p) { return p.tile_off[p.n_species]; }
+
+// grow capacities from what the last build saw
+aenet_status grow_caps(aenet_ctx* c, const int* hf) {
+  const int need = hf[1], need_a = hf[2];
+  int cap = std::max(c->cap, pad_to((int)(need * 1.2) + 16, 16));
+  int cap_a = std::max(c->cap_ang, pad_to((int)(need_a * 1.25) + 8, 8));
+  if (cap_a > cap) cap = pad_to(cap_a, 16);
+  if (cap_a > 700) return fail(c, AENET_E_INVALID, "angular neighbour shell too crowded (" + std::to_string(need_a) + " entries)");
+  c->cap = cap;
+  c->cap_ang = cap_a;
+  c->stats.n_capacity_retries++;
+  return ensure_rows(c);
+}
+
+aenet_status read_flags(aenet_ctx* c, hipStream_t s, int* hf) {
+  HIP_TRY(c, hipMemcpyAsync(hf, c->d_flags.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return AENET_OK;
+}
+
+aenet_status flag_status(aenet_ctx* c, int f) {
+  if (f & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
+  if (f & kFlagOverlap) return fail(c, AENET_E_OVERLAP, "two atoms (or an atom and an image) coincide");
+  if (f & kFlagReverse) return fail(c, AENET_E_DEVICE, "internal error: neighbour list not symmetric");
+  return AENET_OK;
+}
+
+// ------------------------------------------------------------------ kernel timing
+void prof_begin(aenet_ctx* c, hipStream_t s, int cls) {
+  if (!c->profiling) return;
+  if (c->ev_used + 2 > c->ev_pool.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        c->profiling = false;
+        return;
+      }
+      c->ev_pool.push_back(e);
+    }
+  }
+  (void)hipEventRecord(c->ev_pool[c->ev_used], s);
+  c->ev_class.push_back(cls);
+}
+
+void prof_end(aenet_ctx* c, hipStream_t s) {
+  // a begin is pending iff one more class than completed pairs was recorded
+  if (!c->profiling || c->ev_class.size() != c->ev_used / 2 + 1) return;
+  (void)hipEventRecord(c->ev_pool[c->ev_used + 1], s);
+  c->ev_used += 2;
+}
+
+void prof_collect(aenet_ctx* c) {
+  const size_t pairs = c->ev_used / 2;
+  for (size_t k = 0; k < pairs; ++k) {
+    float ms = 0.f;
+    if (hipEventSynchronize(c->ev_pool[2 * k + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]) == hipSuccess) {
+      c->prof_ms[c->ev_class[k]] += ms;
+      c->prof_n[c->ev_class[k]] += 1;
+    }
+    (void)hipGetLastError();
+  }
+  c->ev_used = 0;
+  c->ev_class.clear();
+}
+
+// the neighbour build as one timed unit
+void build_neighbors_timed(aenet_ctx* c, const NbrParams& p, hipStream_t s) {
+  prof_begin(c, s, AENET_K_NEIGHBOR);
+  launch_build_neighbors(p, s);
+  prof_end(c, s);
+}
+
+// descriptors -> networks -> forces (internal order).  vel != NULL applies the closing half kick.
+aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, double half_dt) {
+  if (c->n == 0) return AENET_OK;
+  DescParams dp = desc_params(c);
+  prof_begin(c, s, AENET_K_DESC_FWD);
+  launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s);
+  prof_end(c, s);
+  MlpParams mp = mlp_params(c, forces);
+  prof_begin(c, s, AENET_K_NETWORK);
+  launch_mlp(c->prec, mp, n_tiles(mp), s);
+  prof_end(c, s);
+  if (forces) {
+    prof_begin(c, s, AENET_K_DESC_BWD);
+    launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s);
+    prof_end(c, s);
+    prof_begin(c, s, AENET_K_FORCE_GATHER);
+    launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nnb.as<int>(), c->d_rev.as<int>(),
+                        c->d_pg.p, c->d_Fself.as<double>(), c->d_F.as<double>(), vel,
+                        c->d_invmk.as<double>(), c->d_species.as<int>(), half_dt, s);
+    prof_end(c, s);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return AENET_OK;
+}
+
+// forced build with capacity retries (positions already in d_pos)
+aenet_status build_checked(aenet_ctx* c, hipStream_t s) {
+  TRY(ensure_rows(c));
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+    build_neighbors_timed(c, nbr_params(c, nullptr), s);
+    HIP_TRY(c, hipGetLastError());
+    int hf[8];
+    TRY(read_flags(c, s, hf));
+    c->stats.n_rebuilds++;
+    c->stats.max_neighbors = hf[1];
+    c->stats.max_angular = hf[2];
+    TRY(flag_status(c, hf[0]));
+    if (!(hf[0] & kFlagOverflow)) {
+      c->nbr_valid = true;
+      c->stats.row_capacity = c->cap;
+      c->stats.ang_capacity = c->cap_ang;
+      return AENET_OK;
+    }
+    TRY(grow_caps(c, hf));
+  }
+  return fail(c, AENET_E_DEVICE, "neighbour capacity retries exhausted");
+}
+
+hipStream_t pick_stream(aenet_ctx* c, void* s) { return s ? (hipStream_t)s : c->stream; }
+
+__global__ void k_take(int n, const int* idx, const double* src, double* dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[idx[k]];
+}
+
+void launch_take(int n, const int* idx, const double* src, double* dst, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_take, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, src, dst);
+}
+
+thread_local std::string g_setup_error;
+
+aenet_status check_ctx(aenet_ctx* c) {
+  if (!c) return AENET_E_INVALID;
+  c->err.clear();
+  HIP_TRY(c, hipSetDevice(c->device));
+  return AENET_OK;
+}
+
+// energies/forces of a batch whose positions are on the device in caller order
+aenet_status ef_core(aenet_ctx* c, int n_struct, const int64_t* offsets, const double* pos,
+                     const int32_t* species, const double* boxes, const uint8_t* pbc,
+                     double* e_struct, double* e_total, double* e_atom, double* forces,
+                     hipStream_t s) {
+  TRY(prepare(c, n_struct, offsets, species, boxes, pbc));
+  const int n = (int)c->n;
+  if (n == 0) {
+    if (e_total) HIP_TRY(c, hipMemsetAsync(e_total, 0, 8, s));
+    if (e_struct) HIP_TRY(c, hipMemsetAsync(e_struct, 0, 8 * (size_t)n_struct, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return AENET_OK;
+  }
+  HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+  launch_gather_in(n, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
+  TRY(build_checked(c, s));
+  TRY(compute(c, s, forces != nullptr, nullptr, 0.0));
+  launch_scatter_out(n, c->d_perm.as<int>(), c->d_F.as<double>(), forces, c->d_E.as<double>(),
+                     c->d_Eorig.as<double>(), s);
+  if (e_atom) HIP_TRY(c, hipMemcpyAsync(e_atom, c->d_Eorig.p, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  if (e_total) launch_sum(n, c->d_Eorig.as<double>(), c->d_red.as<double>(), e_total, s);
+  if (e_struct)
+    launch_segment_sum(n_struct, c->d_segoff.as<int64_t>(), c->d_Eorig.as<double>(), e_struct, s);
+  HIP_TRY(c, hipGetLastError());
+  int hf[8];
+  TRY(read_flags(c, s, hf));
+  TRY(flag_status(c, hf[0]));
+  return AENET_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
+  if (!out) return AENET_E_INVALID;
+  *out = nullptr;
+  if (!m) return AENET_E_INVALID;
+  aenet_ctx* c = new (std::nothrow) aenet_ctx();
+  if (!c) return AENET_E_OOM;
+  g_setup_error.clear();
+  auto bad = [&](const std::string& msg) {
+    g_setup_error = msg;
+    delete c;
+    return AENET_E_INVALID;
+  };
+  if (m->n_species < 1 || m->n_species > kMaxSpecies) return bad("n_species must be 1..8");
+  if (m->radial_order < 0 || m->angular_order < 0) return bad("orders must be >= 0");
+  if (!desc_supported(m->radial_order, m->angular_order)) return bad("descriptor orders not compiled in");
+  if (!(m->radial_cutoff > 0) || !(m->angular_cutoff > 0)) return bad("cutoffs must be positive");
+  if (!(m->skin >= 0) || !std::isfinite(m->skin)) return bad("skin must be >= 0");
+  if (m->precision < 0 || m->precision > 2) return bad("unknown precision");
+  if (!m->nets) return bad("nets is NULL");
+  c->S = m->n_species;
+  c->nr = m->radial_order;
+  c->na = m->angular_order;
+  c->rr = m->radial_cutoff;
+  c->ra = m->angular_cutoff;
+  c->skin = m->skin;
+  c->rlist = std::max(c->rr, c->ra) + c->skin;
+  c->prec = m->precision;
+  c->device = m->device;
+  const int typed = c->nr + 1 + c->na + 1;
+  c->D = c->S > 1 ? 2 * typed : typed;
+  for (int s = 0; s < c->S; ++s) {
+    if (c->S > 1 && !m->type_weight) return bad("type_weight is NULL");
+    c->tw[s] = c->S > 1 ? m->type_weight[s] : 0.0;  // one species: no weighted half
+    if (m->mass_amu) {
+      if (!(m->mass_amu[s] > 0)) return bad("masses must be positive");
+      c->mass[s] = m->mass_amu[s];
+    }
+  }
+  c->have_mass = m->mass_amu != nullptr;
+  const aenet_net& n0 = m->nets[0];
+  if (n0.n_layers < 1 || n0.n_layers > kMaxLayers) return bad("n_layers must be 1..4");
+  c->L = n0.n_layers;
+  for (int l = 0; l <= c->L; ++l) {
+    c->w[l] = n0.widths[l];
+    if (c->w[l] < 1 || c->w[l] > kMaxWidth) return bad("widths must be 1..64");
+    c->wp[l] = pad_to(c->w[l], kPad);
+  }
+  if (c->w[0] != c->D) return bad("widths[0] must equal the descriptor dimension " + std::to_string(c->D));
+  if (c->w[c->L] != 1) return bad("the last width must be 1");
+  for (int l = 0; l < c->L; ++l) {
+    c->act[l] = n0.act[l];
+    if (c->act[l] != AENET_ACT_LINEAR && c->act[l] != AENET_ACT_TANH) return bad("unknown activation");
+  }
+  if (c->act[c->L - 1] != AENET_ACT_LINEAR) return bad("the output layer must be linear");
+  c->ldG = c->wp[0];
+  c->nps = 0;
+  for (int l = 1; l <= c->L; ++l) c->nps += (int64_t)c->w[l] * (c->w[l - 1] + 1);
+  c->params.assign((size_t)c->S * c->nps, 0.0);
+  c->shift.assign((size_t)c->S * c->D, 0.0);
+  c->scale.assign((size_t)c->S * c->D, 1.0);
+  for (int s = 0; s < c->S; ++s) {
+    const aenet_net& nt = m->nets[s];
+    if (nt.n_layers != c->L) return bad("all species need the same network shape");
+    for (int l = 0; l <= c->L; ++l)
+      if (nt.widths[l] != c->w[l]) return bad("all species need the same network shape");
+    for (int l = 0; l < c->L; ++l)
+      if (nt.act[l] != c->act[l]) return bad("all species need the same activations");
+    double* P = c->params.data() + (size_t)s * c->nps;
+    size_t po = 0;
+    for (int l = 0; l < c->L; ++l) {
+      const size_t nw = (size_t)c->w[l + 1] * c->w[l];
+      if (!nt.W || !nt.b || !nt.W[l] || !nt.b[l]) return bad("missing weights");
+      std::memcpy(P + po, nt.W[l], nw * 8);
+      po += nw;
+      std::memcpy(P + po, nt.b[l], (size_t)c->w[l + 1] * 8);
+      po += c->w[l + 1];
+    }
+    for (int k = 0; k < c->D; ++k) {
+      if (nt.in_shift) c->shift[(size_t)s * c->D + k] = nt.in_shift[k];
+      if (nt.in_scale) c->scale[(size_t)s * c->D + k] = nt.in_scale[k];
+    }
+    c->e_off[s] = nt.e_offset;
+    for (size_t k = 0; k < (size_t)c->nps; ++k)
+      if (!std::isfinite(P[k])) return bad("non-finite network parameter");
+  }
+  // MLP shape
+  c->mlp.n_layers = c->L;
+  for (int l = 0; l <= c->L; ++l) {
+    c->mlp.w[l] = c->w[l];
+    c->mlp.wp[l] = c->wp[l];
+  }
+  for (int l = 0; l < c->L; ++l) c->mlp.act[l] = c->act[l];
+  c->mlp.ldG = c->ldG;
+  // padded training layout
+  c->npad_species = 0;
+  for (int l = 1; l <= c->L; ++l) {
+    const int out = l == c->L ? 1 : c->wp[l];
+    c->npad_species += out * c->wp[l - 1] + out;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    g_setup_error = "hipSetDevice failed";
+    delete c;
+    return AENET_E_DEVICE;
+  }
+  if (hipStreamCreate(&c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    g_setup_error = "hipStreamCreate failed";
+    delete c;
+    return AENET_E_DEVICE;
+  }
+  if (pack_networks(c) != AENET_OK) {
+    g_setup_error = c->err;
+    aenet_destroy(c);
+    return AENET_E_DEVICE;
+  }
+  // masses (kappa / m per species) and the API -> padded parameter map
+  double invmk[kMaxSpecies] = {0};
+  for (int s = 0; s < c->S; ++s) invmk[s] = c->mass[s] > 0 ? kKappa / c->mass[s] : 0.0;
+  std::vector<int> pidx((size_t)c->S * c->nps);
+  for (int s = 0; s < c->S; ++s) {
+    size_t po = (size_t)s * c->nps, go = 0;
+    for (int l = 1; l <= c->L; ++l) {
+      const int in = c->w[l - 1], out = c->w[l];
+      const int outp = l == c->L ? 1 : c->wp[l], inp = c->wp[l - 1];
+      for (int q = 0; q < out; ++q)
+        for (int k = 0; k < in; ++k) pidx[po++] = (int)((size_t)s * c->npad_species + go + (size_t)q * inp + k);
+      for (int q = 0; q < out; ++q) pidx[po++] = (int)((size_t)s * c->npad_species + go + (size_t)outp * inp + q);
+      go += (size_t)outp * inp + outp;
+    }
+  }
+  if (ensure(c, c->d_mass, kMaxSpecies * 8) || ensure(c, c->d_invmk, kMaxSpecies * 8) ||
+      ensure(c, c->d_pidx, pidx.size() * 4) ||
+      hipMemcpy(c->d_mass.p, c->mass, kMaxSpecies * 8, hipMemcpyHostToDevice) ||
+      hipMemcpy(c->d_invmk.p, invmk, kMaxSpecies * 8, hipMemcpyHostToDevice) ||
+      hipMemcpy(c->d_pidx.p, pidx.data(), pidx.size() * 4, hipMemcpyHostToDevice)) {
+    g_setup_error = "device buffers for the model could not be set up";
+    aenet_destroy(c);
+    return AENET_E_DEVICE;
+  }
+  c->stats.rebuild_every = c->rebuild_every;
+  c->stats.deterministic = 1;
+  *out = c;
+  return AENET_OK;
+}
+
+void aenet_destroy(aenet_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamDestroy(c->stream);
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* aenet_last_error(const aenet_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+int aenet_descriptor_dim(const aenet_ctx* c) { return c ? c->D : -1; }
+
+int64_t aenet_n_params(const aenet_ctx* c) { return c ? (int64_t)c->S * c->nps : -1; }
+
+aenet_status aenet_get_params(aenet_ctx* c, double* params) {
+  if (!c || !params) return AENET_E_INVALID;
+  std::memcpy(params, c->params.data(), c->params.size() * 8);
+  return AENET_OK;
+}
+
+aenet_status aenet_set_params(aenet_ctx* c, const double* params) {
+  TRY(check_ctx(c));
+  if (!params) return fail(c, AENET_E_INVALID, "params is NULL");
+  for (size_t k = 0; k < c->params.size(); ++k)
+    if (!std::isfinite(params[k])) return fail(c, AENET_E_NONFINITE, "non-finite parameter");
+  std::memcpy(c->params.data(), params, c->params.size() * 8);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return pack_networks(c);
+}
+
+int aenet_supported_orders(int* orders, int max_pairs) { return desc_supported_list(orders, max_pairs); }
+
+aenet_status aenet_energy_forces_dev(aenet_ctx* c, int64_t n, const double* pos,
+                                     const int32_t* species, const double box[3],
+                                     const uint8_t pbc[3], double* e_total, double* e_atom,
+                                     double* forces, void* stream) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && !pos)) return fail(c, AENET_E_INVALID, "bad arguments");
+  const int64_t off[2] = {0, n};
+  return ef_core(c, 1, off, pos, species, box, pbc, nullptr, e_total, e_atom, forces, pick_stream(c, stream));
+}
+
+aenet_status aenet_energy_forces_batch_dev(aenet_ctx* c, int n_struct, const int64_t* offsets,
+                                           const double* pos, const int32_t* species,
+                                           const double* boxes, const uint8_t pbc[3],
+                                           double* e_struct, double* e_atom, double* forces,
+                                           void* stream) {
+  TRY(check_ctx(c));
+  if (n_struct < 1 || !offsets || !boxes) return fail(c, AENET_E_INVALID, "bad arguments");
+  return ef_core(c, n_struct, offsets, pos, species, boxes, pbc, e_struct, nullptr, e_atom, forces,
+                 pick_stream(c, stream));
+}
+
+aenet_status aenet_energy_forces(aenet_ctx* c, int64_t n, const double* pos,
+                                 const int32_t* species, const double box[3],
+                                 const uint8_t pbc[3], double* e_total, double* e_atom,
+                                 double* forces) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && !pos)) return fail(c, AENET_E_INVALID, "bad arguments");
+  for (int64_t k = 0; k < 3 * n; ++k)
+    if (!std::isfinite(pos[k])) return fail(c, AENET_E_NONFINITE, "non-finite position");
+  const size_t nb = (size_t)std::max<int64_t>(n, 1);
+  TRY(ensure(c, c->h_pos, nb * 24));
+  TRY(ensure(c, c->h_F, nb * 24));
+  TRY(ensure(c, c->h_E, (nb + 1) * 8));
+  hipStream_t s = c->stream;
+  if (n > 0) HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
+  const int64_t off[2] = {0, n};
+  double* dE = c->h_E.as<double>();
+  TRY(ef_core(c, 1, off, c->h_pos.as<double>(), species, box, pbc, nullptr, dE + nb,
+              e_atom ? dE : nullptr, forces ? c->h_F.as<double>() : nullptr, s));
+  double et = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&et, dE + nb, 8, hipMemcpyDeviceToHost, s));
+  if (e_atom && n > 0) HIP_TRY(c, hipMemcpyAsync(e_atom, dE, n * 8, hipMemcpyDeviceToHost, s));
+  if (forces && n > 0) HIP_TRY(c, hipMemcpyAsync(forces, c->h_F.p, n * 24, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (!std::isfinite(et)) return fail(c, AENET_E_NONFINITE, "non-finite energy");
+  if (e_total) *e_total = et;
+  return AENET_OK;
+}
+
+aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const int32_t* species,
+                               const double box[3], const uint8_t pbc[3], double* G) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && (!pos || !G))) return fail(c, AENET_E_INVALID, "bad arguments");
+  const int64_t off[2] = {0, n};
+  TRY(prepare(c, 1, off, species, box, pbc));
+  if (n == 0) return AENET_OK;
+  hipStream_t s = c->stream;
+  TRY(ensure(c, c->h_pos, (size_t)n * 24));
+  HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+  launch_gather_in((int)n, c->d_perm.as<int>(), c->h_pos.as<double>(), c->d_pos.as<double>(),
+                   c->d_flags.as<int>(), s);
+  TRY(build_checked(c, s));
+  DescParams dp = desc_params(c);
+  launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s);
+  HIP_TRY(c, hipGetLastError());
+  const size_t el = real_size(c);
+  std::vector<unsigned char> buf((size_t)n * c->ldG * el);
+  HIP_TRY(c, hipMemcpyAsync(buf.data(), c->d_G.p, buf.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  for (int64_t p = 0; p < n; ++p) {
+    double* dst = G + (size_t)c->perm[p] * c->D;
+    for (int k = 0; k < c->D; ++k)
+      dst[k] = el == 8 ? reinterpret_cast<double*>(buf.data())[(size_t)p * c->ldG + k]
+                       : (double)reinterpret_cast<float*>(buf.data())[(size_t)p * c->ldG + k];
+  }
+  return AENET_OK;
+}
+
+static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, const int32_t* species,
+                            const double box[3], const uint8_t pbc[3], double dt, int n_steps,
+                            double* e_pot, double* e_kin, double* forces, hipStream_t s) {
+  if (!c->have_mass) return fail(c, AENET_E_INVALID, "molecular dynamics needs mass_amu in the model");
+  if (!(dt > 0) || n_steps < 0) return fail(c, AENET_E_INVALID, "dt must be > 0 and n_steps >= 0");
+  const int64_t off[2] = {0, n};
+  TRY(prepare(c, 1, off, species, box, pbc));
+  const int N = (int)n;
+  if (N == 0) {
+    if (e_pot) HIP_TRY(c, hipMemsetAsync(e_pot, 0, 8, s));
+    if (e_kin) HIP_TRY(c, hipMemsetAsync(e_kin, 0, 8, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return AENET_OK;
+  }
+  TRY(ensure(c, c->d_save_pos, (size_t)N * 24));
+  TRY(ensure(c, c->d_save_vel, (size_t)N * 24));
+  TRY(ensure(c, c->d_save_F, (size_t)N * 24));
+  HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+  launch_gather_in(N, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
+  launch_gather_in(N, c->d_perm.as<int>(), vel, c->d_vel.as<double>(), c->d_flags.as<int>(), s);
+  TRY(build_checked(c, s));
+  TRY(compute(c, s, true, nullptr, 0.0));
+  const double half_dt = 0.5 * dt;
+  const double hs2 = 0.25 * c->skin * c->skin;
+  const int K = std::max(1, c->rebuild_every);
+  int* flags = c->d_flags.as<int>();
+  int t = 0;  // steps done
+  while (t < n_steps) {
+    const int len = std::min(K - (t % K), n_steps - t);
+    // checkpoint for a capacity retry
+    launch_copy_f64(3 * (int64_t)N, c->d_pos.as<double>(), c->d_save_pos.as<double>(), s);
+    launch_copy_f64(3 * (int64_t)N, c->d_vel.as<double>(), c->d_save_vel.as<double>(), s);
+    launch_copy_f64(3 * (int64_t)N, c->d_F.as<double>(), c->d_save_F.as<double>(), s);
+    HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+    bool force_first = false;
+    for (int attempt = 0;; ++attempt) {
+      for (int k = 0; k < len; ++k) {
+        const int step = t + k + 1;  // 1-based index of this step
+        int* rb = flags + 3 + (step & 1);
+        int* other = flags + 3 + ((step + 1) & 1);
+        const int force = (step % K == 0) || (force_first && k == 0);
+        prof_begin(c, s, AENET_K_INTEGRATE);
+        launch_vv_drift(N, c->d_pos.as<double>(), c->d_vel.as<double>(), c->d_F.as<double>(),
+                        c->d_pos_ref.as<double>(), c->d_invmk.as<double>(), c->d_species.as<int>(),
+                        half_dt, dt, hs2, rb, other, force, s);
+        prof_end(c, s);
+        build_neighbors_timed(c, nbr_params(c, rb), s);
+        TRY(compute(c, s, true, c->d_vel.as<double>(), half_dt));
+      }
+      int hf[8];
+      TRY(read_flags(c, s, hf));
+      TRY(flag_status(c, hf[0]));
+      if (!(hf[0] & kFlagOverflow)) break;
+      if (attempt >= 3) return fail(c, AENET_E_DEVICE, "neighbour capacity retries exhausted");
+      TRY(grow_caps(c, hf));
+      launch_copy_f64(3 * (int64_t)N, c->d_save_pos.as<double>(), c->d_pos.as<double>(), s);
+      launch_copy_f64(3 * (int64_t)N, c->d_save_vel.as<double>(), c->d_vel.as<double>(), s);
+      launch_copy_f64(3 * (int64_t)N, c->d_save_F.as<double>(), c->d_F.as<double>(), s);
+      HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+      force_first = true;
+    }
+    t += len;
+  }
+  // outputs
+  double* scal = c->d_scal.as<double>();
+  launch_sum(N, c->d_E.as<double>(), c->d_red.as<double>(), e_pot ? e_pot : scal, s);
+  launch_kinetic(N, c->d_vel.as<double>(), c->d_mass.as<double>(), c->d_species.as<int>(),
+                 c->d_tmp.as<double>(), s);
+  launch_sum(N, c->d_tmp.as<double>(), c->d_red.as<double>(), e_kin ? e_kin : scal + 1, s);
+  launch_wrap_scatter_out(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
+                          c->d_boxes.as<BoxInfo>(), c->pbc, pos, s);
+  launch_scatter_out(N, c->d_perm.as<int>(), c->d_vel.as<double>(), vel, nullptr, nullptr, s);
+  if (forces) launch_scatter_out(N, c->d_perm.as<int>(), c->d_F.as<double>(), forces, nullptr, nullptr, s);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return AENET_OK;
+}
+
+aenet_status aenet_md_step_dev(aenet_ctx* c, int64_t n, double* pos, double* vel,
+                               const int32_t* species, const double box[3], const uint8_t pbc[3],
+                               double dt_ps, int n_steps, double* e_pot, double* e_kin,
+                               double* forces, void* stream) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && (!pos || !vel))) return fail(c, AENET_E_INVALID, "bad arguments");
+  return md_core(c, n, pos, vel, species, box, pbc, dt_ps, n_steps, e_pot, e_kin, forces,
+                 pick_stream(c, stream));
+}
+
+aenet_status aenet_md_step(aenet_ctx* c, int64_t n, double* pos, double* vel,
+                           const int32_t* species, const double box[3], const uint8_t pbc[3],
+                           double dt_ps, int n_steps, double* e_pot, double* e_kin,
+                           double* forces) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && (!pos || !vel))) return fail(c, AENET_E_INVALID, "bad arguments");
+  for (int64_t k = 0; k < 3 * n; ++k)
+    if (!std::isfinite(pos[k]) || !std::isfinite(vel[k]))
+      return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
+  const size_t nb = (size_t)std::max<int64_t>(n, 1);
+  TRY(ensure(c, c->h_pos, nb * 24));
+  TRY(ensure(c, c->h_vel, nb * 24));
+  TRY(ensure(c, c->h_F, nb * 24));
+  TRY(ensure(c, c->h_E, (nb + 2) * 8));
+  hipStream_t s = c->stream;
+  if (n > 0) {
+    HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_vel.p, vel, n * 24, hipMemcpyHostToDevice, s));
+  }
+  double* dE = c->h_E.as<double>();
+  TRY(md_core(c, n, c->h_pos.as<double>(), c->h_vel.as<double>(), species, box, pbc, dt_ps, n_steps,
+              dE, dE + 1, forces ? c->h_F.as<double>() : nullptr, s));
+  double e2[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(e2, dE, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (!std::isfinite(e2[0]) || !std::isfinite(e2[1])) return fail(c, AENET_E_NONFINITE, "non-finite energy");
+  if (n > 0) {
+    HIP_TRY(c, hipMemcpyAsync(pos, c->h_pos.p, n * 24, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(vel, c->h_vel.p, n * 24, hipMemcpyDeviceToHost, s));
+    if (forces) HIP_TRY(c, hipMemcpyAsync(forces, c->h_F.p, n * 24, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (e_pot) *e_pot = e2[0];
+  if (e_kin) *e_kin = e2[1];
+  return AENET_OK;
+}
+
+aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offsets,
+                                 const double* pos, const int32_t* species, const double* boxes,
+                                 const uint8_t pbc[3], const double* e_ref, const double* f_ref,
+                                 double lambda_f, double* loss, double* grad, void* stream) {
+  TRY(check_ctx(c));
+  if (c->prec == AENET_BF16) return fail(c, AENET_E_INVALID, "training needs an FP64 or FP32 context");
+  if (n_struct < 1 || !offsets || !boxes || !e_ref || !f_ref || !loss || !grad || !(lambda_f >= 0))
+    return fail(c, AENET_E_INVALID, "bad arguments");
+  hipStream_t s = pick_stream(c, stream);
+  TRY(prepare(c, n_struct, offsets, species, boxes, pbc));
+  const int n = (int)c->n;
+  if (n == 0) return fail(c, AENET_E_INVALID, "empty batch");
+  for (int b = 0; b < n_struct; ++b)
+    if (offsets[b + 1] == offsets[b]) return fail(c, AENET_E_INVALID, "empty structure in batch");
+  const size_t el = real_size(c);
+  TRY(ensure(c, c->d_U, (size_t)n * c->ldG * el));
+  TRY(ensure(c, c->d_adj, (size_t)n * 24));
+  TRY(ensure(c, c->d_eps, (size_t)n * 8));
+  TRY(ensure(c, c->d_estruct, (size_t)n_struct * 8));
+  HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+  launch_gather_in(n, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
+  TRY(build_checked(c, s));
+  TRY(compute(c, s, true, nullptr, 0.0));
+  // structure energies (caller order makes every structure contiguous)
+  launch_scatter_out(n, c->d_perm.as<int>(), nullptr, nullptr, c->d_E.as<double>(), c->d_Eorig.as<double>(), s);
+  launch_segment_sum(n_struct, c->d_segoff.as<int64_t>(), c->d_Eorig.as<double>(), c->d_estruct.as<double>(), s);
+  // loss terms: tmp[0..n) force part per atom, tmp[n..n+B) energy part per structure
+  double* tmp = c->d_tmp.as<double>();
+  launch_loss_terms(n, n_struct, c->d_seg.as<int>(), c->d_perm.as<int>(), c->d_F.as<double>(), f_ref,
+                    c->d_estruct.as<double>(), e_ref, c->d_segcount.as<int64_t>(), lambda_f,
+                    c->d_adj.as<double>(), c->d_eps.as<double>(), tmp, tmp + n, s);
+  launch_sum((int64_t)n + n_struct, tmp, c->d_red.as<double>(), loss, s);
+  // descriptor JVP along the force adjoint, then double back-propagation
+  DescParams dp = desc_params(c);
+  launch_desc_jvp(desc_prec(c), c->nr, c->na, dp, s);
+  MlpParams mp = mlp_params(c, false);
+  mp.U = c->d_U.p;
+  mp.eps_atom = c->d_eps.as<double>();
+  mp.tiles_per_block = 8;
+  int nblocks = 0;
+  for (int t = 0; t < c->S; ++t) {
+    const int nt = mp.tile_off[t + 1] - mp.tile_off[t];
+    nblocks += (nt + mp.tiles_per_block - 1) / mp.tiles_per_block;
+  }
+  const int npad = c->S * c->npad_species;
+  mp.n_params_pad = npad;
+  for (int t = 0; t < c->S; ++t) mp.param_off[t] = t * c->npad_species;
+  TRY(ensure(c, c->d_gradpart, (size_t)std::max(nblocks, 1) * npad * 8));
+  TRY(ensure(c, c->d_gradpad, (size_t)npad * 8));
+  mp.grad_part = c->d_gradpart.as<double>();
+  if (mlp_train_lds_bytes(c->prec, mp) > 160 * 1024) return fail(c, AENET_E_INVALID, "network too wide for the training kernel");
+  launch_mlp_train(c->prec == 0 ? 0 : 1, mp, nblocks, s);
+  launch_grad_reduce(nblocks, npad, c->d_gradpart.as<double>(), c->d_gradpad.as<double>(), s);
+  // padded -> API layout
+  launch_take((int)(c->S * c->nps), c->d_pidx.as<int>(), c->d_gradpad.as<double>(), grad, s);
+  HIP_TRY(c, hipGetLastError());
+  int hf[8];
+  TRY(read_flags(c, s, hf));
+  TRY(flag_status(c, hf[0]));
+  return AENET_OK;
+}
+
+aenet_status aenet_get_stats(const aenet_ctx* c, aenet_stats* out) {
+  if (!c || !out) return AENET_E_INVALID;
+  *out = c->stats;
+  out->rebuild_every = c->rebuild_every;
+  out->row_capacity = c->cap;
+  out->ang_capacity = c->cap_ang;
+  return AENET_OK;
+}
+
+aenet_status aenet_set_rebuild_every(aenet_ctx* c, int k) {
+  if (!c || k < 1) return AENET_E_INVALID;
+  c->rebuild_every = k;
+  return AENET_OK;
+}
+
+aenet_status aenet_set_profiling(aenet_ctx* c, int enable) {
+  TRY(check_ctx(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  c->profiling = enable != 0;
+  return AENET_OK;
+}
+
+aenet_status aenet_get_kernel_times(aenet_ctx* c, double* ms, int64_t* launches) {
+  TRY(check_ctx(c));
+  if (!ms || !launches) return fail(c, AENET_E_INVALID, "bad arguments");
+  prof_collect(c);
+  for (int k = 0; k < AENET_K_COUNT; ++k) {
+    ms[k] = c->prof_ms[k];
+    launches[k] = c->prof_n[k];
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return AENET_OK;
+}
+
+}  // extern "C"
+

@@ -1,0 +1,303 @@
+// md.hip -- velocity-Verlet integrator (the propagation step of the MD cycle,
+// Fig. 1), the deterministic force gather, permutations between the caller's
+// atom order and the internal species-sorted order, deterministic reductions
+// (total energy, Sec. II A, Eq. 2; kinetic energy) and the per-atom terms of
+// the training loss.
+#include "aenet_internal.h"
+
+namespace aenet {
+
+namespace {
+
+constexpr double kKappa = 9648.533215665;  // (eV/amu) in A^2/ps^2
+
+inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+__device__ inline bool finite3(double a, double b, double c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+__global__ void k_gather_in(int n, const int* perm, const double* src, double* dst, int* flags) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const size_t o = (size_t)perm[p];
+  const double a = src[3 * o], b = src[3 * o + 1], c = src[3 * o + 2];
+  if (!finite3(a, b, c)) atomicOr(flags, kFlagNonFinite);
+  dst[3 * (size_t)p] = a;
+  dst[3 * (size_t)p + 1] = b;
+  dst[3 * (size_t)p + 2] = c;
+}
+
+__global__ void k_scatter_out(int n, const int* perm, const double* src3, double* dst3,
+                              const double* src1, double* dst1) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const size_t o = (size_t)perm[p];
+  if (dst3) {
+    dst3[3 * o] = src3[3 * (size_t)p];
+    dst3[3 * o + 1] = src3[3 * (size_t)p + 1];
+    dst3[3 * o + 2] = src3[3 * (size_t)p + 2];
+  }
+  if (dst1) dst1[o] = src1[p];
+}
+
+__global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
+                                   const BoxInfo* boxes, int px, int py, int pz, double* dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const BoxInfo b = boxes[seg[p]];
+  const int pb[3] = {px, py, pz};
+  const size_t o = (size_t)perm[p];
+  for (int a = 0; a < 3; ++a) {
+    double x = pos[3 * (size_t)p + a];
+    if (pb[a]) {
+      x = x - b.L[a] * floor(x / b.L[a]);
+      if (x >= b.L[a]) x -= b.L[a];
+      if (x < 0.0) x = 0.0;
+    }
+    dst[3 * o + a] = x;
+  }
+}
+
+// F_i = sum_e pg[i,e] - sum_e pg[rev(i,e)]: the first sum was formed by the
+// descriptor backward kernel (Fself); the second gathers the reverse entries.
+template <typename R>
+__global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nnb, const int* rev,
+                                                      const R* pg, const double* Fself, double* F,
+                                                      double* vel, const double* inv_mass_k,
+                                                      const int* species, double half_dt) {
+  constexpr int LPA = 16;
+  const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
+  const int i = blockIdx.x * (blockDim.x / LPA) + g;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  const int nn = i < n ? nnb[i] : 0;
+  for (int e = l; e < nn; e += LPA) {
+    const int r = rev[(size_t)i * cap + e];
+    if (r >= 0) {
+      sx += (double)pg[3 * (size_t)r];
+      sy += (double)pg[3 * (size_t)r + 1];
+      sz += (double)pg[3 * (size_t)r + 2];
+    }
+  }
+#pragma unroll
+  for (int o = LPA / 2; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o, LPA);
+    sy += __shfl_xor(sy, o, LPA);
+    sz += __shfl_xor(sz, o, LPA);
+  }
+  if (i < n && l == 0) {
+    const double fx = Fself[3 * (size_t)i] - sx;
+    const double fy = Fself[3 * (size_t)i + 1] - sy;
+    const double fz = Fself[3 * (size_t)i + 2] - sz;
+    F[3 * (size_t)i] = fx;
+    F[3 * (size_t)i + 1] = fy;
+    F[3 * (size_t)i + 2] = fz;
+    if (vel) {
+      const double c = half_dt * inv_mass_k[species[i]];
+      vel[3 * (size_t)i] += c * fx;
+      vel[3 * (size_t)i + 1] += c * fy;
+      vel[3 * (size_t)i + 2] += c * fz;
+    }
+  }
+}
+
+// first half kick + drift; flags a neighbour-list rebuild when an atom has
+// moved more than skin/2 since the last build
+__global__ void k_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
+                           const double* inv_mass_k, const int* species, double half_dt, double dt,
+                           double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *clear_flag = 0;
+    if (force_rebuild) *rebuild_flag = 1;
+  }
+  if (i >= n) return;
+  const double c = half_dt * inv_mass_k[species[i]];
+  double d2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const size_t k = 3 * (size_t)i + a;
+    const double v = vel[k] + c * F[k];
+    vel[k] = v;
+    const double x = pos[k] + dt * v;
+    pos[k] = x;
+    const double dd = x - pos_ref[k];
+    d2 += dd * dd;
+  }
+  if (!(d2 <= half_skin2)) *rebuild_flag = 1;
+}
+
+constexpr int kRedChunk = 2048;  // elements per partial sum (fixed: results depend only on n)
+
+__global__ __launch_bounds__(256) void k_partial_sum(int64_t n, const double* x, double* part) {
+  __shared__ double s[256];
+  const int64_t base = (int64_t)blockIdx.x * kRedChunk;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < kRedChunk; k += 256) {
+    const int64_t idx = base + k;
+    if (idx < n) acc += x[idx];
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(1024) void k_final_sum(int m, const double* part, double* out) {
+  __shared__ double s[1024];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < m; k += 1024) acc += part[k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void k_kinetic(int n, const double* vel, const double* mass, const int* species,
+                          double* tmp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double vx = vel[3 * (size_t)i], vy = vel[3 * (size_t)i + 1], vz = vel[3 * (size_t)i + 2];
+  tmp[i] = 0.5 * mass[species[i]] * (vx * vx + vy * vy + vz * vz) / kKappa;
+}
+
+__global__ __launch_bounds__(256) void k_segment_sum(const int64_t* off, const double* x, double* out) {
+  __shared__ double s[256];
+  const int64_t lo = off[blockIdx.x], hi = off[blockIdx.x + 1];
+  double acc = 0.0;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) acc += x[k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+__global__ void k_copy(int64_t n, const double* src, double* dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[k];
+}
+
+__global__ void k_check_finite(int64_t n, const double* x, int* flags) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && !isfinite(x[k])) atomicOr(flags, kFlagNonFinite);
+}
+
+// per-atom loss terms in internal order; f_ref in the caller's order
+__global__ void k_loss_atoms(int n, int n_struct, const int* seg, const int* perm, const double* F,
+                             const double* f_ref, const double* e_struct, const double* e_ref,
+                             const int64_t* seg_count, double lambda_f, double* adj,
+                             double* eps_atom, double* floss_atom) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int s = seg[p];
+  const double Ns = (double)seg_count[s];
+  const double B = (double)n_struct;
+  const size_t o = (size_t)perm[p];
+  double sq = 0.0;
+  const double c = 2.0 * lambda_f / (3.0 * Ns * B);
+  for (int a = 0; a < 3; ++a) {
+    const double df = F[3 * (size_t)p + a] - f_ref[3 * o + a];
+    adj[3 * (size_t)p + a] = c * df;
+    sq += df * df;
+  }
+  floss_atom[p] = lambda_f * sq / (3.0 * Ns * B);
+  eps_atom[p] = 2.0 * (e_struct[s] - e_ref[s]) / (Ns * Ns * B);
+}
+
+__global__ void k_loss_structs(int n_struct, const double* e_struct, const double* e_ref,
+                               const int64_t* seg_count, double* eloss) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_struct) return;
+  const double de = (e_struct[s] - e_ref[s]) / (double)seg_count[s];
+  eloss[s] = de * de / (double)n_struct;
+}
+
+}  // namespace
+
+void launch_gather_in(int n, const int* perm, const double* src, double* dst, int* flags,
+                      hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_in, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, src, dst, flags);
+}
+
+void launch_scatter_out(int n, const int* perm, const double* src3, double* dst3,
+                        const double* src1, double* dst1, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, src3, dst3, src1, dst1);
+}
+
+void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
+                             const BoxInfo* boxes, const int pbc[3], double* dst, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_wrap_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, pos, seg,
+                       boxes, pbc[0], pbc[1], pbc[2], dst);
+}
+
+void launch_force_gather(int prec, int n, int cap, const int* nnb, const int* rev, const void* pg,
+                         const double* Fself, double* F, double* vel, const double* inv_mass_k,
+                         const int* species, double half_dt, hipStream_t s) {
+  if (n <= 0) return;
+  const dim3 grid(nblk(n, 16)), block(256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_force_gather<double>, grid, block, 0, s, n, cap, nnb, rev,
+                       (const double*)pg, Fself, F, vel, inv_mass_k, species, half_dt);
+  else
+    hipLaunchKernelGGL(k_force_gather<float>, grid, block, 0, s, n, cap, nnb, rev,
+                       (const float*)pg, Fself, F, vel, inv_mass_k, species, half_dt);
+}
+
+void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
+                     const double* inv_mass_k, const int* species, double half_dt, double dt,
+                     double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_vv_drift, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, s, n, pos, vel, F,
+                     pos_ref, inv_mass_k, species, half_dt, dt, half_skin2, rebuild_flag,
+                     clear_flag, force_rebuild);
+}
+
+int reduce_blocks(int64_t n) { return (int)((n + kRedChunk - 1) / kRedChunk); }
+
+void launch_sum(int64_t n, const double* x, double* partials, double* out, hipStream_t s) {
+  const int m = reduce_blocks(n);
+  if (m > 0) hipLaunchKernelGGL(k_partial_sum, dim3(m), dim3(256), 0, s, n, x, partials);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(1024), 0, s, m, partials, out);
+}
+
+void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
+                    hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_kinetic, dim3(nblk(n, 256)), dim3(256), 0, s, n, vel, mass, species, tmp);
+}
+
+void launch_segment_sum(int n_seg, const int64_t* seg_off, const double* x, double* out,
+                        hipStream_t s) {
+  if (n_seg > 0) hipLaunchKernelGGL(k_segment_sum, dim3(n_seg), dim3(256), 0, s, seg_off, x, out);
+}
+
+void launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+}
+
+void launch_check_finite(int64_t n, const double* x, int* flags, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_check_finite, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, flags);
+}
+
+void launch_loss_terms(int n, int n_struct, const int* seg, const int* perm, const double* F,
+                       const double* f_ref, const double* e_struct, const double* e_ref,
+                       const int64_t* seg_count, double lambda_f, double* adj, double* eps_atom,
+                       double* floss_atom, double* eloss_struct, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_loss_atoms, dim3(nblk(n, 256)), dim3(256), 0, s, n, n_struct, seg, perm, F,
+                       f_ref, e_struct, e_ref, seg_count, lambda_f, adj, eps_atom, floss_atom);
+  if (n_struct > 0)
+    hipLaunchKernelGGL(k_loss_structs, dim3(nblk(n_struct, 256)), dim3(256), 0, s, n_struct,
+                       e_struct, e_ref, seg_count, eloss_struct);
+}
+
+}  // namespace aenet
