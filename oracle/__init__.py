@@ -67,6 +67,8 @@ def lib():
         L.orc_descriptors.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp]
         L.orc_energy_forces.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp, dp, dp, dp]
         L.orc_forces_dense.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp]
+        L.orc_energy_forces_subset.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, C.c_int, ip,
+                                               dp, dp, dp]
         L.orc_md_vv.argtypes = [C.POINTER(_Model), C.c_int, dp, dp, ip, dp, dp, ip, C.c_double,
                                 C.c_int, dp, dp, dp]
         L.orc_loss.argtypes = [C.POINTER(_Model), C.c_int, ip, dp, ip, dp, ip, dp, dp, C.c_double, dp]
@@ -239,6 +241,21 @@ def energy_forces(model, pos, species, box, pbc, want_G=False):
     if want_G:
         return E.value, Ea, F, G
     return E.value, Ea, F
+
+
+def energy_forces_subset(model, pos, species, box, pbc, sel):
+    """(E_atom [k], F [k,3], G [k,D]) of the selected atoms only."""
+    pos, box, pbc = _geom(pos, box, pbc)
+    sp = _i32(species)
+    sel = _i32(sel)
+    pk = _Packed(model)
+    D = descriptor_dim(model.n_species, model.radial_order, model.angular_order)
+    E = np.zeros(sel.size)
+    F = np.zeros((sel.size, 3))
+    G = np.zeros((sel.size, D))
+    _check(lib().orc_energy_forces_subset(pk.ptr, pos.shape[0], _dp(pos), _ip(sp), _dp(box), _ip(pbc),
+                                          sel.size, _ip(sel), _dp(E), _dp(F), _dp(G)))
+    return E, F, G
 
 
 def forces_dense(model, pos, species, box, pbc):

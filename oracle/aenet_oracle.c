@@ -573,6 +573,135 @@ int orc_energy_forces(const orc_model* m, int n, const double* pos, const int* s
 }
 
 /* ------------------------------------------------------------------------- */
+/* Selected atoms of a large structure: E_m, F_m (and G_m) for the atoms in   */
+/* sel only.  F_m = -sum_i dE_i/dr_m needs every atom i whose environment      */
+/* contains m, i.e. m itself and its neighbours, each with its own list.       */
+/* ------------------------------------------------------------------------- */
+
+/* entries of atom i alone (brute force over all atoms and images) */
+static int atom_list(int n, const double* posw, const double* box, const int* pbc, double cutoff,
+                     int i, entry** out, int* count) {
+  int smax[3];
+  int minimg = 1;
+  for (int a = 0; a < 3; ++a) {
+    smax[a] = pbc[a] ? (int)ceil(cutoff / box[a]) + 1 : 0;
+    if (pbc[a] && box[a] < 2.0 * cutoff) minimg = 0;
+  }
+  int cap = 256, used = 0;
+  entry* e = (entry*)malloc(sizeof(entry) * (size_t)cap);
+  if (!e) return ORC_E_NOMEM;
+  const double c2 = cutoff * cutoff;
+  for (int j = 0; j < n; ++j) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = -smax[a]; hi[a] = smax[a]; }
+    if (minimg) {
+      if (j == i) continue;
+      for (int a = 0; a < 3; ++a) {
+        int s = 0;
+        if (pbc[a]) {
+          double dd = posw[3 * j + a] - posw[3 * i + a];
+          if (dd > 0.5 * box[a]) s = -1;
+          else if (dd < -0.5 * box[a]) s = 1;
+        }
+        lo[a] = hi[a] = s;
+      }
+    }
+    for (int sx = lo[0]; sx <= hi[0]; ++sx)
+      for (int sy = lo[1]; sy <= hi[1]; ++sy)
+        for (int sz = lo[2]; sz <= hi[2]; ++sz) {
+          if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
+          int s[3] = {sx, sy, sz};
+          double d[3];
+          for (int a = 0; a < 3; ++a) d[a] = posw[3 * j + a] + (double)s[a] * box[a] - posw[3 * i + a];
+          double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          if (!(r2 < c2)) continue;
+          if (r2 == 0.0) { free(e); return ORC_E_OVERLAP; }
+          if (used == cap) {
+            cap *= 2;
+            entry* ne = (entry*)realloc(e, sizeof(entry) * (size_t)cap);
+            if (!ne) { free(e); return ORC_E_NOMEM; }
+            e = ne;
+          }
+          e[used].j = j;
+          for (int a = 0; a < 3; ++a) { e[used].s[a] = s[a]; e[used].d[a] = d[a]; }
+          e[used].r = sqrt(r2);
+          ++used;
+        }
+  }
+  *out = e;
+  *count = used;
+  return ORC_OK;
+}
+
+int orc_energy_forces_subset(const orc_model* m, int n, const double* pos, const int* species,
+                             const double* box, const int* pbc, int n_sel, const int* sel,
+                             double* e_sel, double* f_sel, double* g_sel) {
+  int st = check_model(m);
+  if (st) return st;
+  if ((st = check_species(m, n, species))) return st;
+  layout L = make_layout(m);
+  const double rc = list_cutoff(m);
+  double* posw = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  double* F = (double*)calloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  int maxo = (m->radial_order > m->angular_order ? m->radial_order : m->angular_order) + 1;
+  double* G = (double*)malloc(sizeof(double) * (size_t)L.D);
+  double* g = (double*)malloc(sizeof(double) * (size_t)L.D);
+  double* T = (double*)malloc(sizeof(double) * (size_t)maxo);
+  double* dT = (double*)malloc(sizeof(double) * (size_t)maxo);
+  net_ws ws;
+  memset(&ws, 0, sizeof(ws));
+  if (!posw || !F || !G || !g || !T || !dT || ws_alloc(m, &ws)) st = ORC_E_NOMEM;
+  if (st == ORC_OK) wrap_positions(n, pos, box, pbc, posw);
+  for (int q = 0; st == ORC_OK && q < n_sel; ++q) {
+    const int mi = sel[q];
+    if (mi < 0 || mi >= n) { st = ORC_E_INVALID; break; }
+    entry* em = NULL;
+    int nm = 0;
+    st = atom_list(n, posw, box, pbc, rc, mi, &em, &nm);
+    if (st) break;
+    /* atoms whose environment holds mi: mi itself and every neighbour atom of mi
+       (each atom once, whatever the number of its images) */
+    int* who = (int*)malloc(sizeof(int) * (size_t)(nm + 1));
+    int nw = 0;
+    who[nw++] = mi;
+    for (int p = 0; p < nm; ++p) {
+      int seen = 0;
+      for (int k = 0; k < nw; ++k) if (who[k] == em[p].j) { seen = 1; break; }
+      if (!seen) who[nw++] = em[p].j;
+    }
+    for (int k = 0; k < 3 * n; ++k) F[k] = 0.0;
+    for (int k = 0; st == ORC_OK && k < nw; ++k) {
+      const int i = who[k];
+      entry* ei = NULL;
+      int ni = 0;
+      st = atom_list(n, posw, box, pbc, rc, i, &ei, &ni);
+      if (st) break;
+      atom_descriptor(m, &L, ei, ni, species, G, T);
+      const orc_net* net = &m->nets[species[i]];
+      double Ei = net_forward(net, G, ws.xs);
+      net_backward(net, ws.xs, ws.b1, ws.b2, g);
+      atom_forces(m, &L, i, ei, ni, species, g, T, dT, F);
+      if (i == mi) {
+        if (e_sel) e_sel[q] = Ei;
+        if (g_sel) memcpy(g_sel + (size_t)q * L.D, G, sizeof(double) * (size_t)L.D);
+      }
+      free(ei);
+    }
+    if (f_sel) for (int c = 0; c < 3; ++c) f_sel[3 * q + c] = F[3 * mi + c];
+    free(who);
+    free(em);
+  }
+  free(posw);
+  free(F);
+  free(G);
+  free(g);
+  free(T);
+  free(dT);
+  ws_free(&ws, m);
+  return st;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Second formulation: Jacobians of the descriptor w.r.t. entry displacements. */
 /* ------------------------------------------------------------------------- */
 

@@ -81,6 +81,13 @@ int orc_energy_forces(const orc_model* m, int n, const double* pos, const int* s
                       const double* box, const int* pbc, double* e_total, double* e_atom,
                       double* forces, double* G);
 
+/* E_m, F_m (and G_m if g_sel != NULL) of the n_sel atoms listed in sel only,
+ * for structures too large for a full evaluation; e_sel [n_sel], f_sel
+ * [n_sel x 3], g_sel [n_sel x D]. */
+int orc_energy_forces_subset(const orc_model* m, int n, const double* pos, const int* species,
+                             const double* box, const int* pbc, int n_sel, const int* sel,
+                             double* e_sel, double* f_sel, double* g_sel);
+
 /* Forces by the second formulation: dense Jacobians J_i = dG_i/dr, F = -sum J_i^T g_i.
  * Memory is O(n * D) per atom; meant for small systems. */
 int orc_forces_dense(const orc_model* m, int n, const double* pos, const int* species,

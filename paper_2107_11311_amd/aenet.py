@@ -77,6 +77,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first (python __graft_entry__.py)")
+    # PyTorch ships its own HIP runtime; it only starts if it initialises the
+    # device before the library's runtime does, so let it go first when present.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = C.CDLL(path)
     ctxp = C.c_void_p
     L.aenet_setup.argtypes = [C.POINTER(_Model), C.POINTER(ctxp)]

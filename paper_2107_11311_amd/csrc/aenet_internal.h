@@ -51,6 +51,7 @@ struct NbrParams {
   int* cell_atoms;       // [n]
   int* atom_cell;        // [n]
   uint32_t* nbr;         // [n*cap]
+  uint32_t* nbr_tmp;     // [n*cap] scratch rows
   int* nnb;              // [n]
   int* nang;             // [n]
   int* rev;              // [n*cap] global index of the reverse entry
@@ -72,6 +73,7 @@ struct DescParams {
   const int* nnb;
   const int* nang;
   int cap, cap_ang;
+  int max_ang;           // largest angular prefix seen at the last checked build (tuning only)
   double rr, ra;
   double tw[kMaxSpecies];
   int weighted;          // n_species > 1

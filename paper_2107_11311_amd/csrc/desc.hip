@@ -613,11 +613,18 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
 
 template <typename R, int NR, int NA>
 void launch_orders(int kind, const DescParams& p, hipStream_t s) {
-  // wide groups for crowded angular shells, narrow ones otherwise
-  if (p.cap_ang > 64) {
+  // Lanes per atom from the angular shell seen at the last build: narrow groups
+  // keep the cross-lane reductions short for sparse shells (water: ~30 angular
+  // neighbours), wide ones give crowded shells (dense amorphous: ~110) enough
+  // lanes.  The backward pass gives one lane per angular entry.
+  const int na = p.max_ang > 0 ? p.max_ang : p.cap_ang;
+  if (na > 64) {
     launch_kind<R, NR, NA, 64>(kind, p, s);
   } else if (kind == BWD) {
-    launch_kind<R, NR, NA, 32>(kind, p, s);
+    if (na > 32)
+      launch_kind<R, NR, NA, 64>(kind, p, s);
+    else
+      launch_kind<R, NR, NA, 32>(kind, p, s);
   } else {
     launch_kind<R, NR, NA, 16>(kind, p, s);
   }

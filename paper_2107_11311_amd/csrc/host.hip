@@ -78,7 +78,7 @@ struct aenet_ctx {
   DevMem d_perm, d_species, d_seg, d_segoff, d_segcount, d_boxes;
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
       d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
-  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_nnb, d_nang, d_rev;
+  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_nbr_tmp, d_nnb, d_nang, d_rev;
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
 
@@ -343,6 +343,7 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
 aenet_status ensure_rows(aenet_ctx* c) {
   const size_t nb = (size_t)std::max<int64_t>(c->n, 1);
   TRY(ensure(c, c->d_nbr, nb * c->cap * 4));
+  TRY(ensure(c, c->d_nbr_tmp, nb * c->cap * 4));
   TRY(ensure(c, c->d_rev, nb * c->cap * 4));
   TRY(ensure(c, c->d_pg, nb * c->cap * 3 * real_size(c)));
   return AENET_OK;
@@ -367,6 +368,7 @@ NbrParams nbr_params(aenet_ctx* c, const int* cond) {
   p.cell_atoms = c->d_cell_atoms.as<int>();
   p.atom_cell = c->d_atom_cell.as<int>();
   p.nbr = c->d_nbr.as<uint32_t>();
+  p.nbr_tmp = c->d_nbr_tmp.as<uint32_t>();
   p.nnb = c->d_nnb.as<int>();
   p.nang = c->d_nang.as<int>();
   p.rev = c->d_rev.as<int>();
@@ -388,6 +390,7 @@ DescParams desc_params(aenet_ctx* c) {
   p.nang = c->d_nang.as<int>();
   p.cap = c->cap;
   p.cap_ang = c->cap_ang;
+  p.max_ang = std::min(c->stats.max_angular, c->cap_ang);
   p.rr = c->rr;
   p.ra = c->ra;
   for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];
@@ -876,7 +879,7 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   TRY(ensure(c, c->d_save_pos, (size_t)N * 24));
   TRY(ensure(c, c->d_save_vel, (size_t)N * 24));
   TRY(ensure(c, c->d_save_F, (size_t)N * 24));
-  HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+  HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 16 * sizeof(int), s));
   launch_gather_in(N, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
   launch_gather_in(N, c->d_perm.as<int>(), vel, c->d_vel.as<double>(), c->d_flags.as<int>(), s);
   TRY(build_checked(c, s));
@@ -923,6 +926,12 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
     t += len;
   }
   // outputs
+  {
+    int dev_builds = 0;
+    HIP_TRY(c, hipMemcpyAsync(&dev_builds, c->d_flags.as<int>() + 8, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->stats.n_rebuilds += dev_builds;
+  }
   double* scal = c->d_scal.as<double>();
   launch_sum(N, c->d_E.as<double>(), c->d_red.as<double>(), e_pot ? e_pot : scal, s);
   launch_kinetic(N, c->d_vel.as<double>(), c->d_mass.as<double>(), c->d_species.as<int>(),

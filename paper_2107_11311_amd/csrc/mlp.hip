@@ -62,8 +62,9 @@ __device__ inline int acc_row(int lane, int i) {
   return PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i;
 }
 
-// one 16x16 output block: sum over K of A[16 x K] (LDS, row-major, ld) times
-// the packed B operand block nb (K/KS k-steps)
+// one 16x16 output block: sum over K of A[16 x K] (LDS, row-major, row stride
+// ld) times the packed B operand block nb (K/KS k-steps).  All operands of the
+// block are loaded before the MFMA chain so their latencies overlap.
 template <int PREC>
 __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* A, int ld, int K,
                                                      const typename Mt<PREC>::B* Bp, int nb,
@@ -72,23 +73,41 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
   typename M::Acc acc = {0, 0, 0, 0};
   const int ksteps = K / M::KS;
   const int r = lane & 15, kq = lane >> 4;
-  for (int ks = 0; ks < ksteps; ++ks) {
-    if constexpr (PREC == 0) {
-      const double a = A[r * ld + ks * 4 + kq];
-      const double b = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    } else if constexpr (PREC == 1) {
-      const float a = A[r * ld + ks * 4 + kq];
-      const float b = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-    } else {
-      v8bf a, b;
-      const float* ap = A + r * ld + ks * 32 + 8 * kq;
+  if constexpr (PREC == 0 || PREC == 1) {
+    typedef typename M::T T;
+    constexpr int MAXKS = kMaxWidth / 4;
+    T a[MAXKS], b[MAXKS];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) a[t] = (__bf16)ap[t];
-      b = *reinterpret_cast<const v8bf*>(Bp + (((size_t)nb * ksteps + ks) * 64 + lane) * 8);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    for (int ks = 0; ks < MAXKS; ++ks) {
+      if (ks < ksteps) {
+        a[ks] = A[r * ld + ks * 4 + kq];
+        b[ks] = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
+      }
     }
+#pragma unroll
+    for (int ks = 0; ks < MAXKS; ++ks) {
+      if (ks < ksteps) {
+        if constexpr (PREC == 0)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+        else
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], b[ks], acc, 0, 0, 0);
+      }
+    }
+  } else {
+    constexpr int MAXKS = kMaxWidth / 32;
+    v8bf a[MAXKS], b[MAXKS];
+#pragma unroll
+    for (int ks = 0; ks < MAXKS; ++ks) {
+      if (ks < ksteps) {
+        const float* ap = A + r * ld + ks * 32 + 8 * kq;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a[ks][t] = (__bf16)ap[t];
+        b[ks] = *reinterpret_cast<const v8bf*>(Bp + (((size_t)nb * ksteps + ks) * 64 + lane) * 8);
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < MAXKS; ++ks)
+      if (ks < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], b[ks], acc, 0, 0, 0);
   }
   return acc;
 }
@@ -120,10 +139,12 @@ __device__ inline TileInfo tile_info(const MlpParams& p, int tile) {
   return t;
 }
 
-// LDS layout of the forward/backward kernel (elements of T)
+// LDS layout of the forward/backward kernel (elements of T): activations of
+// layer l at act_offset(l), row stride wp[l] + 1 (the odd stride spreads the
+// 16 rows of an MFMA operand over the LDS banks)
 __host__ __device__ inline size_t act_offset(const MlpParams& p, int l) {
   size_t o = 0;
-  for (int k = 0; k < l; ++k) o += 16 * (size_t)p.wp[k];
+  for (int k = 0; k < l; ++k) o += 16 * (size_t)(p.wp[k] + 1);
   return o;
 }
 
@@ -137,8 +158,9 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
   const TileInfo ti = tile_info(p, blockIdx.x);
   const MlpNet& net = p.net[ti.species];
   const int L = p.n_layers;
-  T* D0 = lds + act_offset(p, L);  // two delta buffers of 16 x 64
-  T* D1 = D0 + 16 * kMaxWidth;
+  constexpr int DLD = kMaxWidth + 1;  // row stride of the delta buffers
+  T* D0 = lds + act_offset(p, L);     // two delta buffers of 16 x DLD
+  T* D1 = D0 + 16 * DLD;
 
   // normalised input tile
   {
@@ -150,7 +172,7 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
       const int r = idx / w0, c = idx % w0;
       T v = T(0);
       if (r < ti.count && c < D) v = (G[(size_t)(ti.first + r) * p.ldG + c] - sh[c]) * sc[c];
-      lds[idx] = v;
+      lds[r * (w0 + 1) + c] = v;
     }
   }
   __syncthreads();
@@ -164,12 +186,12 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
     const T* bias = reinterpret_cast<const T*>(net.bias[l]);
     const int act = p.act[l - 1];
     for (int nb = 0; nb < N / 16; ++nb) {
-      auto acc = mfma_block<PREC>(X, K, K, Bp, nb, lane);
+      auto acc = mfma_block<PREC>(X, K + 1, K, Bp, nb, lane);
       const int col = nb * 16 + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = acc_row<PREC>(lane, i);
-        Y[row * N + col] = act_fn<T>(act, T(acc[i]) + bias[col]);
+        Y[row * (N + 1) + col] = act_fn<T>(act, T(acc[i]) + bias[col]);
       }
     }
     __syncthreads();
@@ -181,7 +203,7 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
   const T* wl = reinterpret_cast<const T*>(net.wlast);
   if (lane < 16) {
     T e = T(0);
-    for (int k = 0; k < KL; ++k) e += XL[lane * KL + k] * wl[k];
+    for (int k = 0; k < KL; ++k) e += XL[lane * (KL + 1) + k] * wl[k];
     if (lane < ti.count) p.E[ti.first + lane] = (double)e + net.blast + net.e_offset;
   }
   if (!p.gG) return;
@@ -189,8 +211,9 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
   // back-propagation to the input (the output layer is linear; X_{L-1} was
   // produced by the activation of layer L-1, none if L == 1)
   for (int idx = lane; idx < 16 * KL; idx += 64) {
-    const int c = idx % KL;
-    D0[idx] = L >= 2 ? wl[c] * act_d1<T>(p.act[L - 2], XL[idx]) : wl[c];
+    const int r = idx / KL, c = idx % KL;
+    const T x = XL[r * (KL + 1) + c];
+    D0[r * DLD + c] = L >= 2 ? wl[c] * act_d1<T>(p.act[L - 2], x) : wl[c];
   }
   __syncthreads();
   T* Dcur = D0;
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
   if (L == 1) {
     for (int idx = lane; idx < 16 * p.wp[0]; idx += 64) {
       const int r = idx / p.wp[0], c = idx % p.wp[0];
-      if (r < ti.count && c < p.w[0]) gout[(size_t)(ti.first + r) * p.ldG + c] = Dcur[idx] * sc[c];
+      if (r < ti.count && c < p.w[0]) gout[(size_t)(ti.first + r) * p.ldG + c] = Dcur[r * DLD + c] * sc[c];
     }
     return;
   }
@@ -210,14 +233,14 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
     const T* Xp = lds + act_offset(p, l - 1);
     const int actp = l >= 2 ? p.act[l - 2] : 0;
     for (int nb = 0; nb < N / 16; ++nb) {
-      auto acc = mfma_block<PREC>(Dcur, K, K, Bp, nb, lane);
+      auto acc = mfma_block<PREC>(Dcur, DLD, K, Bp, nb, lane);
       const int col = nb * 16 + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = acc_row<PREC>(lane, i);
         const T v = T(acc[i]);
         if (l >= 2) {
-          Dnext[row * N + col] = v * act_d1<T>(actp, Xp[row * N + col]);
+          Dnext[row * DLD + col] = v * act_d1<T>(actp, Xp[row * (N + 1) + col]);
         } else if (row < ti.count && col < p.w[0]) {
           gout[(size_t)(ti.first + row) * p.ldG + col] = v * sc[col];
         }
@@ -446,7 +469,7 @@ __global__ void k_grad_reduce(int n_blocks, int n, const double* part, double* o
 
 size_t mlp_lds_bytes(int prec, const MlpParams& p) {
   const size_t el = prec == 0 ? sizeof(double) : sizeof(float);
-  return (act_offset(p, p.n_layers) + 2 * 16 * kMaxWidth) * el;
+  return (act_offset(p, p.n_layers) + 2 * 16 * (kMaxWidth + 1)) * el;
 }
 
 size_t mlp_train_lds_bytes(int prec, const MlpParams& p) {

@@ -14,6 +14,8 @@
 // parts are ordered by (stencil cell, atom).  That order makes the reverse
 // entry (j -> i, -s) of every (i -> j, s) findable by binary search, which the
 // deterministic force gather uses instead of atomics.
+#include <climits>
+
 #include "aenet_internal.h"
 
 namespace aenet {
@@ -54,6 +56,7 @@ __global__ void k_zero(NbrParams p) {
   if (c == 0) {
     p.maxcnt[0] = 0;
     p.maxcnt[1] = 0;
+    if (p.cond) atomicAdd(p.flags + 8, 1);  // builds triggered on the device (MD)
   }
 }
 
@@ -114,104 +117,161 @@ __global__ void k_scatter(NbrParams p) {
   p.cell_atoms[p.cell_start[cell] + slot] = i;
 }
 
-// the scatter order depends on atomics; sorting each cell makes rows deterministic
-__global__ void k_sort_cells(NbrParams p) {
+// The scatter order depends on atomics; sorting each cell by atom index makes
+// the rows deterministic.  One block per cell: bitonic sort in LDS (cells of
+// up to kSortMax atoms; larger ones, possible only for very thin non-periodic
+// boxes, fall back to an insertion sort by one thread).
+constexpr int kSortMax = 4096;
+
+__global__ __launch_bounds__(256) void k_sort_cells(NbrParams p) {
   if (skip(p)) return;
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p.n_cells) return;
+  __shared__ int v[kSortMax];
+  const int c = blockIdx.x;
   int* a = p.cell_atoms + p.cell_start[c];
   const int m = p.cell_count[c];
-  for (int k = 1; k < m; ++k) {
-    int v = a[k];
-    int j = k - 1;
-    while (j >= 0 && a[j] > v) {
-      a[j + 1] = a[j];
-      --j;
+  if (m <= 1) return;
+  if (m > kSortMax) {
+    if (threadIdx.x == 0) {
+      for (int k = 1; k < m; ++k) {
+        int x = a[k];
+        int j = k - 1;
+        while (j >= 0 && a[j] > x) {
+          a[j + 1] = a[j];
+          --j;
+        }
+        a[j + 1] = x;
+      }
     }
-    a[j + 1] = v;
+    return;
   }
-}
-
-// one wavefront per atom
-__global__ __launch_bounds__(256) void k_rows(NbrParams p) {
-  if (skip(p)) return;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= p.n) return;  // uniform per wave
-  const BoxInfo b = p.boxes[p.seg[i]];
-  int ci[3];
-  cell_coords(b, p.atom_cell[i], ci);
-  const double xi0 = p.pos[3 * (size_t)i], xi1 = p.pos[3 * (size_t)i + 1], xi2 = p.pos[3 * (size_t)i + 2];
-  uint32_t* row = p.nbr + (size_t)i * p.cap;
-  int count = 0, count_ang = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int oz = -1; oz <= 1; ++oz)
-      for (int oy = -1; oy <= 1; ++oy)
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int o[3] = {ox, oy, oz};
-          int w[3], s[3];
-          bool out = false;
-          for (int a = 0; a < 3; ++a) {
-            int u = ci[a] + o[a];
-            if (p.pbc[a]) {
-              s[a] = u < 0 ? -1 : (u >= b.nc[a] ? 1 : 0);
-              w[a] = u - s[a] * b.nc[a];
-            } else {
-              s[a] = 0;
-              w[a] = u;
-              out |= (u < 0 || u >= b.nc[a]);
-            }
-          }
-          if (out) continue;
-          const int cell = b.cell_base + (w[2] * b.nc[1] + w[1]) * b.nc[0] + w[0];
-          const int start = p.cell_start[cell], cnt = p.cell_count[cell];
-          const int code = (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1);
-          // canonical orientation of the self-image pair: lexicographically positive shift
-          const bool spos = s[2] > 0 || (s[2] == 0 && (s[1] > 0 || (s[1] == 0 && s[0] > 0)));
-          for (int base = 0; base < cnt; base += 64) {
-            const int k = base + lane;
-            bool take = false;
-            int q = 0;
-            if (k < cnt) {
-              q = p.cell_atoms[start + k];
-              const bool self = (q == i) && code == 13;
-              if (!self) {
-                // displacement computed from the lower-index atom, so that the
-                // entry and its reverse agree bit for bit on r^2
-                const bool iq = (i < q) || (i == q && spos);
-                const size_t ia = iq ? (size_t)i : (size_t)q;
-                const size_t ib = iq ? (size_t)q : (size_t)i;
-                const double sg = iq ? 1.0 : -1.0;
-                double d0 = p.pos[3 * ib] + sg * (double)s[0] * b.L[0] - p.pos[3 * ia];
-                double d1 = p.pos[3 * ib + 1] + sg * (double)s[1] * b.L[1] - p.pos[3 * ia + 1];
-                double d2 = p.pos[3 * ib + 2] + sg * (double)s[2] * b.L[2] - p.pos[3 * ia + 2];
-                double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                if (r2 == 0.0) atomicOr(p.flags, kFlagOverlap);
-                const bool ang = r2 < p.r_ang2;
-                take = pass == 0 ? ang : (!ang && r2 < p.r_list2);
-              }
-            }
-            const uint64_t m = __ballot(take);
-            if (take) {
-              const int at = count + __popcll(m & ((1ull << lane) - 1ull));
-              if (at < p.cap) row[at] = (uint32_t)q | ((uint32_t)code << kImgBits);
-            }
-            count += __popcll(m);
+  int pw = 2;
+  while (pw < m) pw <<= 1;
+  for (int k = threadIdx.x; k < pw; k += blockDim.x) v[k] = k < m ? a[k] : INT_MAX;
+  __syncthreads();
+  for (int size = 2; size <= pw; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int k = threadIdx.x; k < pw; k += blockDim.x) {
+        const int partner = k ^ stride;
+        if (partner > k) {
+          const bool up = (k & size) == 0;
+          const int x = v[k], y = v[partner];
+          if ((x > y) == up) {
+            v[k] = y;
+            v[partner] = x;
           }
         }
-    if (pass == 0) count_ang = count;
+      }
+      __syncthreads();
+    }
   }
-  (void)xi0;
-  (void)xi1;
-  (void)xi2;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) a[k] = v[k];
+}
+
+// One wavefront per atom.  The 27 stencil cells (unwrapped, so each
+// (cell, image) pair appears once) are flattened into one candidate stream
+// that the 64 lanes walk together; angular candidates go straight into the
+// row, the remaining ones into a scratch row that is appended at the end.
+__global__ __launch_bounds__(256) void k_rows(NbrParams p) {
+  if (skip(p)) return;
+  __shared__ int s_start[4][27], s_count[4][27], s_code[4][27], s_pref[4][28];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * (blockDim.x >> 6) + wv;
+  const bool active = i < p.n;  // waves past the end stay until the barriers
+  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
+  int ci[3] = {0, 0, 0};
+  if (active) cell_coords(b, p.atom_cell[i], ci);
+  if (lane < 27) {
+    const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+    int w[3], s[3];
+    bool out = !active;
+    for (int a = 0; a < 3; ++a) {
+      const int u = ci[a] + o[a];
+      if (p.pbc[a]) {
+        s[a] = u < 0 ? -1 : (u >= b.nc[a] ? 1 : 0);
+        w[a] = u - s[a] * b.nc[a];
+      } else {
+        s[a] = 0;
+        w[a] = u;
+        out |= (u < 0 || u >= b.nc[a]);
+      }
+    }
+    const int cell = out ? 0 : b.cell_base + (w[2] * b.nc[1] + w[1]) * b.nc[0] + w[0];
+    s_start[wv][lane] = out ? 0 : p.cell_start[cell];
+    s_count[wv][lane] = out ? 0 : p.cell_count[cell];
+    s_code[wv][lane] = (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1);
+  }
+  __syncthreads();
   if (lane == 0) {
-    if (count > p.cap || count_ang > p.cap_ang) atomicOr(p.flags, kFlagOverflow);
+    int run = 0;
+    for (int k = 0; k < 27; ++k) {
+      s_pref[wv][k] = run;
+      run += s_count[wv][k];
+    }
+    s_pref[wv][27] = run;
+  }
+  __syncthreads();
+  if (!active) return;
+  const int total = s_pref[wv][27];
+  uint32_t* row = p.nbr + (size_t)i * p.cap;
+  uint32_t* tmp = p.nbr_tmp + (size_t)i * p.cap;
+  int cnt_a = 0, cnt_r = 0;
+  int k_cell = 0;  // stencil cell of this lane's candidate (candidates advance monotonically)
+  for (int base = 0; base < total; base += 64) {
+    const int t = base + lane;
+    bool ang = false, rad = false;
+    uint32_t entry = 0;
+    if (t < total) {
+      while (k_cell < 26 && t >= s_pref[wv][k_cell + 1]) ++k_cell;
+      const int q = p.cell_atoms[s_start[wv][k_cell] + (t - s_pref[wv][k_cell])];
+      const int code = s_code[wv][k_cell];
+      const int s0 = code % 3 - 1, s1 = (code / 3) % 3 - 1, s2 = code / 9 - 1;
+      const bool self = (q == i) && code == 13;
+      if (!self) {
+        // displacement computed from the lower-index atom, so that the entry
+        // and its reverse agree bit for bit on r^2
+        const bool spos = s2 > 0 || (s2 == 0 && (s1 > 0 || (s1 == 0 && s0 > 0)));
+        const bool iq = (i < q) || (i == q && spos);
+        const size_t ia = iq ? (size_t)i : (size_t)q;
+        const size_t ib = iq ? (size_t)q : (size_t)i;
+        const double sg = iq ? 1.0 : -1.0;
+        const double d0 = p.pos[3 * ib] + sg * (double)s0 * b.L[0] - p.pos[3 * ia];
+        const double d1 = p.pos[3 * ib + 1] + sg * (double)s1 * b.L[1] - p.pos[3 * ia + 1];
+        const double d2 = p.pos[3 * ib + 2] + sg * (double)s2 * b.L[2] - p.pos[3 * ia + 2];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (r2 == 0.0) atomicOr(p.flags, kFlagOverlap);
+        ang = r2 < p.r_ang2;
+        rad = !ang && r2 < p.r_list2;
+        entry = (uint32_t)q | ((uint32_t)code << kImgBits);
+      }
+    }
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t ma = __ballot(ang), mr = __ballot(rad);
+    if (ang) {
+      const int at = cnt_a + __popcll(ma & below);
+      if (at < p.cap) row[at] = entry;
+    }
+    if (rad) {
+      const int at = cnt_r + __popcll(mr & below);
+      if (at < p.cap) tmp[at] = entry;
+    }
+    cnt_a += __popcll(ma);
+    cnt_r += __popcll(mr);
+  }
+  const int count = cnt_a + cnt_r;
+  // append the radial-only entries after the angular ones
+  for (int k = lane; k < cnt_r; k += 64) {
+    const int at = cnt_a + k;
+    if (at < p.cap && k < p.cap) row[at] = tmp[k];
+  }
+  if (lane == 0) {
+    if (count > p.cap || cnt_a > p.cap_ang) atomicOr(p.flags, kFlagOverflow);
     // clamp so that every later kernel stays inside the row even after an overflow
-    const int nang = min(count_ang, min(p.cap_ang, p.cap));
+    const int nang = min(cnt_a, min(p.cap_ang, p.cap));
     p.nnb[i] = max(min(count, p.cap), nang);
     p.nang[i] = nang;
     atomicMax(&p.maxcnt[0], count);
-    atomicMax(&p.maxcnt[1], count_ang);
+    atomicMax(&p.maxcnt[1], cnt_a);
   }
 }
 
@@ -290,7 +350,7 @@ void launch_build_neighbors(const NbrParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_bin, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, p);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(k_sort_cells, dim3(blocks_for(p.n_cells, 64)), dim3(64), 0, s, p);
+  hipLaunchKernelGGL(k_sort_cells, dim3(p.n_cells), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_rows, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_reverse, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
 }

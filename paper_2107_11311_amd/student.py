@@ -1,0 +1,208 @@
+"""Distilled student potential: data from teacher MD, training with the
+library's loss-gradient kernels, and MD with the teacher as judge and fallback.
+
+The paper shows that shrinking the descriptor of its water potential from 52
+to 20 dimensions makes MD about three times faster at some cost in accuracy
+(Sec. IV, model-complexity study).  Here the smaller network is obtained by
+distillation: it is trained on configurations, energies and forces produced by
+MD with the full network, and during production MD the full network re-checks
+the student's forces every few steps and takes over when they drift.
+
+Everything numerical runs through the C ABI (teacher MD, student energies and
+forces, the loss gradient by double back-propagation); torch only holds device
+buffers and applies the Adam update to the flat parameter vector.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Snapshots:
+    pos: "object"          # torch [S, N, 3] float64 (device)
+    forces: "object"       # torch [S, N, 3] float32 (device)
+    energy: "object"       # torch [S] float64 (device)
+    species: np.ndarray
+    box: np.ndarray
+    pbc: np.ndarray
+    seconds: float = 0.0
+
+
+def generate_snapshots(teacher, system, vel0, n_snap: int, stride: int, dt_ps: float,
+                       device="cuda:0") -> Snapshots:
+    """Runs NVE MD with the teacher context and stores every stride-th state."""
+    import torch
+    dev = torch.device(device)
+    n = system.pos.shape[0]
+    pos = torch.from_numpy(np.ascontiguousarray(system.pos, dtype=np.float64)).to(dev)
+    vel = torch.from_numpy(np.ascontiguousarray(vel0, dtype=np.float64)).to(dev)
+    P = torch.empty((n_snap, n, 3), dtype=torch.float64, device=dev)
+    Fs = torch.empty((n_snap, n, 3), dtype=torch.float32, device=dev)
+    Es = torch.empty((n_snap,), dtype=torch.float64, device=dev)
+    F = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    ep = torch.zeros(1, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    for k in range(n_snap):
+        teacher.md_step_dev(pos, vel, system.species, system.box, system.pbc, dt_ps, stride, ep, None, F)
+        P[k].copy_(pos)
+        Fs[k].copy_(F)
+        Es[k:k + 1].copy_(ep)
+    torch.cuda.synchronize()
+    return Snapshots(P, Fs, Es, system.species, system.box, system.pbc, time.perf_counter() - t0)
+
+
+@dataclass
+class TrainResult:
+    params: np.ndarray
+    losses: List[float] = field(default_factory=list)
+    seconds: float = 0.0
+    steps: int = 0
+
+
+def train(student, snaps: Snapshots, train_idx: np.ndarray, steps: int, batch: int, lr: float,
+          lambda_f: float = 1.0, seed: int = 0, lr_final: Optional[float] = None,
+          log_every: int = 0, log: Callable[[str], None] = print) -> TrainResult:
+    """Adam on mini-batches of snapshots; the gradient of the energy+force loss
+    comes from aenet_loss_grad_dev (double back-propagation on the GPU)."""
+    import torch
+    dev = snaps.pos.device
+    rng = np.random.default_rng(seed)
+    n = snaps.pos.shape[1]
+    p = torch.from_numpy(student.get_params()).to(dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    grad = torch.zeros_like(p)
+    offs = np.arange(batch + 1, dtype=np.int64) * n
+    species = np.tile(snaps.species, batch)
+    boxes = np.tile(np.asarray(snaps.box, dtype=np.float64).reshape(1, 3), (batch, 1))
+    res = TrainResult(p.cpu().numpy())
+    t0 = time.perf_counter()
+    lr_final = lr if lr_final is None else lr_final
+    for it in range(steps):
+        idx = torch.from_numpy(rng.choice(train_idx, size=batch, replace=False)).to(dev)
+        pos = snaps.pos.index_select(0, idx).reshape(batch * n, 3)
+        f_ref = snaps.forces.index_select(0, idx).reshape(batch * n, 3).to(torch.float64)
+        e_ref = snaps.energy.index_select(0, idx)
+        student.loss_grad_dev(offs, pos, species, boxes, snaps.pbc, e_ref, f_ref, lambda_f, loss, grad)
+        # Adam with a geometric learning-rate schedule
+        a = lr * (lr_final / lr) ** (it / max(steps - 1, 1))
+        m.mul_(b1).add_(grad, alpha=1 - b1)
+        v.mul_(b2).addcmul_(grad, grad, value=1 - b2)
+        mh = m / (1 - b1 ** (it + 1))
+        vh = v / (1 - b2 ** (it + 1))
+        p.add_(-a * mh / (vh.sqrt() + eps))
+        student.set_params(p.cpu().numpy())
+        if log_every and (it % log_every == 0 or it == steps - 1):
+            res.losses.append(loss.item())
+            log(f"step {it} loss {res.losses[-1]:.4e} lr {a:.2e}")
+    torch.cuda.synchronize()
+    res.params = p.cpu().numpy()
+    res.seconds = time.perf_counter() - t0
+    res.steps = steps
+    return res
+
+
+def force_rmse(ctx, snaps: Snapshots, idx) -> float:
+    """Force RMSE (eV/A) of a context against the stored teacher forces."""
+    import torch
+    dev = snaps.pos.device
+    n = snaps.pos.shape[1]
+    F = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    acc, cnt = 0.0, 0
+    for k in idx:
+        ctx.energy_forces_dev(snaps.pos[k], snaps.species, snaps.box, snaps.pbc, None, None, F)
+        d = F - snaps.forces[k].to(torch.float64)
+        acc += float((d * d).sum().item())
+        cnt += 3 * n
+    return float(np.sqrt(acc / cnt))
+
+
+@dataclass
+class JudgeReport:
+    steps: int = 0
+    chunks: int = 0
+    fallbacks: int = 0
+    rmse_per_chunk: List[float] = field(default_factory=list)
+    student_seconds: float = 0.0
+    teacher_seconds: float = 0.0
+    judge_seconds: float = 0.0
+
+
+def md_with_judge(run_student: Callable, run_teacher: Callable, teacher_forces: Callable,
+                  state, n_steps: int, every: int, threshold: float) -> JudgeReport:
+    """Production MD with a judge.
+
+    run_student(state, k) / run_teacher(state, k) advance the state by k steps
+    in place and return the forces at the final positions; teacher_forces(state)
+    evaluates the teacher there; state.save() / state.restore(snapshot) make and
+    restore a checkpoint.  Every `every` steps the student's final forces are
+    compared with the teacher's; if the RMSE exceeds `threshold` the chunk is
+    undone and redone with the teacher."""
+    rep = JudgeReport()
+    done = 0
+    while done < n_steps:
+        k = min(every, n_steps - done)
+        ckpt = state.save()
+        t0 = time.perf_counter()
+        Fs = run_student(state, k)
+        t1 = time.perf_counter()
+        Ft = teacher_forces(state)
+        t2 = time.perf_counter()
+        rmse = float(np.sqrt(np.mean((np.asarray(Fs) - np.asarray(Ft)) ** 2)))
+        rep.rmse_per_chunk.append(rmse)
+        rep.student_seconds += t1 - t0
+        rep.judge_seconds += t2 - t1
+        if not rmse <= threshold:
+            state.restore(ckpt)
+            t3 = time.perf_counter()
+            run_teacher(state, k)
+            rep.teacher_seconds += time.perf_counter() - t3
+            rep.fallbacks += 1
+        done += k
+        rep.chunks += 1
+    rep.steps = done
+    return rep
+
+
+class DeviceState:
+    """MD state on the GPU (positions, velocities) with copy checkpoints, for
+    md_with_judge driving two contexts."""
+
+    def __init__(self, system, vel, device="cuda:0"):
+        import torch
+        dev = torch.device(device)
+        self.system = system
+        self.pos = torch.from_numpy(np.ascontiguousarray(system.pos, dtype=np.float64)).to(dev)
+        self.vel = torch.from_numpy(np.ascontiguousarray(vel, dtype=np.float64)).to(dev)
+        self.F = torch.empty_like(self.pos)
+        self.ep = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.ek = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def save(self):
+        return (self.pos.clone(), self.vel.clone())
+
+    def restore(self, ck):
+        self.pos.copy_(ck[0])
+        self.vel.copy_(ck[1])
+
+    def runner(self, ctx, dt_ps):
+        def run(state, k):
+            s = state.system
+            ctx.md_step_dev(state.pos, state.vel, s.species, s.box, s.pbc, dt_ps, k, state.ep, state.ek, state.F)
+            return state.F.cpu().numpy()
+        return run
+
+    def forces(self, ctx):
+        def f(state):
+            import torch
+            s = state.system
+            F = torch.empty_like(state.pos)
+            ctx.energy_forces_dev(state.pos, s.species, s.box, s.pbc, None, None, F)
+            return F.cpu().numpy()
+        return f

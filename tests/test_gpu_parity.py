@@ -162,3 +162,39 @@ def test_empty_input(A):
     ctx = A.Context(I.load_model("water64"), "fp64")
     E, Ea, F = ctx.energy_forces(np.zeros((0, 3)), np.zeros(0, np.int32), [12.42] * 3, (1, 1, 1))
     assert E == 0.0 and Ea.size == 0 and F.size == 0
+
+
+def test_md_long_with_rebuilds(A, orc):
+    """120 steps with a small skin: many device-triggered and forced rebuilds
+    (wrap + new list) must leave the trajectory on the oracle's (which
+    rebuilds every step)."""
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 9)
+    ctx = A.Context(m, "fp64", skin=0.2)
+    ctx.set_rebuild_every(7)
+    p1, v1, ep, ek, F = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 120)
+    st = ctx.stats()
+    p0, v0, ep0, ek0, F0 = orc.md_vv(m, s.pos, v, s.species, m.masses, s.box, s.pbc, 5e-4, 120)
+    dp = float(np.abs((p1 - p0 + s.box / 2) % s.box - s.box / 2).max())
+    dv = float(np.abs(v1 - v0).max() / np.abs(v0).max())
+    de = abs(ep + ek - ep0 - ek0) / abs(ep0 + ek0)
+    print(f"md120: rebuilds={st['n_rebuilds']} dpos={dp:.3e} rel dvel={dv:.3e} rel dE={de:.3e}")
+    assert st["n_rebuilds"] > 120 // 7
+    assert dp < 1e-8, dp
+    assert dv < 1e-8, dv
+    assert de < 1e-10, de
+
+
+def test_md_resume_is_bitwise(A):
+    """100 steps == 50 steps + (positions, velocities) handed back + 50 steps."""
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 4)
+    ctx = A.Context(m, "fp64", skin=0.3)
+    ctx.set_rebuild_every(25)
+    pa, va, epa, eka, _ = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 100)
+    pb, vb, _, _, _ = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 50)
+    pb, vb, epb, ekb, _ = ctx.md_step(pb, vb, s.species, s.box, s.pbc, 5e-4, 50)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    assert epa == epb and eka == ekb

@@ -381,3 +381,21 @@ def test_loss_zero_at_reference(orc):
     E, _, F = orc.energy_forces(m, b.pos, b.species, b.box, b.pbc)
     L, grad = orc.loss_grad(m, [0, len(b.pos)], b.pos, b.species, b.box, [1, 1, 1], [E], F, 1.0)
     assert L == 0.0 and np.all(grad == 0.0)
+
+
+def test_subset_evaluation_equals_full(orc, water_small):
+    """Per-atom evaluation of selected atoms (used for sampled checks of large
+    structures) reproduces the full evaluation."""
+    m, s = water_small
+    E, Ea, F, G = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc, want_G=True)
+    sel = np.array([0, 5, 17, len(s.pos) - 1])
+    Es, Fs, Gs = orc.energy_forces_subset(m, s.pos, s.species, s.box, s.pbc, sel)
+    np.testing.assert_allclose(Es, Ea[sel], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Fs, F[sel], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Gs, G[sel], rtol=0, atol=1e-12)
+    # a box smaller than twice the cutoff (image sums)
+    s2 = I.water_box(8, 55)
+    m2 = normalised(tiny_model(S=2, nr=6, rr=6.0, na=4, ra=4.0), 12)
+    E, Ea, F = orc.energy_forces(m2, s2.pos, s2.species, s2.box, s2.pbc)
+    Es, Fs, _ = orc.energy_forces_subset(m2, s2.pos, s2.species, s2.box, s2.pbc, np.arange(len(s2.pos)))
+    np.testing.assert_allclose(Fs, F, rtol=0, atol=1e-11)
