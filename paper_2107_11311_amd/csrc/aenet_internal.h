@@ -51,7 +51,7 @@ struct NbrParams {
   int* cell_atoms;       // [n]
   int* atom_cell;        // [n]
   uint32_t* nbr;         // [n*cap]
-  uint32_t* nbr_tmp;     // [n*cap] scratch rows
+  uint32_t* key;         // [n*cap] search keys (stencil cell << 27 | atom), sorted per row part
   int* nnb;              // [n]
   int* nang;             // [n]
   int* rev;              // [n*cap] global index of the reverse entry
@@ -73,7 +73,7 @@ struct DescParams {
   const int* nnb;
   const int* nang;
   int cap, cap_ang;
-  int max_ang;           // largest angular prefix seen at the last checked build (tuning only)
+  int ang_hint;          // expected largest angular shell within R_a (tuning only)
   double rr, ra;
   double tw[kMaxSpecies];
   int weighted;          // n_species > 1

@@ -35,13 +35,6 @@ __device__ inline uint64_t group_ballot(bool pred) {
 }
 
 template <typename R>
-__device__ inline void sincos_r(R x, R* s, R* c);
-template <>
-__device__ inline void sincos_r<double>(double x, double* s, double* c) { sincos(x, s, c); }
-template <>
-__device__ inline void sincos_r<float>(float x, float* s, float* c) { sincosf(x, s, c); }
-
-template <typename R>
 __device__ inline R sqrt_r(R x);
 template <>
 __device__ inline double sqrt_r<double>(double x) { return sqrt(x); }
@@ -49,6 +42,71 @@ template <>
 __device__ inline float sqrt_r<float>(float x) { return sqrtf(x); }
 
 constexpr double kPi = 3.14159265358979323846;
+
+// sin t and cos t for |t| <= pi/2 by their Taylor series in nested (Horner)
+// form; truncation below 1e-19 (double: terms to t^23 / t^24) or 1e-9
+// (float: terms to t^15 / t^14), i.e. under the rounding error of each type.
+template <typename R>
+__device__ inline void sincos_halfpi(R t, R* s, R* c);
+template <>
+__device__ inline void sincos_halfpi<double>(double t, double* s, double* c) {
+  const double u = t * t;
+  double a = 1.0 - u * (1.0 / 506.0);
+  a = 1.0 - u * (1.0 / 420.0) * a;
+  a = 1.0 - u * (1.0 / 342.0) * a;
+  a = 1.0 - u * (1.0 / 272.0) * a;
+  a = 1.0 - u * (1.0 / 210.0) * a;
+  a = 1.0 - u * (1.0 / 156.0) * a;
+  a = 1.0 - u * (1.0 / 110.0) * a;
+  a = 1.0 - u * (1.0 / 72.0) * a;
+  a = 1.0 - u * (1.0 / 42.0) * a;
+  a = 1.0 - u * (1.0 / 20.0) * a;
+  a = 1.0 - u * (1.0 / 6.0) * a;
+  *s = t * a;
+  double b = 1.0 - u * (1.0 / 552.0);
+  b = 1.0 - u * (1.0 / 462.0) * b;
+  b = 1.0 - u * (1.0 / 380.0) * b;
+  b = 1.0 - u * (1.0 / 306.0) * b;
+  b = 1.0 - u * (1.0 / 240.0) * b;
+  b = 1.0 - u * (1.0 / 182.0) * b;
+  b = 1.0 - u * (1.0 / 132.0) * b;
+  b = 1.0 - u * (1.0 / 90.0) * b;
+  b = 1.0 - u * (1.0 / 56.0) * b;
+  b = 1.0 - u * (1.0 / 30.0) * b;
+  b = 1.0 - u * (1.0 / 12.0) * b;
+  *c = 1.0 - u * 0.5 * b;
+}
+template <>
+__device__ inline void sincos_halfpi<float>(float t, float* s, float* c) {
+  const float u = t * t;
+  float a = 1.0f - u * (1.0f / 210.0f);
+  a = 1.0f - u * (1.0f / 156.0f) * a;
+  a = 1.0f - u * (1.0f / 110.0f) * a;
+  a = 1.0f - u * (1.0f / 72.0f) * a;
+  a = 1.0f - u * (1.0f / 42.0f) * a;
+  a = 1.0f - u * (1.0f / 20.0f) * a;
+  a = 1.0f - u * (1.0f / 6.0f) * a;
+  *s = t * a;
+  float b = 1.0f - u * (1.0f / 182.0f);
+  b = 1.0f - u * (1.0f / 132.0f) * b;
+  b = 1.0f - u * (1.0f / 90.0f) * b;
+  b = 1.0f - u * (1.0f / 56.0f) * b;
+  b = 1.0f - u * (1.0f / 30.0f) * b;
+  b = 1.0f - u * (1.0f / 12.0f) * b;
+  *c = 1.0f - u * 0.5f * b;
+}
+
+// sin and cos of pi r / R for 0 <= r < R (the cosine cutoff, Eq. 5): with
+// x = 2r/R - 1 in [-1, 1) and t = pi x / 2, pi r / R = t + pi/2, so
+// sin(pi r/R) = cos t and cos(pi r/R) = -sin t.
+template <typename R>
+__device__ inline void sincos_cut(R r, R two_over_R, R* sn, R* cs) {
+  const R t = R(0.5 * kPi) * (r * two_over_R - R(1));
+  R st, ct;
+  sincos_halfpi<R>(t, &st, &ct);
+  *sn = ct;
+  *cs = -st;
+}
 
 // displacement d = r_j + s L - r_i of a packed entry (always in double)
 __device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double xi0, double xi1,
@@ -91,6 +149,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
   const int na = active ? p.nang[i] : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
   const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+  const R two_ra = R(2.0 / p.ra);
 
   // radial terms, Eq. 3
   for (int e = l; e < nn; e += LPA) {
@@ -101,7 +160,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
       const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
       const R x = r * inv_rr2 - R(1);
       R sn, cs;
-      sincos_r<R>(r * pi_rr, &sn, &cs);
+      sincos_cut<R>(r, inv_rr2, &sn, &cs);
       const R fc = R(0.5) * (cs + R(1));
       const R wf = R(p.tw[p.species[q]]) * fc;
       R t0 = R(1), t1 = x;
@@ -136,7 +195,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
         vy = R(d1) * ir;
         vz = R(d2) * ir;
         R sn, cs;
-        sincos_r<R>(r * pi_ra, &sn, &cs);
+        sincos_cut<R>(r, two_ra, &sn, &cs);
         vf = R(0.5) * (cs + R(1));
         vw = R(p.tw[p.species[q]]);
       }
@@ -242,6 +301,7 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
   const int na = active ? p.nang[i] : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
   const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+  const R two_ra = R(2.0 / p.ra);
   const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)(active ? i : 0) * p.ldG;
   constexpr int T1 = NR + 1, T2 = NR + NA + 2;
 
@@ -263,7 +323,7 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
         vy = R(d1) * vri;
         vz = R(d2) * vri;
         R sn, cs;
-        sincos_r<R>(r * pi_ra, &sn, &cs);
+        sincos_cut<R>(r, two_ra, &sn, &cs);
         vf = R(0.5) * (cs + R(1));
         vfp = R(-0.5) * pi_ra * sn;
         vw = R(p.tw[p.species[q]]);
@@ -354,7 +414,7 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
       const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
       const R x = r * inv_rr2 - R(1);
       R sn, cs;
-      sincos_r<R>(r * pi_rr, &sn, &cs);
+      sincos_cut<R>(r, inv_rr2, &sn, &cs);
       const R fc = R(0.5) * (cs + R(1));
       const R fcp = R(-0.5) * pi_rr * sn;
       R t0 = R(1), t1 = x, u0 = R(1), u1 = R(2) * x;
@@ -444,6 +504,7 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
   const int na = active ? p.nang[i] : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
   const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+  const R two_ra = R(2.0 / p.ra);
 
   for (int e = l; e < nn; e += LPA) {
     double d0, d1, d2;
@@ -456,7 +517,7 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
                       dz * R(p.adj[3 * (size_t)q + 2] - ai2)) / r;
       const R x = r * inv_rr2 - R(1);
       R sn, cs;
-      sincos_r<R>(r * pi_rr, &sn, &cs);
+      sincos_cut<R>(r, inv_rr2, &sn, &cs);
       const R fc = R(0.5) * (cs + R(1));
       const R fcp = R(-0.5) * pi_rr * sn;
       const R w = R(p.tw[p.species[q]]);
@@ -499,7 +560,7 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
         dz_ = R(p.adj[3 * (size_t)q + 2] - ai2);
         vpa = vx * dx_ + vy * dy_ + vz * dz_;
         R sn, cs;
-        sincos_r<R>(r * pi_ra, &sn, &cs);
+        sincos_cut<R>(r, two_ra, &sn, &cs);
         vf = R(0.5) * (cs + R(1));
         vfd = R(-0.5) * pi_ra * sn * vpa;
         vw = R(p.tw[p.species[q]]);
@@ -613,12 +674,12 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
 
 template <typename R, int NR, int NA>
 void launch_orders(int kind, const DescParams& p, hipStream_t s) {
-  // Lanes per atom from the angular shell seen at the last build: narrow groups
-  // keep the cross-lane reductions short for sparse shells (water: ~30 angular
-  // neighbours), wide ones give crowded shells (dense amorphous: ~110) enough
-  // lanes.  The backward pass gives one lane per angular entry.
-  const int na = p.max_ang > 0 ? p.max_ang : p.cap_ang;
-  if (na > 64) {
+  // Lanes per atom from the expected number of angular neighbours within R_a:
+  // narrow groups keep the cross-lane reductions short for sparse shells
+  // (water: ~30), wide ones give crowded shells (dense amorphous: ~110)
+  // enough lanes.  The backward pass gives one lane per angular entry.
+  const int na = p.ang_hint > 0 ? p.ang_hint : p.cap_ang;
+  if (na > 48) {
     launch_kind<R, NR, NA, 64>(kind, p, s);
   } else if (kind == BWD) {
     if (na > 32)

@@ -78,7 +78,7 @@ struct aenet_ctx {
   DevMem d_perm, d_species, d_seg, d_segoff, d_segcount, d_boxes;
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
       d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
-  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_nbr_tmp, d_nnb, d_nang, d_rev;
+  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_key, d_nnb, d_nang, d_rev;
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
 
@@ -343,7 +343,7 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
 aenet_status ensure_rows(aenet_ctx* c) {
   const size_t nb = (size_t)std::max<int64_t>(c->n, 1);
   TRY(ensure(c, c->d_nbr, nb * c->cap * 4));
-  TRY(ensure(c, c->d_nbr_tmp, nb * c->cap * 4));
+  TRY(ensure(c, c->d_key, nb * c->cap * 4));
   TRY(ensure(c, c->d_rev, nb * c->cap * 4));
   TRY(ensure(c, c->d_pg, nb * c->cap * 3 * real_size(c)));
   return AENET_OK;
@@ -368,7 +368,7 @@ NbrParams nbr_params(aenet_ctx* c, const int* cond) {
   p.cell_atoms = c->d_cell_atoms.as<int>();
   p.atom_cell = c->d_atom_cell.as<int>();
   p.nbr = c->d_nbr.as<uint32_t>();
-  p.nbr_tmp = c->d_nbr_tmp.as<uint32_t>();
+  p.key = c->d_key.as<uint32_t>();
   p.nnb = c->d_nnb.as<int>();
   p.nang = c->d_nang.as<int>();
   p.rev = c->d_rev.as<int>();
@@ -390,7 +390,11 @@ DescParams desc_params(aenet_ctx* c) {
   p.nang = c->d_nang.as<int>();
   p.cap = c->cap;
   p.cap_ang = c->cap_ang;
-  p.max_ang = std::min(c->stats.max_angular, c->cap_ang);
+  {
+    // the build counts entries within R_a + skin; scale to the shell within R_a
+    const double f = c->ra / (c->ra + c->skin);
+    p.ang_hint = (int)(std::min(c->stats.max_angular, c->cap_ang) * f * f * f + 0.5);
+  }
   p.rr = c->rr;
   p.ra = c->ra;
   for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];

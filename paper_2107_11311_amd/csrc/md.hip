@@ -123,7 +123,7 @@ __global__ void k_vv_drift(int n, double* pos, double* vel, const double* F, con
     const double dd = x - pos_ref[k];
     d2 += dd * dd;
   }
-  if (!(d2 <= half_skin2)) *rebuild_flag = 1;
+  if (!(d2 <= half_skin2) && *rebuild_flag == 0) *rebuild_flag = 1;
 }
 
 constexpr int kRedChunk = 2048;  // elements per partial sum (fixed: results depend only on n)

@@ -174,14 +174,16 @@ __global__ __launch_bounds__(256) void k_sort_cells(NbrParams p) {
 __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
   if (skip(p)) return;
   __shared__ int s_start[4][27], s_count[4][27], s_code[4][27], s_pref[4][28];
+  extern __shared__ uint32_t s_rad[];  // per wave: radial-only entries, then their keys
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int i = blockIdx.x * (blockDim.x >> 6) + wv;
-  const bool active = i < p.n;  // waves past the end stay until the barriers
+  const bool active = i < p.n;  // waves past the end stay for the barriers
   const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
   int ci[3] = {0, 0, 0};
   if (active) cell_coords(b, p.atom_cell[i], ci);
   if (lane < 27) {
+    // stencil cell `lane` = offset (lane%3-1, lane/3%3-1, lane/9-1), in unwrapped coordinates
     const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
     int w[3], s[3];
     bool out = !active;
@@ -211,16 +213,18 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
     s_pref[wv][27] = run;
   }
   __syncthreads();
-  if (!active) return;
   const int total = s_pref[wv][27];
-  uint32_t* row = p.nbr + (size_t)i * p.cap;
-  uint32_t* tmp = p.nbr_tmp + (size_t)i * p.cap;
+  const size_t rbase = (size_t)(active ? i : 0) * p.cap;
+  uint32_t* row = p.nbr + rbase;
+  uint32_t* key = p.key + rbase;
+  uint32_t* rad_e = s_rad + (size_t)wv * 2 * p.cap;
+  uint32_t* rad_k = rad_e + p.cap;
   int cnt_a = 0, cnt_r = 0;
   int k_cell = 0;  // stencil cell of this lane's candidate (candidates advance monotonically)
   for (int base = 0; base < total; base += 64) {
     const int t = base + lane;
     bool ang = false, rad = false;
-    uint32_t entry = 0;
+    uint32_t entry = 0, ekey = 0;
     if (t < total) {
       while (k_cell < 26 && t >= s_pref[wv][k_cell + 1]) ++k_cell;
       const int q = p.cell_atoms[s_start[wv][k_cell] + (t - s_pref[wv][k_cell])];
@@ -243,72 +247,65 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
         ang = r2 < p.r_ang2;
         rad = !ang && r2 < p.r_list2;
         entry = (uint32_t)q | ((uint32_t)code << kImgBits);
+        // search key of the entry: (stencil cell, atom); rows are sorted by it
+        ekey = (uint32_t)q | ((uint32_t)k_cell << kImgBits);
       }
     }
     const uint64_t below = (1ull << lane) - 1ull;
     const uint64_t ma = __ballot(ang), mr = __ballot(rad);
     if (ang) {
       const int at = cnt_a + __popcll(ma & below);
-      if (at < p.cap) row[at] = entry;
+      if (at < p.cap) {
+        row[at] = entry;
+        key[at] = ekey;
+      }
     }
     if (rad) {
       const int at = cnt_r + __popcll(mr & below);
-      if (at < p.cap) tmp[at] = entry;
+      if (at < p.cap) {
+        rad_e[at] = entry;
+        rad_k[at] = ekey;
+      }
     }
     cnt_a += __popcll(ma);
     cnt_r += __popcll(mr);
   }
-  const int count = cnt_a + cnt_r;
+  __syncthreads();
   // append the radial-only entries after the angular ones
   for (int k = lane; k < cnt_r; k += 64) {
     const int at = cnt_a + k;
-    if (at < p.cap && k < p.cap) row[at] = tmp[k];
+    if (at < p.cap && k < p.cap) {
+      row[at] = rad_e[k];
+      key[at] = rad_k[k];
+    }
   }
-  if (lane == 0) {
+  if (active && lane == 0) {
+    const int count = cnt_a + cnt_r;
     if (count > p.cap || cnt_a > p.cap_ang) atomicOr(p.flags, kFlagOverflow);
     // clamp so that every later kernel stays inside the row even after an overflow
     const int nang = min(cnt_a, min(p.cap_ang, p.cap));
     p.nnb[i] = max(min(count, p.cap), nang);
     p.nang[i] = nang;
-    atomicMax(&p.maxcnt[0], count);
-    atomicMax(&p.maxcnt[1], cnt_a);
+    // maxima for capacity planning; the plain read first keeps the atomics rare
+    if (count > p.maxcnt[0]) atomicMax(&p.maxcnt[0], count);
+    if (cnt_a > p.maxcnt[1]) atomicMax(&p.maxcnt[1], cnt_a);
   }
 }
 
-__device__ inline uint32_t entry_key(const NbrParams& p, const BoxInfo& b, const int cc[3],
-                                     uint32_t en) {
-  const int x = (int)(en & kAtomMask);
-  const int code = (int)(en >> kImgBits);
-  const int s[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
-  int cx[3];
-  cell_coords(b, p.atom_cell[x], cx);
-  int o[3];
-  for (int a = 0; a < 3; ++a) o[a] = cx[a] - cc[a] + s[a] * b.nc[a];
-  return ((uint32_t)stencil_index(o[0], o[1], o[2]) << kImgBits) | (uint32_t)x;
-}
-
-// reverse entry of every row entry, one wavefront per atom
+// reverse entry of every row entry, one wavefront per atom: the reverse of
+// (i -> q) found in stencil cell k of i is (q -> i) in stencil cell 26 - k of q
 __global__ __launch_bounds__(256) void k_reverse(NbrParams p) {
   if (skip(p)) return;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= p.n) return;
-  const BoxInfo b = p.boxes[p.seg[i]];
-  int ci[3];
-  cell_coords(b, p.atom_cell[i], ci);
   const int nn = p.nnb[i], na = p.nang[i];
-  const uint32_t* row = p.nbr + (size_t)i * p.cap;
+  const uint32_t* krow = p.key + (size_t)i * p.cap;
   for (int e = lane; e < nn; e += 64) {
-    const uint32_t en = row[e];
-    const int q = (int)(en & kAtomMask);
-    const int code = (int)(en >> kImgBits);
-    const int s[3] = {code % 3 - 1, (code / 3) % 3 - 1, code / 9 - 1};
-    int cq[3];
-    cell_coords(b, p.atom_cell[q], cq);
-    int o[3];
-    for (int a = 0; a < 3; ++a) o[a] = cq[a] - ci[a] + s[a] * b.nc[a];
-    const uint32_t key = ((uint32_t)stencil_index(-o[0], -o[1], -o[2]) << kImgBits) | (uint32_t)i;
-    const uint32_t* rq = p.nbr + (size_t)q * p.cap;
+    const uint32_t k = krow[e];
+    const int q = (int)(k & kAtomMask);
+    const uint32_t target = ((26u - (k >> kImgBits)) << kImgBits) | (uint32_t)i;
+    const uint32_t* kq = p.key + (size_t)q * p.cap;
     int lo, hi;
     if (e < na) {
       lo = 0;
@@ -320,12 +317,12 @@ __global__ __launch_bounds__(256) void k_reverse(NbrParams p) {
     int found = -1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      const uint32_t km = entry_key(p, b, cq, rq[mid]);
-      if (km == key) {
+      const uint32_t km = kq[mid];
+      if (km == target) {
         found = mid;
         break;
       }
-      if (km < key) lo = mid + 1; else hi = mid;
+      if (km < target) lo = mid + 1; else hi = mid;
     }
     if (found < 0) {
       atomicOr(p.flags, kFlagReverse);
@@ -351,7 +348,7 @@ void launch_build_neighbors(const NbrParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, p);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_sort_cells, dim3(p.n_cells), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(k_rows, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_rows, dim3(blocks_for(p.n, 4)), dim3(256), (size_t)4 * 2 * p.cap * sizeof(uint32_t), s, p);
   hipLaunchKernelGGL(k_reverse, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
 }
 
