@@ -120,6 +120,31 @@ __device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double x
   return q;
 }
 
+// A neighbour entry with its atom's position loaded (issued one loop
+// iteration ahead of its use so the gather latency hides behind the
+// arithmetic of the current iteration).
+struct NbrLoad {
+  int q, code;
+  double x, y, z;
+};
+
+__device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t w) {
+  NbrLoad n;
+  n.q = (int)(w & kAtomMask);
+  n.code = (int)(w >> kImgBits);
+  n.x = p.pos[3 * (size_t)n.q];
+  n.y = p.pos[3 * (size_t)n.q + 1];
+  n.z = p.pos[3 * (size_t)n.q + 2];
+  return n;
+}
+
+__device__ inline void nbr_disp(const NbrLoad& n, const BoxInfo& b, double xi0, double xi1, double xi2,
+                                double& d0, double& d1, double& d2) {
+  d0 = n.x + (double)(n.code % 3 - 1) * b.L[0] - xi0;
+  d1 = n.y + (double)((n.code / 3) % 3 - 1) * b.L[1] - xi1;
+  d2 = n.z + (double)(n.code / 9 - 1) * b.L[2] - xi2;
+}
+
 // ------------------------------------------------------------------ forward
 template <typename R, int NR, int NA, int LPA>
 __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
@@ -151,29 +176,51 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
   const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
   const R two_ra = R(2.0 / p.ra);
 
-  // radial terms, Eq. 3
-  for (int e = l; e < nn; e += LPA) {
-    double d0, d1, d2;
-    const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
-    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    if (r2 < rr2) {
-      const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
-      const R x = r * inv_rr2 - R(1);
-      R sn, cs;
-      sincos_cut<R>(r, inv_rr2, &sn, &cs);
-      const R fc = R(0.5) * (cs + R(1));
-      const R wf = R(p.tw[p.species[q]]) * fc;
-      R t0 = R(1), t1 = x;
-      rt[0] += fc;
-      rw[0] += wf;
+  // radial terms, Eq. 3.  Two entries per lane per iteration give two
+  // independent recurrence chains; entries beyond R_r (skin) or past the end
+  // of the row are computed with weight 0 instead of branching.
+  // slots past the end of the row repeat its last entry (an empty row reads the
+  // atom itself, always in bounds) and are given weight 0
+  const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
+  auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
+  NbrLoad na_ = load_nbr(p, word(l)), nb_ = load_nbr(p, word(l + LPA));
+  uint32_t wa1 = word(l + 2 * LPA), wb1 = word(l + 3 * LPA);
+  for (int e = l; e < nn; e += 2 * LPA) {
+    const NbrLoad na1 = load_nbr(p, wa1), nb1 = load_nbr(p, wb1);
+    const uint32_t wa2 = word(e + 4 * LPA), wb2 = word(e + 5 * LPA);
+    const bool hb = e + LPA < nn;
+    double a0, a1, a2, b0, b1, b2;
+    nbr_disp(na_, b, xi0, xi1, xi2, a0, a1, a2);
+    nbr_disp(nb_, b, xi0, xi1, xi2, b0, b1, b2);
+    const int qa = na_.q, qb = nb_.q;
+    na_ = na1;
+    nb_ = nb1;
+    wa1 = wa2;
+    wb1 = wb2;
+    const bool va = a0 * a0 + a1 * a1 + a2 * a2 < rr2;
+    const bool vb = hb && (b0 * b0 + b1 * b1 + b2 * b2 < rr2);
+    const R ra = sqrt_r<R>(R(a0) * R(a0) + R(a1) * R(a1) + R(a2) * R(a2));
+    const R rb = sqrt_r<R>(R(b0) * R(b0) + R(b1) * R(b1) + R(b2) * R(b2));
+    const R xa = ra * inv_rr2 - R(1), xb = rb * inv_rr2 - R(1);
+    R sna, csa, snb, csb;
+    sincos_cut<R>(ra, inv_rr2, &sna, &csa);
+    sincos_cut<R>(rb, inv_rr2, &snb, &csb);
+    const R fa = va ? R(0.5) * (csa + R(1)) : R(0);
+    const R fb = vb ? R(0.5) * (csb + R(1)) : R(0);
+    const R wa = R(p.tw[p.species[qa]]) * fa, wb = R(p.tw[p.species[qb]]) * fb;
+    R ta0 = R(1), ta1 = xa, tb0 = R(1), tb1 = xb;
+    rt[0] += fa + fb;
+    rw[0] += wa + wb;
 #pragma unroll
-      for (int a = 1; a <= NR; ++a) {
-        rt[a] += t1 * fc;
-        rw[a] += t1 * wf;
-        const R t2 = R(2) * x * t1 - t0;
-        t0 = t1;
-        t1 = t2;
-      }
+    for (int a = 1; a <= NR; ++a) {
+      rt[a] += ta1 * fa + tb1 * fb;
+      rw[a] += ta1 * wa + tb1 * wb;
+      const R ta2 = R(2) * xa * ta1 - ta0;
+      const R tb2 = R(2) * xb * tb1 - tb0;
+      ta0 = ta1;
+      ta1 = ta2;
+      tb0 = tb1;
+      tb1 = tb2;
     }
   }
 
@@ -213,7 +260,8 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
   }
   __syncthreads();
 
-  // angular terms, Eq. 6: unordered pairs j < k, lanes strided over the pair index
+  // angular terms, Eq. 6: unordered pairs j < k, lanes strided over the pair
+  // index, two pairs per iteration (the second with weight 0 past the end)
   if (nv >= 2) {
     int j = 0, rem = l;
     while (j < nv - 1 && rem >= nv - 1 - j) {
@@ -222,21 +270,35 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
     }
     int k = j + 1 + rem;
     while (j < nv - 1) {
-      const R c = ux[j] * ux[k] + uy[j] * uy[k] + uz[j] * uz[k];
-      const R ff = fs[j] * fs[k];
-      const R wf = ws[j] * ws[k] * ff;
-      R t0 = R(1), t1 = c;
-      at[0] += ff;
-      aw[0] += wf;
+      int j2 = j, k2 = k + LPA;
+      while (j2 < nv - 1 && k2 >= nv) {
+        k2 = k2 - nv + j2 + 2;
+        ++j2;
+      }
+      const bool v2 = j2 < nv - 1;
+      const int jb = v2 ? j2 : j, kb = v2 ? k2 : k;
+      const R ca = ux[j] * ux[k] + uy[j] * uy[k] + uz[j] * uz[k];
+      const R cb = ux[jb] * ux[kb] + uy[jb] * uy[kb] + uz[jb] * uz[kb];
+      const R fa = fs[j] * fs[k];
+      const R fb = v2 ? fs[jb] * fs[kb] : R(0);
+      const R wa = ws[j] * ws[k] * fa, wb = ws[jb] * ws[kb] * fb;
+      R ta0 = R(1), ta1 = ca, tb0 = R(1), tb1 = cb;
+      at[0] += fa + fb;
+      aw[0] += wa + wb;
 #pragma unroll
       for (int a = 1; a <= NA; ++a) {
-        at[a] += t1 * ff;
-        aw[a] += t1 * wf;
-        const R t2 = R(2) * c * t1 - t0;
-        t0 = t1;
-        t1 = t2;
+        at[a] += ta1 * fa + tb1 * fb;
+        aw[a] += ta1 * wa + tb1 * wb;
+        const R ta2 = R(2) * ca * ta1 - ta0;
+        const R tb2 = R(2) * cb * tb1 - tb0;
+        ta0 = ta1;
+        ta1 = ta2;
+        tb0 = tb1;
+        tb1 = tb2;
       }
-      k += LPA;
+      if (!v2) break;
+      j = j2;
+      k = k2 + LPA;
       while (j < nv - 1 && k >= nv) {
         k = k - nv + j + 2;
         ++j;
@@ -358,33 +420,53 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
     for (int k = l; k < nv; k += LPA) {
       const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
       R ax = 0, ay = 0, az = 0;
-      for (int j = 0; j < nv; ++j) {
-        if (j == k) continue;
-        const R jx = ux[j], jy = uy[j], jz = uz[j];
-        const R c = jx * kx + jy * ky + jz * kz;
+      // two partners per iteration (independent chains); j == k and the slot
+      // past the end are computed with weight 0
+      for (int j = 0; j < nv; j += 2) {
+        const int jb = j + 1 < nv ? j + 1 : j;
+        const R ma = j != k ? R(1) : R(0);
+        const R mb = (j + 1 < nv && j + 1 != k) ? R(1) : R(0);
+        const R jax = ux[j], jay = uy[j], jaz = uz[j];
+        const R jbx = ux[jb], jby = uy[jb], jbz = uz[jb];
+        const R c1 = jax * kx + jay * ky + jaz * kz;
+        const R c2 = jbx * kx + jby * ky + jbz * kz;
         // sum_a coef_a T_a(c) and sum_a coef_a T_a'(c), T_a' = a U_{a-1}
-        R t0 = R(1), t1 = c, u0 = R(1), u1 = R(2) * c;
+        R t0 = R(1), t1 = c1, u0 = R(1), u1 = R(2) * c1;
+        R s0 = R(1), s1 = c2, v0 = R(1), v1 = R(2) * c2;
         R At = ga[0], Aw = gw[0], Bt = R(0), Bw = R(0);
+        R Ct = ga[0], Cw = gw[0], Dt = R(0), Dw = R(0);
 #pragma unroll
         for (int a = 1; a <= NA; ++a) {
           At += ga[a] * t1;
           Aw += gw[a] * t1;
           Bt += da[a] * u0;
           Bw += dw[a] * u0;
-          const R t2 = R(2) * c * t1 - t0;
+          Ct += ga[a] * s1;
+          Cw += gw[a] * s1;
+          Dt += da[a] * v0;
+          Dw += dw[a] * v0;
+          const R t2 = R(2) * c1 * t1 - t0;
           t0 = t1;
           t1 = t2;
-          const R u2 = R(2) * c * u1 - u0;
+          const R u2 = R(2) * c1 * u1 - u0;
           u0 = u1;
           u1 = u2;
+          const R s2 = R(2) * c2 * s1 - s0;
+          s0 = s1;
+          s1 = s2;
+          const R v2 = R(2) * c2 * v1 - v0;
+          v0 = v1;
+          v1 = v2;
         }
-        const R ww = ws[j] * wk;
-        const R A = At + ww * Aw, B = Bt + ww * Bw;
-        const R fj = fs[j];
-        const R cb = B * fj * fk * rik, ca_ = A * fj * fpk;
-        ax += cb * (jx - c * kx) + ca_ * kx;
-        ay += cb * (jy - c * ky) + ca_ * ky;
-        az += cb * (jz - c * kz) + ca_ * kz;
+        const R wwa = ws[j] * wk, wwb = ws[jb] * wk;
+        const R A1 = At + wwa * Aw, B1 = Bt + wwa * Bw;
+        const R A2 = Ct + wwb * Cw, B2 = Dt + wwb * Dw;
+        const R fja = fs[j] * ma, fjb = fs[jb] * mb;
+        const R cb1 = B1 * fja * fk * rik, ca1 = A1 * fja * fpk;
+        const R cb2 = B2 * fjb * fk * rik, ca2 = A2 * fjb * fpk;
+        ax += cb1 * (jax - c1 * kx) + ca1 * kx + cb2 * (jbx - c2 * kx) + ca2 * kx;
+        ay += cb1 * (jay - c1 * ky) + ca1 * ky + cb2 * (jby - c2 * ky) + ca2 * ky;
+        az += cb1 * (jaz - c1 * kz) + ca1 * kz + cb2 * (jbz - c2 * kz) + ca2 * kz;
       }
       gx[k] = R(2) * ax;
       gy[k] = R(2) * ay;
@@ -404,55 +486,98 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
   }
   R* pg = reinterpret_cast<R*>(p.pg) + (size_t)(active ? i : 0) * p.cap * 3;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  for (int e = l; e < nn; e += LPA) {
-    double d0, d1, d2;
-    const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
-    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    R px = 0, py = 0, pz = 0;
-    if (r2 < rr2) {
-      const R dx = R(d0), dy = R(d1), dz = R(d2);
-      const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
-      const R x = r * inv_rr2 - R(1);
-      R sn, cs;
-      sincos_cut<R>(r, inv_rr2, &sn, &cs);
-      const R fc = R(0.5) * (cs + R(1));
-      const R fcp = R(-0.5) * pi_rr * sn;
-      R t0 = R(1), t1 = x, u0 = R(1), u1 = R(2) * x;
-      R St = grt[0], Sw = grw[0], Dt = R(0), Dw = R(0);
+  // two entries per lane per iteration (independent chains); entries beyond
+  // R_r get a zero radial gradient through a zero weight
+  const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
+  auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
+  NbrLoad na_ = load_nbr(p, word(l)), nb_ = load_nbr(p, word(l + LPA));
+  uint32_t wa1 = word(l + 2 * LPA), wb1 = word(l + 3 * LPA);
+  for (int e = l; e < nn; e += 2 * LPA) {
+    const NbrLoad na1 = load_nbr(p, wa1), nb1 = load_nbr(p, wb1);
+    const uint32_t wa2 = word(e + 4 * LPA), wb2 = word(e + 5 * LPA);
+    const bool hb = e + LPA < nn;
+    const int eb = hb ? e + LPA : e;
+    double a0, a1, a2, b0, b1, b2;
+    nbr_disp(na_, b, xi0, xi1, xi2, a0, a1, a2);
+    nbr_disp(nb_, b, xi0, xi1, xi2, b0, b1, b2);
+    const int qa = na_.q, qb = nb_.q;
+    na_ = na1;
+    nb_ = nb1;
+    wa1 = wa2;
+    wb1 = wb2;
+    const R ma = (a0 * a0 + a1 * a1 + a2 * a2 < rr2) ? R(1) : R(0);
+    const R mb = (hb && b0 * b0 + b1 * b1 + b2 * b2 < rr2) ? R(1) : R(0);
+    const R dax = R(a0), day = R(a1), daz = R(a2), dbx = R(b0), dby = R(b1), dbz = R(b2);
+    const R ra = sqrt_r<R>(dax * dax + day * day + daz * daz);
+    const R rb = sqrt_r<R>(dbx * dbx + dby * dby + dbz * dbz);
+    const R xa = ra * inv_rr2 - R(1), xb = rb * inv_rr2 - R(1);
+    R sna, csa, snb, csb;
+    sincos_cut<R>(ra, inv_rr2, &sna, &csa);
+    sincos_cut<R>(rb, inv_rr2, &snb, &csb);
+    const R fca = R(0.5) * (csa + R(1)), fcpa = R(-0.5) * pi_rr * sna;
+    const R fcb = R(0.5) * (csb + R(1)), fcpb = R(-0.5) * pi_rr * snb;
+    R ta0 = R(1), ta1 = xa, ua0 = R(1), ua1 = R(2) * xa;
+    R tb0 = R(1), tb1 = xb, ub0 = R(1), ub1 = R(2) * xb;
+    R Sat = grt[0], Saw = grw[0], Dat = R(0), Daw = R(0);
+    R Sbt = grt[0], Sbw = grw[0], Dbt = R(0), Dbw = R(0);
 #pragma unroll
-      for (int a = 1; a <= NR; ++a) {
-        St += grt[a] * t1;
-        Sw += grw[a] * t1;
-        Dt += drt[a] * u0;
-        Dw += drw[a] * u0;
-        const R t2 = R(2) * x * t1 - t0;
-        t0 = t1;
-        t1 = t2;
-        const R u2 = R(2) * x * u1 - u0;
-        u0 = u1;
-        u1 = u2;
-      }
-      const R w = R(p.tw[p.species[q]]);
-      const R dEdr = (Dt + w * Dw) * inv_rr2 * fc + (St + w * Sw) * fcp;
-      const R s = dEdr / r;
-      px = s * dx;
-      py = s * dy;
-      pz = s * dz;
+    for (int a = 1; a <= NR; ++a) {
+      Sat += grt[a] * ta1;
+      Saw += grw[a] * ta1;
+      Dat += drt[a] * ua0;
+      Daw += drw[a] * ua0;
+      Sbt += grt[a] * tb1;
+      Sbw += grw[a] * tb1;
+      Dbt += drt[a] * ub0;
+      Dbw += drw[a] * ub0;
+      const R ta2 = R(2) * xa * ta1 - ta0;
+      ta0 = ta1;
+      ta1 = ta2;
+      const R ua2 = R(2) * xa * ua1 - ua0;
+      ua0 = ua1;
+      ua1 = ua2;
+      const R tb2 = R(2) * xb * tb1 - tb0;
+      tb0 = tb1;
+      tb1 = tb2;
+      const R ub2 = R(2) * xb * ub1 - ub0;
+      ub0 = ub1;
+      ub1 = ub2;
     }
+    const R wa = R(p.tw[p.species[qa]]), wb = R(p.tw[p.species[qb]]);
+    const R sa = ma * ((Dat + wa * Daw) * inv_rr2 * fca + (Sat + wa * Saw) * fcpa) / ra;
+    const R sb = mb * ((Dbt + wb * Dbw) * inv_rr2 * fcb + (Sbt + wb * Sbw) * fcpb) / rb;
+    R pax = sa * dax, pay = sa * day, paz = sa * daz;
+    R pbx = sb * dbx, pby = sb * dby, pbz = sb * dbz;
     if (e < na) {
       const int k = kidx[e];
       if (k >= 0) {
-        px += gx[k];
-        py += gy[k];
-        pz += gz[k];
+        pax += gx[k];
+        pay += gy[k];
+        paz += gz[k];
       }
     }
-    pg[3 * (size_t)e] = px;
-    pg[3 * (size_t)e + 1] = py;
-    pg[3 * (size_t)e + 2] = pz;
-    sx += (double)px;
-    sy += (double)py;
-    sz += (double)pz;
+    if (hb && eb < na) {
+      const int k = kidx[eb];
+      if (k >= 0) {
+        pbx += gx[k];
+        pby += gy[k];
+        pbz += gz[k];
+      }
+    }
+    pg[3 * (size_t)e] = pax;
+    pg[3 * (size_t)e + 1] = pay;
+    pg[3 * (size_t)e + 2] = paz;
+    sx += (double)pax;
+    sy += (double)pay;
+    sz += (double)paz;
+    if (hb) {
+      pg[3 * (size_t)eb] = pbx;
+      pg[3 * (size_t)eb + 1] = pby;
+      pg[3 * (size_t)eb + 2] = pbz;
+      sx += (double)pbx;
+      sy += (double)pby;
+      sz += (double)pbz;
+    }
   }
   sx = group_sum<LPA>(sx);
   sy = group_sum<LPA>(sy);

@@ -73,6 +73,7 @@ struct aenet_ctx {
   int pbc[3] = {1, 1, 1};
   int n_cells = 0;
   int cap = 0, cap_ang = 0;
+  int ang_mean = 0;  // expected mean number of neighbours within R_a (densest structure)
   bool nbr_valid = false;
 
   DevMem d_perm, d_species, d_seg, d_segoff, d_segcount, d_boxes;
@@ -216,7 +217,7 @@ aenet_status pack_networks(aenet_ctx* c) {
 
 // ------------------------------------------------------------------ geometry
 aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const int32_t* species,
-                     const double* boxes, const uint8_t* pbc) {
+                     const double* boxes, const uint8_t* pbc, const double* pos_dev) {
   if (n_struct < 1 || !offsets || offsets[0] != 0) return fail(c, AENET_E_INVALID, "bad structure offsets");
   for (int s = 0; s < n_struct; ++s)
     if (offsets[s + 1] < offsets[s]) return fail(c, AENET_E_INVALID, "structure offsets must not decrease");
@@ -262,17 +263,50 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
     c->n_struct = n_struct;
     c->offsets_cache.assign(offsets, offsets + n_struct + 1);
     c->species_cache.assign(species, species + n);
-    // stable counting sort by species: internal position p holds caller atom perm[p]
+    // internal order: by species (so that network tiles have one species), then
+    // by structure, then spatially (Z-order of the neighbour cells of the
+    // positions at this call) for cache locality of the neighbour gathers;
+    // internal position p holds caller atom perm[p]
     std::vector<int> cnt(c->S + 1, 0);
     for (int64_t i = 0; i < n; ++i) cnt[species[i] + 1]++;
     for (int s = 0; s < c->S; ++s) cnt[s + 1] += cnt[s];
     for (int s = 0; s <= c->S; ++s) c->sp_off[s] = cnt[s];
-    c->perm.assign(n, 0);
-    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t i = 0; i < n; ++i) c->perm[fill[species[i]]++] = (int)i;
-    std::vector<int> sp_int(n), seg_int(n), seg_orig(n);
+    std::vector<uint64_t> zkey(n, 0);
+    if (pos_dev && n > 0) {
+      std::vector<double> ph((size_t)n * 3);
+      // positions may still be in flight on the caller's stream (rare path: new species pattern)
+      HIP_TRY(c, hipDeviceSynchronize());
+      HIP_TRY(c, hipMemcpy(ph.data(), pos_dev, (size_t)n * 24, hipMemcpyDeviceToHost));
+      for (int s = 0; s < n_struct; ++s) {
+        const BoxInfo& b = bx[s];
+        for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) {
+          uint32_t cc[3];
+          for (int a = 0; a < 3; ++a) {
+            double x = ph[3 * i + a];
+            double f = std::floor(x / b.L[a] * b.nc[a]);
+            if (pb[a]) f -= b.nc[a] * std::floor(f / b.nc[a]);
+            if (!(f >= 0)) f = 0;
+            if (f > b.nc[a] - 1) f = b.nc[a] - 1;
+            cc[a] = (uint32_t)f;
+          }
+          uint64_t z = 0;
+          for (int bit = 0; bit < 10; ++bit)
+            for (int a = 0; a < 3; ++a) z |= (uint64_t)((cc[a] >> bit) & 1u) << (3 * bit + a);
+          zkey[i] = z;
+        }
+      }
+    }
+    std::vector<int> seg_orig(n);
     for (int s = 0; s < n_struct; ++s)
       for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) seg_orig[i] = s;
+    c->perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) c->perm[i] = (int)i;
+    std::stable_sort(c->perm.begin(), c->perm.end(), [&](int a, int b) {
+      if (species[a] != species[b]) return species[a] < species[b];
+      if (seg_orig[a] != seg_orig[b]) return seg_orig[a] < seg_orig[b];
+      return zkey[a] < zkey[b];
+    });
+    std::vector<int> sp_int(n), seg_int(n);
     for (int64_t p = 0; p < n; ++p) {
       sp_int[p] = species[c->perm[p]];
       seg_int[p] = seg_orig[c->perm[p]];
@@ -335,6 +369,13 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
       est_a = std::max(est_a, rho * 4.18879020478639 * ra * ra * ra);
     }
     c->cap = pad_to((int)(est * 1.35) + 24, 16);
+    double mean_a = 0.0;
+    for (int s = 0; s < n_struct; ++s) {
+      const double V = bx[s].L[0] * bx[s].L[1] * bx[s].L[2];
+      const double rho = (double)(offsets[s + 1] - offsets[s]) / V;
+      mean_a = std::max(mean_a, rho * 4.18879020478639 * c->ra * c->ra * c->ra);
+    }
+    c->ang_mean = (int)(mean_a + 0.5);
     c->cap_ang = std::min(c->cap, pad_to((int)(est_a * 1.6) + 16, 8));
   }
   return AENET_OK;
@@ -390,11 +431,7 @@ DescParams desc_params(aenet_ctx* c) {
   p.nang = c->d_nang.as<int>();
   p.cap = c->cap;
   p.cap_ang = c->cap_ang;
-  {
-    // the build counts entries within R_a + skin; scale to the shell within R_a
-    const double f = c->ra / (c->ra + c->skin);
-    p.ang_hint = (int)(std::min(c->stats.max_angular, c->cap_ang) * f * f * f + 0.5);
-  }
+  p.ang_hint = c->ang_mean;
   p.rr = c->rr;
   p.ra = c->ra;
   for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];
@@ -575,7 +612,7 @@ aenet_status ef_core(aenet_ctx* c, int n_struct, const int64_t* offsets, const d
                      const int32_t* species, const double* boxes, const uint8_t* pbc,
                      double* e_struct, double* e_total, double* e_atom, double* forces,
                      hipStream_t s) {
-  TRY(prepare(c, n_struct, offsets, species, boxes, pbc));
+  TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos));
   const int n = (int)c->n;
   if (n == 0) {
     if (e_total) HIP_TRY(c, hipMemsetAsync(e_total, 0, 8, s));
@@ -841,11 +878,14 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
   TRY(check_ctx(c));
   if (n < 0 || !box || (n > 0 && (!pos || !G))) return fail(c, AENET_E_INVALID, "bad arguments");
   const int64_t off[2] = {0, n};
-  TRY(prepare(c, 1, off, species, box, pbc));
-  if (n == 0) return AENET_OK;
   hipStream_t s = c->stream;
-  TRY(ensure(c, c->h_pos, (size_t)n * 24));
-  HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
+  if (n > 0) {
+    TRY(ensure(c, c->h_pos, (size_t)n * 24));
+    HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  TRY(prepare(c, 1, off, species, box, pbc, n > 0 ? c->h_pos.as<double>() : nullptr));
+  if (n == 0) return AENET_OK;
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
   launch_gather_in((int)n, c->d_perm.as<int>(), c->h_pos.as<double>(), c->d_pos.as<double>(),
                    c->d_flags.as<int>(), s);
@@ -872,7 +912,7 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   if (!c->have_mass) return fail(c, AENET_E_INVALID, "molecular dynamics needs mass_amu in the model");
   if (!(dt > 0) || n_steps < 0) return fail(c, AENET_E_INVALID, "dt must be > 0 and n_steps >= 0");
   const int64_t off[2] = {0, n};
-  TRY(prepare(c, 1, off, species, box, pbc));
+  TRY(prepare(c, 1, off, species, box, pbc, pos));
   const int N = (int)n;
   if (N == 0) {
     if (e_pot) HIP_TRY(c, hipMemsetAsync(e_pot, 0, 8, s));
@@ -1006,7 +1046,7 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   if (n_struct < 1 || !offsets || !boxes || !e_ref || !f_ref || !loss || !grad || !(lambda_f >= 0))
     return fail(c, AENET_E_INVALID, "bad arguments");
   hipStream_t s = pick_stream(c, stream);
-  TRY(prepare(c, n_struct, offsets, species, boxes, pbc));
+  TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos));
   const int n = (int)c->n;
   if (n == 0) return fail(c, AENET_E_INVALID, "empty batch");
   for (int b = 0; b < n_struct; ++b)

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
   const int i = blockIdx.x * (blockDim.x / LPA) + g;
   double sx = 0.0, sy = 0.0, sz = 0.0;
   const int nn = i < n ? nnb[i] : 0;
+#pragma unroll 4
   for (int e = l; e < nn; e += LPA) {
     const int r = rev[(size_t)i * cap + e];
     if (r >= 0) {

@@ -84,15 +84,25 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
         b[ks] = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
       }
     }
+    // two independent accumulation chains (even / odd k-steps) halve the
+    // dependent MFMA latency
+    typename M::Acc acc1 = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < MAXKS; ++ks) {
+    for (int ks = 0; ks < MAXKS; ks += 2) {
       if (ks < ksteps) {
         if constexpr (PREC == 0)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
         else
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], b[ks], acc, 0, 0, 0);
       }
+      if (ks + 1 < ksteps) {
+        if constexpr (PREC == 0)
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks + 1], b[ks + 1], acc1, 0, 0, 0);
+        else
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks + 1], b[ks + 1], acc1, 0, 0, 0);
+      }
     }
+    acc += acc1;
   } else {
     constexpr int MAXKS = kMaxWidth / 32;
     v8bf a[MAXKS], b[MAXKS];

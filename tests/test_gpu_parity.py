@@ -198,3 +198,26 @@ def test_md_resume_is_bitwise(A):
     pb, vb, epb, ekb, _ = ctx.md_step(pb, vb, s.species, s.box, s.pbc, 5e-4, 50)
     assert np.array_equal(pa, pb) and np.array_equal(va, vb)
     assert epa == epb and eka == ekb
+
+
+def test_nve_energy_error_scales_dt2(A):
+    """Velocity Verlet on the GPU: the total-energy error over a fixed time
+    falls by about 4x when dt is halved."""
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 5)
+    ctx = A.Context(m, "fp64", skin=0.3)
+
+    def max_dev(dt, nsteps, every):
+        p, vv = s.pos, v
+        _, _, ep0, ek0, _ = ctx.md_step(p, vv, s.species, s.box, s.pbc, dt, 0)
+        dev = 0.0
+        for _ in range(nsteps // every):
+            p, vv, ep, ek, _ = ctx.md_step(p, vv, s.species, s.box, s.pbc, dt, every)
+            dev = max(dev, abs(ep + ek - ep0 - ek0))
+        return dev
+
+    d1 = max_dev(5e-4, 40, 2)
+    d2 = max_dev(2.5e-4, 80, 4)
+    print(f"nve: max |dE| {d1:.3e} (dt 0.5 fs) {d2:.3e} (dt 0.25 fs) ratio {d1 / d2:.2f}")
+    assert 2.5 < d1 / d2 < 5.5
