@@ -34,6 +34,27 @@ __device__ inline uint64_t group_ballot(bool pred) {
   return (m >> (g * LPA)) & ((1ull << LPA) - 1ull);
 }
 
+// Reduce-scatter over a group of LPA lanes: on entry every lane holds N
+// partial sums v[0..N); on exit lane l holds in v[0..N/LPA) the group sums of
+// components (N/LPA)*l + i.  Each halving step sends the half the lane gives
+// up to its partner, so N(1 - 1/LPA) values cross lanes instead of
+// N log2(LPA) for a full butterfly.
+template <int LPA, int N, typename T>
+__device__ inline void group_reduce_scatter(T (&v)[N], int l) {
+#pragma unroll
+  for (int mask = LPA / 2, h = N / 2; mask > 0; mask >>= 1, h >>= 1) {
+    const bool up = (l & mask) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const T send = up ? v[k] : v[k + h];
+      const T keep = up ? v[k + h] : v[k];
+      v[k] = keep + __shfl_xor(send, mask, LPA);
+    }
+  }
+}
+
+constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
+
 template <typename R>
 __device__ inline R sqrt_r(R x);
 template <>
@@ -306,28 +327,31 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
     }
   }
 
+  // pack in the G layout [rad_typ | ang_typ | rad_wt | ang_wt] (ordered angular
+  // pairs = 2 x unordered), reduce-scatter over the group, write
+  constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+  constexpr int NV = pow2_at_least(2 * T2 > LPA ? 2 * T2 : LPA);
+  R v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = R(0);
 #pragma unroll
   for (int a = 0; a <= NR; ++a) {
-    rt[a] = group_sum<LPA>(rt[a]);
-    rw[a] = group_sum<LPA>(rw[a]);
+    v[a] = rt[a];
+    v[T2 + a] = rw[a];
   }
 #pragma unroll
   for (int a = 0; a <= NA; ++a) {
-    at[a] = group_sum<LPA>(at[a]) * R(2);
-    aw[a] = group_sum<LPA>(aw[a]) * R(2);
+    v[T1 + a] = R(2) * at[a];
+    v[T2 + T1 + a] = R(2) * aw[a];
   }
+  group_reduce_scatter<LPA, NV, R>(v, l);
   if (active) {
     R* G = reinterpret_cast<R*>(p.G) + (size_t)i * p.ldG;
-    constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+    const int D = p.weighted ? 2 * T2 : T2;
 #pragma unroll
-    for (int a = 0; a <= NR; ++a) {
-      if (a % LPA == l) G[a] = rt[a];
-      if (p.weighted && (T2 + a) % LPA == l) G[T2 + a] = rw[a];
-    }
-#pragma unroll
-    for (int a = 0; a <= NA; ++a) {
-      if ((T1 + a) % LPA == l) G[T1 + a] = at[a];
-      if (p.weighted && (T2 + T1 + a) % LPA == l) G[T2 + T1 + a] = aw[a];
+    for (int k = 0; k < NV / LPA; ++k) {
+      const int c = (NV / LPA) * l + k;
+      if (c < D) G[c] = v[k];
     }
   }
 }
@@ -417,6 +441,64 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
       da[a] = R(a) * ga[a];
       dw[a] = R(a) * gw[a];
     }
+    if (nv <= LPA) {
+      // Unordered pairs by rotation: lane l owns entry l; at step t it takes
+      // the pair (l, (l+t) mod nv), adds the gradient w.r.t. its own entry
+      // and passes the partner's gradient to the partner's lane (a rotation
+      // by t within the group).  Steps t = 1..floor(nv/2) visit every pair
+      // once (for even nv the last step is taken by the first half only).
+      const bool own = l < nv;
+      const int k = own ? l : 0;
+      const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
+      R ax = 0, ay = 0, az = 0;
+      const int nsteps = nv / 2;
+      for (int t = 1; t <= nsteps; ++t) {
+        int m = l + t;
+        if (m >= nv) m -= nv;
+        if (!own) m = 0;
+        const R wgt = (own && (2 * t != nv || l < t)) ? R(1) : R(0);
+        const R jx = ux[m], jy = uy[m], jz = uz[m], fm = fs[m], fpm = fp[m], rim = ri[m];
+        const R c = jx * kx + jy * ky + jz * kz;
+        R t0 = R(1), t1 = c, u0 = R(1), u1 = R(2) * c;
+        R At = ga[0], Aw = gw[0], Bt = R(0), Bw = R(0);
+#pragma unroll
+        for (int a = 1; a <= NA; ++a) {
+          At += ga[a] * t1;
+          Aw += gw[a] * t1;
+          Bt += da[a] * u0;
+          Bw += dw[a] * u0;
+          const R t2 = R(2) * c * t1 - t0;
+          t0 = t1;
+          t1 = t2;
+          const R u2 = R(2) * c * u1 - u0;
+          u0 = u1;
+          u1 = u2;
+        }
+        const R ww = ws[m] * wk;
+        const R A = (At + ww * Aw) * wgt, B = (Bt + ww * Bw) * wgt;
+        // own side
+        const R cbk = B * fk * fm * rik, cak = A * fm * fpk;
+        ax += cbk * (jx - c * kx) + cak * kx;
+        ay += cbk * (jy - c * ky) + cak * ky;
+        az += cbk * (jz - c * kz) + cak * kz;
+        // partner side, delivered to lane m: this lane receives from (l - t) mod nv
+        const R cbm = B * fk * fm * rim, cam = A * fk * fpm;
+        const R gxm = cbm * (kx - c * jx) + cam * jx;
+        const R gym = cbm * (ky - c * jy) + cam * jy;
+        const R gzm = cbm * (kz - c * jz) + cam * jz;
+        int src = l - t;
+        if (src < 0) src += nv;
+        if (!own) src = l;
+        ax += __shfl(gxm, src, LPA);
+        ay += __shfl(gym, src, LPA);
+        az += __shfl(gzm, src, LPA);
+      }
+      if (own) {
+        gx[l] = R(2) * ax;
+        gy[l] = R(2) * ay;
+        gz[l] = R(2) * az;
+      }
+    } else
     for (int k = l; k < nv; k += LPA) {
       const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
       R ax = 0, ay = 0, az = 0;

@@ -376,7 +376,7 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
       mean_a = std::max(mean_a, rho * 4.18879020478639 * c->ra * c->ra * c->ra);
     }
     c->ang_mean = (int)(mean_a + 0.5);
-    c->cap_ang = std::min(c->cap, pad_to((int)(est_a * 1.6) + 16, 8));
+    c->cap_ang = std::min(c->cap, pad_to((int)(est_a * 1.3) + 8, 8));
   }
   return AENET_OK;
 }
@@ -469,7 +469,7 @@ int n_tiles(const MlpParams& p) { return p.tile_off[p.n_species]; }
 aenet_status grow_caps(aenet_ctx* c, const int* hf) {
   const int need = hf[1], need_a = hf[2];
   int cap = std::max(c->cap, pad_to((int)(need * 1.2) + 16, 16));
-  int cap_a = std::max(c->cap_ang, pad_to((int)(need_a * 1.25) + 8, 8));
+  int cap_a = std::max(c->cap_ang, pad_to((int)(need_a * 1.15) + 8, 8));
   if (cap_a > cap) cap = pad_to(cap_a, 16);
   if (cap_a > 700) return fail(c, AENET_E_INVALID, "angular neighbour shell too crowded (" + std::to_string(need_a) + " entries)");
   c->cap = cap;

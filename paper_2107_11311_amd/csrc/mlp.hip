@@ -178,11 +178,20 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
     const T* sh = reinterpret_cast<const T*>(net.shift);
     const T* sc = reinterpret_cast<const T*>(net.scale);
     const int w0 = p.wp[0], D = p.w[0];
-    for (int idx = lane; idx < 16 * w0; idx += 64) {
+    // all loads of the tile issued before any use (16 x w0 <= 16 x 64 elements)
+    constexpr int IT = 16 * kMaxWidth / 64;
+    T v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = lane + 64 * it;
       const int r = idx / w0, c = idx % w0;
-      T v = T(0);
-      if (r < ti.count && c < D) v = (G[(size_t)(ti.first + r) * p.ldG + c] - sh[c]) * sc[c];
-      lds[r * (w0 + 1) + c] = v;
+      v[it] = (idx < 16 * w0 && r < ti.count && c < D) ? G[(size_t)(ti.first + r) * p.ldG + c] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = lane + 64 * it;
+      const int r = idx / w0, c = idx % w0;
+      if (idx < 16 * w0) lds[r * (w0 + 1) + c] = (r < ti.count && c < D) ? (v[it] - sh[c]) * sc[c] : T(0);
     }
   }
   __syncthreads();
@@ -326,16 +335,28 @@ __global__ __launch_bounds__(64) void k_mlp_train(MlpParams p) {
 
   for (int tile = tiles_lo; tile < tiles_hi; ++tile) {
     const TileInfo ti = tile_info(p, tile);
-    for (int idx = lane; idx < 16 * w0; idx += 64) {
-      const int r = idx / w0, c = idx % w0;
-      T v = T(0), vd = T(0);
-      if (r < ti.count && c < D) {
-        const size_t o = (size_t)(ti.first + r) * p.ldG + c;
-        v = (Gm[o] - sh[c]) * sc[c];
-        vd = Um[o] * sc[c];
+    {
+      constexpr int IT = 16 * kMaxWidth / 64;
+      T g[IT], u[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = lane + 64 * it;
+        const int r = idx / w0, c = idx % w0;
+        const bool in = idx < 16 * w0 && r < ti.count && c < D;
+        const size_t o = (size_t)(ti.first + (in ? r : 0)) * p.ldG + (in ? c : 0);
+        g[it] = in ? Gm[o] : T(0);
+        u[it] = in ? Um[o] : T(0);
       }
-      X[idx] = v;
-      Xd[idx] = vd;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = lane + 64 * it;
+        const int r = idx / w0, c = idx % w0;
+        if (idx < 16 * w0) {
+          const bool in = r < ti.count && c < D;
+          X[idx] = in ? (g[it] - sh[c]) * sc[c] : T(0);
+          Xd[idx] = in ? u[it] * sc[c] : T(0);
+        }
+      }
     }
     __syncthreads();
     // forward and tangent
