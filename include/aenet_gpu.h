@@ -205,6 +205,15 @@ typedef struct {
 aenet_status aenet_get_stats(const aenet_ctx* ctx, aenet_stats* out);
 /* rebuild_every >= 1 (default 50). */
 aenet_status aenet_set_rebuild_every(aenet_ctx* ctx, int rebuild_every);
+/* Neighbour-row capacities used from the next call on: row_capacity entries
+ * per atom within R_r + skin, ang_capacity of them within R_a + skin
+ * (1 <= ang_capacity <= row_capacity, ang_capacity <= 700, row_capacity <=
+ * 4096).  Rows grow by themselves when a build overflows them (the build, or
+ * the MD chunk since the last checkpoint, is redone), so this only sets the
+ * starting point: a caller who knows the densest environment avoids the
+ * retry, and small values exercise it.  (0, 0) returns to the estimate from
+ * the number density.  AENET_E_INVALID for other values. */
+aenet_status aenet_set_capacity(aenet_ctx* ctx, int row_capacity, int ang_capacity);
 
 /* Kernel timing (diagnostics).  While enabled, every launch of a hot-path
  * kernel is bracketed by HIP events on the stream it is launched on, and

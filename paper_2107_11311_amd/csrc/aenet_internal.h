@@ -57,7 +57,7 @@ struct NbrParams {
   int* rev;              // [n*cap] global index of the reverse entry
   int* flags;
   int* maxcnt;           // [2] largest row, largest angular prefix
-  const int* cond;       // build only if *cond != 0 (NULL = always)
+  int* cond;             // build only if *cond != 0 (NULL = always)
 };
 void launch_build_neighbors(const NbrParams& p, hipStream_t s);
 void launch_set_int(int* dst, int value, hipStream_t s);

@@ -35,14 +35,23 @@ __device__ inline uint64_t group_ballot(bool pred) {
 }
 
 // Reduce-scatter over a group of LPA lanes: on entry every lane holds N
-// partial sums v[0..N); on exit lane l holds in v[0..N/LPA) the group sums of
-// components (N/LPA)*l + i.  Each halving step sends the half the lane gives
-// up to its partner, so N(1 - 1/LPA) values cross lanes instead of
-// N log2(LPA) for a full butterfly.
+// partial sums v[0..N) (N a power of two); on exit lane l holds the group sum
+// of component rs_comp<LPA, N>(l, i) in v[i] for i < max(N / LPA, 1).  Each
+// halving step sends the half the lane gives up to its partner, so about N
+// values cross lanes instead of N log2(LPA) for a full butterfly.  When
+// N < LPA the lanes that differ above bit log2(N) first add their vectors,
+// and lanes l and l + N end with the same component.
 template <int LPA, int N, typename T>
 __device__ inline void group_reduce_scatter(T (&v)[N], int l) {
+  if constexpr (LPA > N) {
 #pragma unroll
-  for (int mask = LPA / 2, h = N / 2; mask > 0; mask >>= 1, h >>= 1) {
+    for (int mask = LPA / 2; mask >= N; mask >>= 1)
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], mask, LPA);
+  }
+  constexpr int W = LPA < N ? LPA : N;
+#pragma unroll
+  for (int mask = W / 2, h = N / 2; mask > 0; mask >>= 1, h >>= 1) {
     const bool up = (l & mask) != 0;
 #pragma unroll
     for (int k = 0; k < h; ++k) {
@@ -51,6 +60,12 @@ __device__ inline void group_reduce_scatter(T (&v)[N], int l) {
       v[k] = keep + __shfl_xor(send, mask, LPA);
     }
   }
+}
+
+template <int LPA, int N>
+__device__ inline int rs_comp(int l, int i) {
+  constexpr int W = LPA < N ? LPA : N;
+  return (N / W) * (l % W) + i;
 }
 
 constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
@@ -145,17 +160,18 @@ __device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double x
 // iteration ahead of its use so the gather latency hides behind the
 // arithmetic of the current iteration).
 struct NbrLoad {
-  int q, code;
-  double x, y, z;
+  int code;
+  double x, y, z, w;  // position and species weight of the neighbour atom
 };
 
-__device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t w) {
+__device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t word) {
   NbrLoad n;
-  n.q = (int)(w & kAtomMask);
-  n.code = (int)(w >> kImgBits);
-  n.x = p.pos[3 * (size_t)n.q];
-  n.y = p.pos[3 * (size_t)n.q + 1];
-  n.z = p.pos[3 * (size_t)n.q + 2];
+  const int q = (int)(word & kAtomMask);
+  n.code = (int)(word >> kImgBits);
+  n.x = p.pos[3 * (size_t)q];
+  n.y = p.pos[3 * (size_t)q + 1];
+  n.z = p.pos[3 * (size_t)q + 2];
+  n.w = p.tw[p.species[q]];
   return n;
 }
 
@@ -166,9 +182,35 @@ __device__ inline void nbr_disp(const NbrLoad& n, const BoxInfo& b, double xi0, 
   d2 = n.z + (double)(n.code / 9 - 1) * b.L[2] - xi2;
 }
 
+// S(x) = sum_{a=0..N} c_a T_a(x) and S'(x) by Clenshaw's recurrence, with
+// c_a = g[a] + w h[a] (the typed and weighted coefficients of one neighbour
+// or pair combined on the fly): b_a = c_a + 2x b_{a+1} - b_{a+2} and its
+// x-derivative b'_a = 2 b_{a+1} + 2x b'_{a+1} - b'_{a+2}, from
+// b_{N+1} = b_{N+2} = 0; then S = c_0 + x b_1 - b_2, S' = b_1 + x b'_1 - b'_2.
+// Five operations per order and only g, h live (instead of the values and
+// derivatives of both channels kept by forward recurrences).
+template <typename R, int N>
+__device__ inline void cheb_series_d(const R (&g)[N + 1], const R (&h)[N + 1], R w, R x, R* S,
+                                     R* dS) {
+  const R x2 = x + x;
+  R b1 = R(0), b2 = R(0), d1 = R(0), d2 = R(0);
+#pragma unroll
+  for (int a = N; a >= 1; --a) {
+    const R c = g[a] + w * h[a];
+    const R bk = x2 * b1 + (c - b2);
+    const R dk = x2 * d1 + (R(2) * b1 - d2);
+    b2 = b1;
+    b1 = bk;
+    d2 = d1;
+    d1 = dk;
+  }
+  *S = x * b1 + ((g[0] + w * h[0]) - b2);
+  *dS = x * d1 + (b1 - d2);
+}
+
 // ------------------------------------------------------------------ forward
 template <typename R, int NR, int NA, int LPA>
-__global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
+__global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int apb = blockDim.x / LPA;
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
@@ -213,7 +255,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
     double a0, a1, a2, b0, b1, b2;
     nbr_disp(na_, b, xi0, xi1, xi2, a0, a1, a2);
     nbr_disp(nb_, b, xi0, xi1, xi2, b0, b1, b2);
-    const int qa = na_.q, qb = nb_.q;
+    const R twa = R(na_.w), twb = R(nb_.w);
     na_ = na1;
     nb_ = nb1;
     wa1 = wa2;
@@ -228,7 +270,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
     sincos_cut<R>(rb, inv_rr2, &snb, &csb);
     const R fa = va ? R(0.5) * (csa + R(1)) : R(0);
     const R fb = vb ? R(0.5) * (csb + R(1)) : R(0);
-    const R wa = R(p.tw[p.species[qa]]) * fa, wb = R(p.tw[p.species[qb]]) * fb;
+    const R wa = twa * fa, wb = twb * fb;
     R ta0 = R(1), ta1 = xa, tb0 = R(1), tb1 = xb;
     rt[0] += fa + fb;
     rw[0] += wa + wb;
@@ -327,42 +369,54 @@ __global__ __launch_bounds__(256) void k_desc_fwd(DescParams p) {
     }
   }
 
-  // pack in the G layout [rad_typ | ang_typ | rad_wt | ang_wt] (ordered angular
-  // pairs = 2 x unordered), reduce-scatter over the group, write
+  // G layout [rad_typ | ang_typ | rad_wt | ang_wt] (ordered angular pairs =
+  // 2 x unordered).  Each half (typed, weighted) is packed into a vector of
+  // NV = 2^k >= T2 partial sums and reduce-scattered over the group on its
+  // own, so only one such vector is live at a time.
   constexpr int T1 = NR + 1, T2 = NR + NA + 2;
-  constexpr int NV = pow2_at_least(2 * T2 > LPA ? 2 * T2 : LPA);
-  R v[NV];
+  constexpr int NV = pow2_at_least(T2);
+  constexpr int PER = NV / LPA > 0 ? NV / LPA : 1;
+  R* G = reinterpret_cast<R*>(p.G) + (size_t)(active ? i : 0) * p.ldG;
+  const bool writer = active && l < NV;
+  {
+    R v[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = R(0);
+    for (int a = 0; a < NV; ++a) v[a] = a <= NR ? rt[a] : (a < T2 ? R(2) * at[a - T1] : R(0));
+    group_reduce_scatter<LPA, NV, R>(v, l);
 #pragma unroll
-  for (int a = 0; a <= NR; ++a) {
-    v[a] = rt[a];
-    v[T2 + a] = rw[a];
+    for (int k = 0; k < PER; ++k) {
+      const int c = rs_comp<LPA, NV>(l, k);
+      if (writer && c < T2) G[c] = v[k];
+    }
   }
+  if (p.weighted) {
+    R v[NV];
 #pragma unroll
-  for (int a = 0; a <= NA; ++a) {
-    v[T1 + a] = R(2) * at[a];
-    v[T2 + T1 + a] = R(2) * aw[a];
-  }
-  group_reduce_scatter<LPA, NV, R>(v, l);
-  if (active) {
-    R* G = reinterpret_cast<R*>(p.G) + (size_t)i * p.ldG;
-    const int D = p.weighted ? 2 * T2 : T2;
+    for (int a = 0; a < NV; ++a) v[a] = a <= NR ? rw[a] : (a < T2 ? R(2) * aw[a - T1] : R(0));
+    group_reduce_scatter<LPA, NV, R>(v, l);
 #pragma unroll
-    for (int k = 0; k < NV / LPA; ++k) {
-      const int c = (NV / LPA) * l + k;
-      if (c < D) G[c] = v[k];
+    for (int k = 0; k < PER; ++k) {
+      const int c = rs_comp<LPA, NV>(l, k);
+      if (writer && c < T2) G[T2 + c] = v[k];
     }
   }
 }
 
 // ------------------------------------------------------------------ backward
-// pg[i, e] = dE_i / d d_e for every entry of atom i; Fself[i] = sum_e pg[i, e]
-template <typename R, int NR, int NA, int LPA>
-__global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
+// pg[i, e] = dE_i / d d_e for every entry of atom i; Fself[i] = sum_e pg[i, e].
+// One wavefront per atom (the atom index is uniform over the wave):
+//   compaction of the entries within R_a into LDS (unit vector, f_c, f_c',
+//     species weight, 1/r);
+//   angular terms by rotation (below), the gradient of entry k kept in the
+//     registers of the lane that owns k, so no atomics are needed;
+//   radial terms, one entry per lane per iteration, adding the angular
+//     gradient of the entry and writing pg.
+template <typename R, int NR, int NA>
+__global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int apb = blockDim.x / LPA;
-  const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
+  const int apb = blockDim.x >> 6;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
   const int i = blockIdx.x * apb + g;
   const bool active = i < p.n;
   const int ca = p.cap_ang;
@@ -391,9 +445,9 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
   const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)(active ? i : 0) * p.ldG;
   constexpr int T1 = NR + 1, T2 = NR + NA + 2;
 
-  // compact the angular entries
+  // compact the entries within R_a
   int nv = 0;
-  for (int base = 0; base < na; base += LPA) {
+  for (int base = 0; base < na; base += 64) {
     const int e = base + l;
     bool valid = false;
     R vx = 0, vy = 0, vz = 0, vf = 0, vfp = 0, vw = 0, vri = 0;
@@ -415,7 +469,7 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
         vw = R(p.tw[p.species[q]]);
       }
     }
-    const uint64_t m = group_ballot<LPA>(valid);
+    const uint64_t m = __ballot(valid);
     const int at_ = nv + __popcll(m & ((1ull << l) - 1ull));
     if (valid) {
       ux[at_] = vx;
@@ -429,241 +483,164 @@ __global__ __launch_bounds__(256) void k_desc_bwd(DescParams p) {
     if (e < na) kidx[e] = valid ? at_ : -1;
     nv += __popcll(m);
   }
+  nv = __builtin_amdgcn_readfirstlane(nv);
   __syncthreads();
 
-  // angular: lane owns entry k, sums d/dd_k over all j != k (ordered pairs)
+  // angular terms: d/dd_k of sum over ordered pairs = 2 x the unordered pairs
   {
-    R ga[NA + 1], gw[NA + 1], da[NA + 1], dw[NA + 1];
+    R ga[NA + 1], gw[NA + 1];
 #pragma unroll
     for (int a = 0; a <= NA; ++a) {
       ga[a] = active ? gG[T1 + a] : R(0);
       gw[a] = (active && p.weighted) ? gG[T2 + T1 + a] : R(0);
-      da[a] = R(a) * ga[a];
-      dw[a] = R(a) * gw[a];
     }
-    if (nv <= LPA) {
-      // Unordered pairs by rotation: lane l owns entry l; at step t it takes
-      // the pair (l, (l+t) mod nv), adds the gradient w.r.t. its own entry
-      // and passes the partner's gradient to the partner's lane (a rotation
-      // by t within the group).  Steps t = 1..floor(nv/2) visit every pair
-      // once (for even nv the last step is taken by the first half only).
-      const bool own = l < nv;
-      const int k = own ? l : 0;
+    if (nv <= 64) {
+      // Unordered pairs by rotation: the lane owning entry e takes at step t
+      // the pair (e, (e + t) mod nv), adds the gradient w.r.t. its own entry
+      // and passes the partner's gradient to the lane owning the partner (a
+      // rotation by t).  Steps t = 1..floor(nv/2) visit every pair once (for
+      // even nv the last step is taken by entries e < t only).  With nv <= 32
+      // both halves of the wave hold all entries and share the steps: the
+      // lower half takes t = 1..T1, the upper half the rest.
+      const bool split = nv <= 32;
+      const int half = split ? (l >> 5) : 0;
+      const int e = split ? (l & 31) : l;
+      const bool own = e < nv;
+      const int T = nv >> 1;
+      const int Tlo = split ? (T + 1) >> 1 : T;
+      const int t0 = half ? Tlo : 0;
+      const int cnt = half ? T - Tlo : Tlo;
+      const int lane0 = half << 5;  // first lane of this half
+      const int k = own ? e : 0;
       const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
       R ax = 0, ay = 0, az = 0;
-      const int nsteps = nv / 2;
-      for (int t = 1; t <= nsteps; ++t) {
-        int m = l + t;
+      for (int st = 1; st <= Tlo; ++st) {
+        const int t = t0 + st;
+        const bool go = own && st <= cnt;
+        int m = e + t;
         if (m >= nv) m -= nv;
-        if (!own) m = 0;
-        const R wgt = (own && (2 * t != nv || l < t)) ? R(1) : R(0);
+        if (!go) m = k;
+        const R wgt = (go && (2 * t != nv || e < t)) ? R(1) : R(0);
         const R jx = ux[m], jy = uy[m], jz = uz[m], fm = fs[m], fpm = fp[m], rim = ri[m];
         const R c = jx * kx + jy * ky + jz * kz;
-        R t0 = R(1), t1 = c, u0 = R(1), u1 = R(2) * c;
-        R At = ga[0], Aw = gw[0], Bt = R(0), Bw = R(0);
-#pragma unroll
-        for (int a = 1; a <= NA; ++a) {
-          At += ga[a] * t1;
-          Aw += gw[a] * t1;
-          Bt += da[a] * u0;
-          Bw += dw[a] * u0;
-          const R t2 = R(2) * c * t1 - t0;
-          t0 = t1;
-          t1 = t2;
-          const R u2 = R(2) * c * u1 - u0;
-          u0 = u1;
-          u1 = u2;
-        }
-        const R ww = ws[m] * wk;
-        const R A = (At + ww * Aw) * wgt, B = (Bt + ww * Bw) * wgt;
+        R A, B;
+        cheb_series_d<R, NA>(ga, gw, ws[m] * wk, c, &A, &B);
+        A *= wgt;
+        B *= wgt;
         // own side
         const R cbk = B * fk * fm * rik, cak = A * fm * fpk;
         ax += cbk * (jx - c * kx) + cak * kx;
         ay += cbk * (jy - c * ky) + cak * ky;
         az += cbk * (jz - c * kz) + cak * kz;
-        // partner side, delivered to lane m: this lane receives from (l - t) mod nv
+        // partner side, delivered by rotation: this lane receives from the
+        // lane owning entry (e - t) mod nv in the same half
         const R cbm = B * fk * fm * rim, cam = A * fk * fpm;
         const R gxm = cbm * (kx - c * jx) + cam * jx;
         const R gym = cbm * (ky - c * jy) + cam * jy;
         const R gzm = cbm * (kz - c * jz) + cam * jz;
-        int src = l - t;
+        int src = e - t;
         if (src < 0) src += nv;
-        if (!own) src = l;
-        ax += __shfl(gxm, src, LPA);
-        ay += __shfl(gym, src, LPA);
-        az += __shfl(gzm, src, LPA);
-      }
-      if (own) {
-        gx[l] = R(2) * ax;
-        gy[l] = R(2) * ay;
-        gz[l] = R(2) * az;
-      }
-    } else
-    for (int k = l; k < nv; k += LPA) {
-      const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
-      R ax = 0, ay = 0, az = 0;
-      // two partners per iteration (independent chains); j == k and the slot
-      // past the end are computed with weight 0
-      for (int j = 0; j < nv; j += 2) {
-        const int jb = j + 1 < nv ? j + 1 : j;
-        const R ma = j != k ? R(1) : R(0);
-        const R mb = (j + 1 < nv && j + 1 != k) ? R(1) : R(0);
-        const R jax = ux[j], jay = uy[j], jaz = uz[j];
-        const R jbx = ux[jb], jby = uy[jb], jbz = uz[jb];
-        const R c1 = jax * kx + jay * ky + jaz * kz;
-        const R c2 = jbx * kx + jby * ky + jbz * kz;
-        // sum_a coef_a T_a(c) and sum_a coef_a T_a'(c), T_a' = a U_{a-1}
-        R t0 = R(1), t1 = c1, u0 = R(1), u1 = R(2) * c1;
-        R s0 = R(1), s1 = c2, v0 = R(1), v1 = R(2) * c2;
-        R At = ga[0], Aw = gw[0], Bt = R(0), Bw = R(0);
-        R Ct = ga[0], Cw = gw[0], Dt = R(0), Dw = R(0);
-#pragma unroll
-        for (int a = 1; a <= NA; ++a) {
-          At += ga[a] * t1;
-          Aw += gw[a] * t1;
-          Bt += da[a] * u0;
-          Bw += dw[a] * u0;
-          Ct += ga[a] * s1;
-          Cw += gw[a] * s1;
-          Dt += da[a] * v0;
-          Dw += dw[a] * v0;
-          const R t2 = R(2) * c1 * t1 - t0;
-          t0 = t1;
-          t1 = t2;
-          const R u2 = R(2) * c1 * u1 - u0;
-          u0 = u1;
-          u1 = u2;
-          const R s2 = R(2) * c2 * s1 - s0;
-          s0 = s1;
-          s1 = s2;
-          const R v2 = R(2) * c2 * v1 - v0;
-          v0 = v1;
-          v1 = v2;
+        src = go ? lane0 + src : l;
+        const R rx = __shfl(gxm, src, 64), ry = __shfl(gym, src, 64), rz = __shfl(gzm, src, 64);
+        if (go) {
+          ax += rx;
+          ay += ry;
+          az += rz;
         }
-        const R wwa = ws[j] * wk, wwb = ws[jb] * wk;
-        const R A1 = At + wwa * Aw, B1 = Bt + wwa * Bw;
-        const R A2 = Ct + wwb * Cw, B2 = Dt + wwb * Dw;
-        const R fja = fs[j] * ma, fjb = fs[jb] * mb;
-        const R cb1 = B1 * fja * fk * rik, ca1 = A1 * fja * fpk;
-        const R cb2 = B2 * fjb * fk * rik, ca2 = A2 * fjb * fpk;
-        ax += cb1 * (jax - c1 * kx) + ca1 * kx + cb2 * (jbx - c2 * kx) + ca2 * kx;
-        ay += cb1 * (jay - c1 * ky) + ca1 * ky + cb2 * (jby - c2 * ky) + ca2 * ky;
-        az += cb1 * (jaz - c1 * kz) + ca1 * kz + cb2 * (jbz - c2 * kz) + ca2 * kz;
       }
-      gx[k] = R(2) * ax;
-      gy[k] = R(2) * ay;
-      gz[k] = R(2) * az;
+      if (split) {
+        ax += __shfl_xor(ax, 32, 64);
+        ay += __shfl_xor(ay, 32, 64);
+        az += __shfl_xor(az, 32, 64);
+      }
+      if (own && half == 0) {
+        gx[e] = R(2) * ax;
+        gy[e] = R(2) * ay;
+        gz[e] = R(2) * az;
+      }
+    } else {
+      // crowded shells: each lane owns entries k = l, l + 64, ... and sums
+      // over all partners j != k (every pair is evaluated from both ends)
+      for (int k = l; k < nv; k += 64) {
+        const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
+        R ax = 0, ay = 0, az = 0;
+        for (int j = 0; j < nv; ++j) {
+          const R mj = j != k ? R(1) : R(0);
+          const R jx = ux[j], jy = uy[j], jz = uz[j];
+          const R c = jx * kx + jy * ky + jz * kz;
+          R A, B;
+          cheb_series_d<R, NA>(ga, gw, ws[j] * wk, c, &A, &B);
+          const R fj = fs[j] * mj;
+          const R cb = B * fj * fk * rik, cak = A * fj * fpk;
+          ax += cb * (jx - c * kx) + cak * kx;
+          ay += cb * (jy - c * ky) + cak * ky;
+          az += cb * (jz - c * kz) + cak * kz;
+        }
+        gx[k] = R(2) * ax;
+        gy[k] = R(2) * ay;
+        gz[k] = R(2) * az;
+      }
     }
   }
   __syncthreads();
 
   // radial terms, plus the angular part of each entry, written per entry
-  R grt[NR + 1], grw[NR + 1], drt[NR + 1], drw[NR + 1];
+  R grt[NR + 1], grw[NR + 1];
 #pragma unroll
   for (int a = 0; a <= NR; ++a) {
     grt[a] = active ? gG[a] : R(0);
     grw[a] = (active && p.weighted) ? gG[T2 + a] : R(0);
-    drt[a] = R(a) * grt[a];
-    drw[a] = R(a) * grw[a];
   }
   R* pg = reinterpret_cast<R*>(p.pg) + (size_t)(active ? i : 0) * p.cap * 3;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  // two entries per lane per iteration (independent chains); entries beyond
-  // R_r get a zero radial gradient through a zero weight
+  // one entry per lane per iteration, the next one's position loaded ahead;
+  // entries beyond R_r (skin) get a zero gradient through a zero weight, and
+  // slots past the end of the row repeat its last entry (an empty row reads
+  // the atom itself, always in bounds)
   const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
   auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
-  NbrLoad na_ = load_nbr(p, word(l)), nb_ = load_nbr(p, word(l + LPA));
-  uint32_t wa1 = word(l + 2 * LPA), wb1 = word(l + 3 * LPA);
-  for (int e = l; e < nn; e += 2 * LPA) {
-    const NbrLoad na1 = load_nbr(p, wa1), nb1 = load_nbr(p, wb1);
-    const uint32_t wa2 = word(e + 4 * LPA), wb2 = word(e + 5 * LPA);
-    const bool hb = e + LPA < nn;
-    const int eb = hb ? e + LPA : e;
-    double a0, a1, a2, b0, b1, b2;
-    nbr_disp(na_, b, xi0, xi1, xi2, a0, a1, a2);
-    nbr_disp(nb_, b, xi0, xi1, xi2, b0, b1, b2);
-    const int qa = na_.q, qb = nb_.q;
-    na_ = na1;
-    nb_ = nb1;
-    wa1 = wa2;
-    wb1 = wb2;
-    const R ma = (a0 * a0 + a1 * a1 + a2 * a2 < rr2) ? R(1) : R(0);
-    const R mb = (hb && b0 * b0 + b1 * b1 + b2 * b2 < rr2) ? R(1) : R(0);
-    const R dax = R(a0), day = R(a1), daz = R(a2), dbx = R(b0), dby = R(b1), dbz = R(b2);
-    const R ra = sqrt_r<R>(dax * dax + day * day + daz * daz);
-    const R rb = sqrt_r<R>(dbx * dbx + dby * dby + dbz * dbz);
-    const R xa = ra * inv_rr2 - R(1), xb = rb * inv_rr2 - R(1);
-    R sna, csa, snb, csb;
-    sincos_cut<R>(ra, inv_rr2, &sna, &csa);
-    sincos_cut<R>(rb, inv_rr2, &snb, &csb);
-    const R fca = R(0.5) * (csa + R(1)), fcpa = R(-0.5) * pi_rr * sna;
-    const R fcb = R(0.5) * (csb + R(1)), fcpb = R(-0.5) * pi_rr * snb;
-    R ta0 = R(1), ta1 = xa, ua0 = R(1), ua1 = R(2) * xa;
-    R tb0 = R(1), tb1 = xb, ub0 = R(1), ub1 = R(2) * xb;
-    R Sat = grt[0], Saw = grw[0], Dat = R(0), Daw = R(0);
-    R Sbt = grt[0], Sbw = grw[0], Dbt = R(0), Dbw = R(0);
-#pragma unroll
-    for (int a = 1; a <= NR; ++a) {
-      Sat += grt[a] * ta1;
-      Saw += grw[a] * ta1;
-      Dat += drt[a] * ua0;
-      Daw += drw[a] * ua0;
-      Sbt += grt[a] * tb1;
-      Sbw += grw[a] * tb1;
-      Dbt += drt[a] * ub0;
-      Dbw += drw[a] * ub0;
-      const R ta2 = R(2) * xa * ta1 - ta0;
-      ta0 = ta1;
-      ta1 = ta2;
-      const R ua2 = R(2) * xa * ua1 - ua0;
-      ua0 = ua1;
-      ua1 = ua2;
-      const R tb2 = R(2) * xb * tb1 - tb0;
-      tb0 = tb1;
-      tb1 = tb2;
-      const R ub2 = R(2) * xb * ub1 - ub0;
-      ub0 = ub1;
-      ub1 = ub2;
-    }
-    const R wa = R(p.tw[p.species[qa]]), wb = R(p.tw[p.species[qb]]);
-    const R sa = ma * ((Dat + wa * Daw) * inv_rr2 * fca + (Sat + wa * Saw) * fcpa) / ra;
-    const R sb = mb * ((Dbt + wb * Dbw) * inv_rr2 * fcb + (Sbt + wb * Sbw) * fcpb) / rb;
-    R pax = sa * dax, pay = sa * day, paz = sa * daz;
-    R pbx = sb * dbx, pby = sb * dby, pbz = sb * dbz;
-    if (e < na) {
+  NbrLoad nx = load_nbr(p, word(l));
+  uint32_t w1 = word(l + 64);
+  for (int e = l; e - l < nn; e += 64) {
+    const NbrLoad n1 = load_nbr(p, w1);
+    w1 = word(e + 128);
+    const bool he = e < nn;
+    double d0, d1, d2;
+    nbr_disp(nx, b, xi0, xi1, xi2, d0, d1, d2);
+    const R wq = R(nx.w);
+    nx = n1;
+    const R mq = (he && d0 * d0 + d1 * d1 + d2 * d2 < rr2) ? R(1) : R(0);
+    const R dx = R(d0), dy = R(d1), dz = R(d2);
+    const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
+    const R x = r * inv_rr2 - R(1);
+    R sn, cs;
+    sincos_cut<R>(r, inv_rr2, &sn, &cs);
+    const R fc = R(0.5) * (cs + R(1)), fcp = R(-0.5) * pi_rr * sn;
+    // dE/dr = S'(x) (2/R_r) f_c + S(x) f_c' with S = sum_a (grt_a + w grw_a) T_a
+    R S, dS;
+    cheb_series_d<R, NR>(grt, grw, wq, x, &S, &dS);
+    const R sc = mq * (dS * inv_rr2 * fc + S * fcp) / r;
+    R px = sc * dx, py = sc * dy, pz = sc * dz;
+    if (he && e < na) {
       const int k = kidx[e];
       if (k >= 0) {
-        pax += gx[k];
-        pay += gy[k];
-        paz += gz[k];
+        px += gx[k];
+        py += gy[k];
+        pz += gz[k];
       }
     }
-    if (hb && eb < na) {
-      const int k = kidx[eb];
-      if (k >= 0) {
-        pbx += gx[k];
-        pby += gy[k];
-        pbz += gz[k];
-      }
-    }
-    pg[3 * (size_t)e] = pax;
-    pg[3 * (size_t)e + 1] = pay;
-    pg[3 * (size_t)e + 2] = paz;
-    sx += (double)pax;
-    sy += (double)pay;
-    sz += (double)paz;
-    if (hb) {
-      pg[3 * (size_t)eb] = pbx;
-      pg[3 * (size_t)eb + 1] = pby;
-      pg[3 * (size_t)eb + 2] = pbz;
-      sx += (double)pbx;
-      sy += (double)pby;
-      sz += (double)pbz;
+    if (he) {
+      pg[3 * (size_t)e] = px;
+      pg[3 * (size_t)e + 1] = py;
+      pg[3 * (size_t)e + 2] = pz;
+      sx += (double)px;
+      sy += (double)py;
+      sz += (double)pz;
     }
   }
-  sx = group_sum<LPA>(sx);
-  sy = group_sum<LPA>(sy);
-  sz = group_sum<LPA>(sz);
+  sx = group_sum<64>(sx);
+  sy = group_sum<64>(sy);
+  sz = group_sum<64>(sz);
   if (active && l == 0) {
     p.Fself[3 * (size_t)i] = sx;
     p.Fself[3 * (size_t)i + 1] = sy;
@@ -873,10 +850,18 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
   const dim3 grid(blocks), block(apb * LPA);
   if (kind == FWD)
     hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA>), grid, block, lds, s, p);
-  else if (kind == BWD)
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, LPA>), grid, block, lds, s, p);
   else
     hipLaunchKernelGGL((k_desc_jvp<R, NR, NA, LPA>), grid, block, lds, s, p);
+}
+
+// the force pass: one wavefront per atom, up to four atoms per block
+template <typename R, int NR, int NA>
+void launch_bwd(const DescParams& p, hipStream_t s) {
+  const size_t per_atom = (size_t)p.cap_ang * (lds_words(BWD) * sizeof(R) + sizeof(int));
+  int apb = 4;
+  while (apb > 1 && (size_t)apb * per_atom > 65536) apb >>= 1;
+  const dim3 grid((p.n + apb - 1) / apb), block(apb * 64);
+  hipLaunchKernelGGL((k_desc_bwd<R, NR, NA>), grid, block, (size_t)apb * per_atom, s, p);
 }
 
 template <typename R, int NR, int NA>
@@ -884,18 +869,16 @@ void launch_orders(int kind, const DescParams& p, hipStream_t s) {
   // Lanes per atom from the expected number of angular neighbours within R_a:
   // narrow groups keep the cross-lane reductions short for sparse shells
   // (water: ~30), wide ones give crowded shells (dense amorphous: ~110)
-  // enough lanes.  The backward pass gives one lane per angular entry.
-  const int na = p.ang_hint > 0 ? p.ang_hint : p.cap_ang;
-  if (na > 48) {
-    launch_kind<R, NR, NA, 64>(kind, p, s);
-  } else if (kind == BWD) {
-    if (na > 32)
-      launch_kind<R, NR, NA, 64>(kind, p, s);
-    else
-      launch_kind<R, NR, NA, 32>(kind, p, s);
-  } else {
-    launch_kind<R, NR, NA, 16>(kind, p, s);
+  // enough lanes.  The force pass takes a wavefront per atom.
+  if (kind == BWD) {
+    launch_bwd<R, NR, NA>(p, s);
+    return;
   }
+  const int na = p.ang_hint > 0 ? p.ang_hint : p.cap_ang;
+  if (na > 48)
+    launch_kind<R, NR, NA, 64>(kind, p, s);
+  else
+    launch_kind<R, NR, NA, 16>(kind, p, s);
 }
 
 #define AENET_ORDERS(X) \

@@ -73,6 +73,7 @@ struct aenet_ctx {
   int pbc[3] = {1, 1, 1};
   int n_cells = 0;
   int cap = 0, cap_ang = 0;
+  int cap_user = 0, cap_ang_user = 0;  // capacities set by the caller (0: estimate)
   int ang_mean = 0;  // expected mean number of neighbours within R_a (densest structure)
   bool nbr_valid = false;
 
@@ -377,6 +378,10 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
     }
     c->ang_mean = (int)(mean_a + 0.5);
     c->cap_ang = std::min(c->cap, pad_to((int)(est_a * 1.3) + 8, 8));
+    if (c->cap_user > 0) {
+      c->cap = c->cap_user;
+      c->cap_ang = c->cap_ang_user;
+    }
   }
   return AENET_OK;
 }
@@ -390,7 +395,7 @@ aenet_status ensure_rows(aenet_ctx* c) {
   return AENET_OK;
 }
 
-NbrParams nbr_params(aenet_ctx* c, const int* cond) {
+NbrParams nbr_params(aenet_ctx* c, int* cond) {
   NbrParams p{};
   p.n = (int)c->n;
   p.pos = c->d_pos.as<double>();
@@ -487,7 +492,10 @@ aenet_status read_flags(aenet_ctx* c, hipStream_t s, int* hf) {
 aenet_status flag_status(aenet_ctx* c, int f) {
   if (f & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
   if (f & kFlagOverlap) return fail(c, AENET_E_OVERLAP, "two atoms (or an atom and an image) coincide");
-  if (f & kFlagReverse) return fail(c, AENET_E_DEVICE, "internal error: neighbour list not symmetric");
+  // a row truncated by a capacity overflow also leaves entries without a
+  // reverse; the caller grows the rows and builds again
+  if ((f & kFlagReverse) && !(f & kFlagOverflow))
+    return fail(c, AENET_E_DEVICE, "internal error: neighbour list not symmetric");
   return AENET_OK;
 }
 
@@ -567,7 +575,12 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
 aenet_status build_checked(aenet_ctx* c, hipStream_t s) {
   TRY(ensure_rows(c));
   for (int attempt = 0; attempt < 4; ++attempt) {
-    HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+    // flags[0] keeps what the input gather found (non-finite input) on the
+    // first attempt; a retry follows a clean flag word
+    if (attempt == 0)
+      HIP_TRY(c, hipMemsetAsync(c->d_flags.as<int>() + 1, 0, 7 * sizeof(int), s));
+    else
+      HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
     build_neighbors_timed(c, nbr_params(c, nullptr), s);
     HIP_TRY(c, hipGetLastError());
     int hf[8];
@@ -957,8 +970,12 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
       }
       int hf[8];
       TRY(read_flags(c, s, hf));
-      TRY(flag_status(c, hf[0]));
-      if (!(hf[0] & kFlagOverflow)) break;
+      if (!(hf[0] & kFlagOverflow)) {
+        TRY(flag_status(c, hf[0]));
+        break;
+      }
+      // truncated rows make the rest of the chunk meaningless, whatever else
+      // it flagged: grow the rows and redo the chunk from its checkpoint
       if (attempt >= 3) return fail(c, AENET_E_DEVICE, "neighbour capacity retries exhausted");
       TRY(grow_caps(c, hf));
       launch_copy_f64(3 * (int64_t)N, c->d_save_pos.as<double>(), c->d_pos.as<double>(), s);
@@ -1111,6 +1128,21 @@ aenet_status aenet_get_stats(const aenet_ctx* c, aenet_stats* out) {
 aenet_status aenet_set_rebuild_every(aenet_ctx* c, int k) {
   if (!c || k < 1) return AENET_E_INVALID;
   c->rebuild_every = k;
+  return AENET_OK;
+}
+
+aenet_status aenet_set_capacity(aenet_ctx* c, int row_capacity, int ang_capacity) {
+  TRY(check_ctx(c));
+  if (row_capacity == 0 && ang_capacity == 0) {
+    c->cap_user = c->cap_ang_user = 0;
+  } else {
+    if (ang_capacity < 1 || row_capacity < ang_capacity || ang_capacity > 700 || row_capacity > 4096)
+      return fail(c, AENET_E_INVALID, "need 1 <= ang_capacity <= row_capacity, ang_capacity <= 700, row_capacity <= 4096");
+    c->cap_user = row_capacity;
+    c->cap_ang_user = ang_capacity;
+  }
+  c->cap = 0;  // applied at the next call's set-up
+  c->nbr_valid = false;
   return AENET_OK;
 }
 

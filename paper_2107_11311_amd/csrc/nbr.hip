@@ -48,6 +48,14 @@ __global__ void k_set_int(int* dst, int v) {
 
 __global__ void k_zero(NbrParams p) {
   if (skip(p)) return;
+  // Inside an MD chunk an overflowed build means the chunk is redone with
+  // longer rows: later builds of the chunk are dropped (their request is
+  // withdrawn, so the rest of this build skips too), which keeps the row
+  // maxima that size the retry those of the build that overflowed.
+  if (p.cond && (p.flags[0] & kFlagOverflow)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.cond = 0;
+    return;
+  }
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < p.n_cells) {
     p.cell_count[c] = 0;

@@ -158,6 +158,73 @@ def test_error_paths(A):
     assert np.isfinite(E)
 
 
+def test_nonfinite_device_input(A):
+    """A NaN in device-resident positions is reported, not computed with."""
+    import torch
+    s = I.make_system("water64")
+    ctx = A.Context(I.load_model("water64"), "fp64")
+    p = torch.from_numpy(s.pos.copy()).to("cuda:0")
+    p[11, 2] = float("nan")
+    F = torch.zeros_like(p)
+    et = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(A.AenetError) as e:
+        ctx.energy_forces_dev(p, s.species, s.box, s.pbc, et, None, F)
+    assert e.value.code == A.AENET_E_NONFINITE
+    E, _, _ = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
+    assert np.isfinite(E)
+
+
+def test_capacity_retry_forces(A):
+    """Rows far too short for the first build: the build overflows, the rows
+    grow and the build is redone, with the same result as estimated rows."""
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    E0, Ea0, F0 = A.Context(m, "fp64").energy_forces(s.pos, s.species, s.box, s.pbc)
+    ctx = A.Context(m, "fp64")
+    ctx.set_capacity(12, 6)
+    E1, Ea1, F1 = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
+    st = ctx.stats()
+    assert st["n_capacity_retries"] >= 1 and st["row_capacity"] > 12 and st["ang_capacity"] > 6
+    assert abs(E1 - E0) <= 1e-13 * abs(E0)
+    np.testing.assert_allclose(Ea1, Ea0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(F1, F0, rtol=0, atol=1e-12)
+    with pytest.raises(A.AenetError) as e:
+        ctx.set_capacity(8, 9)
+    assert e.value.code == A.AENET_E_INVALID
+
+
+def test_capacity_retry_md(A):
+    """Rows sized to exactly the first configuration: as atoms move, a later
+    build overflows inside an MD chunk; the chunk is redone from its
+    checkpoint with longer rows and the trajectory stays on the one run with
+    estimated rows."""
+    # with this seed the largest angular shell (42 entries within R_a + skin
+    # at the start) has grown by step 7 and stays above 42 (checked with the
+    # oracle's MD), so the build at step 10 at the latest overflows and the
+    # chunk of steps 1..10 is redone
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    v = I.maxwell_boltzmann(m.masses[s.species], 600.0, 12)
+    probe = A.Context(m, "fp64", skin=0.3)
+    probe.energy_forces(s.pos, s.species, s.box, s.pbc)
+    st0 = probe.stats()
+    ref = A.Context(m, "fp64", skin=0.3)
+    ref.set_rebuild_every(10)
+    p0, v0, ep0, ek0, _ = ref.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 40)
+    ctx = A.Context(m, "fp64", skin=0.3)
+    ctx.set_rebuild_every(10)
+    ctx.set_capacity(st0["max_neighbors"], st0["max_angular"])
+    p1, v1, ep1, ek1, _ = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 40)
+    st = ctx.stats()
+    dp = float(np.abs((p1 - p0 + s.box / 2) % s.box - s.box / 2).max())
+    dv = float(np.abs(v1 - v0).max() / np.abs(v0).max())
+    print(f"capacity retry md: retries={st['n_capacity_retries']} rows {st0['max_neighbors']}->"
+          f"{st['row_capacity']} ang {st0['max_angular']}->{st['ang_capacity']} dpos={dp:.3e} dvel={dv:.3e}")
+    assert st["n_capacity_retries"] >= 1
+    assert dp < 1e-9 and dv < 1e-9
+    assert abs(ep1 + ek1 - ep0 - ek0) < 1e-10 * abs(ep0 + ek0)
+
+
 def test_empty_input(A):
     ctx = A.Context(I.load_model("water64"), "fp64")
     E, Ea, F = ctx.energy_forces(np.zeros((0, 3)), np.zeros(0, np.int32), [12.42] * 3, (1, 1, 1))
