@@ -80,8 +80,10 @@ struct DescParams {
   int ldG;               // row stride of G / dE/dG
   void* G;               // [n x ldG] (float or double)
   const void* gG;        // dE/dG [n x ldG]
-  void* pg;              // [n*cap*3] per-entry dE_i/dd
-  double* Fself;         // [n*3]  sum_e pg
+  const int* rev;        // [n*cap] global index of the reverse entry
+  void* pg;              // [n*cap*3] dE_i/dd_e, stored at the slot of the
+                         // reverse entry: pg[rev(i,e)] (see the force gather)
+  double* Fself;         // [n*3]  sum_e dE_i/dd_e
   const double* adj;     // [n*3] JVP direction (loss adjoint of the forces)
   void* U;               // [n x ldG] JVP output
   int* flags;
@@ -142,8 +144,10 @@ void launch_scatter_out(int n, const int* perm, const double* src3, double* dst3
                         const double* src1, double* dst1, hipStream_t s);
 void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
                              const BoxInfo* boxes, const int pbc[3], double* dst, hipStream_t s);
-// F = Fself - sum_e pg[rev[e]]; prec of pg: 0 double, 1 float.  If vel != NULL also v += c*F/m.
-void launch_force_gather(int prec, int n, int cap, const int* nnb, const int* rev, const void* pg,
+// F_q = Fself_q - sum_{f < nnb[q]} pg[q, f] (pg holds at slot (q, f) the
+// gradient of the entry whose reverse is (q, f)); prec of pg: 0 double,
+// 1 float.  If vel != NULL also v += c*F/m.
+void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
                          const int* species, double half_dt, hipStream_t s);
 void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,

@@ -403,7 +403,8 @@ __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
 }
 
 // ------------------------------------------------------------------ backward
-// pg[i, e] = dE_i / d d_e for every entry of atom i; Fself[i] = sum_e pg[i, e].
+// dE_i / d d_e for every entry e of atom i, stored at the slot of the reverse
+// entry (pg[rev(i, e)]) for the force gather; Fself[i] = sum_e dE_i / d d_e.
 // One wavefront per atom (the atom index is uniform over the wave):
 //   compaction of the entries within R_a into LDS (unit vector, f_c, f_c',
 //     species weight, 1/r);
@@ -591,7 +592,8 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     grt[a] = active ? gG[a] : R(0);
     grw[a] = (active && p.weighted) ? gG[T2 + a] : R(0);
   }
-  R* pg = reinterpret_cast<R*>(p.pg) + (size_t)(active ? i : 0) * p.cap * 3;
+  R* pg = reinterpret_cast<R*>(p.pg);
+  const int* rev = p.rev + (size_t)(active ? i : 0) * p.cap;
   double sx = 0.0, sy = 0.0, sz = 0.0;
   // one entry per lane per iteration, the next one's position loaded ahead;
   // entries beyond R_r (skin) get a zero gradient through a zero weight, and
@@ -630,9 +632,14 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
       }
     }
     if (he) {
-      pg[3 * (size_t)e] = px;
-      pg[3 * (size_t)e + 1] = py;
-      pg[3 * (size_t)e + 2] = pz;
+      // stored at the reverse entry's slot, where the force gather of the
+      // neighbour reads it (no slot if the list was flagged asymmetric)
+      const int dst = rev[e];
+      if (dst >= 0) {
+        pg[3 * (size_t)dst] = px;
+        pg[3 * (size_t)dst + 1] = py;
+        pg[3 * (size_t)dst + 2] = pz;
+      }
       sx += (double)px;
       sy += (double)py;
       sz += (double)pz;

@@ -444,6 +444,7 @@ DescParams desc_params(aenet_ctx* c) {
   p.ldG = c->ldG;
   p.G = c->d_G.p;
   p.gG = c->d_gG.p;
+  p.rev = c->d_rev.as<int>();
   p.pg = c->d_pg.p;
   p.Fself = c->d_Fself.as<double>();
   p.adj = c->d_adj.as<double>();
@@ -562,8 +563,7 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
     launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s);
     prof_end(c, s);
     prof_begin(c, s, AENET_K_FORCE_GATHER);
-    launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nnb.as<int>(), c->d_rev.as<int>(),
-                        c->d_pg.p, c->d_Fself.as<double>(), c->d_F.as<double>(), vel,
+    launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nnb.as<int>(), c->d_pg.p, c->d_Fself.as<double>(), c->d_F.as<double>(), vel,
                         c->d_invmk.as<double>(), c->d_species.as<int>(), half_dt, s);
     prof_end(c, s);
   }

@@ -59,26 +59,28 @@ __global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, co
   }
 }
 
-// F_i = sum_e pg[i,e] - sum_e pg[rev(i,e)]: the first sum was formed by the
-// descriptor backward kernel (Fself); the second gathers the reverse entries.
+// F_q = sum_e dE_q/dd_e - sum over the entries (i -> q) of dE_i/dd: the first
+// sum was formed by the force pass (Fself); the second is row q of pg, where
+// the force pass stored the gradient of every entry at the slot of its reverse
+// entry, so this gather reads each row contiguously.
+constexpr int kGatherLanes = 16;  // lanes per atom in the force gather
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nnb, const int* rev,
-                                                      const R* pg, const double* Fself, double* F,
+__global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nnb, const R* pg,
+                                                      const double* Fself, double* F,
                                                       double* vel, const double* inv_mass_k,
                                                       const int* species, double half_dt) {
-  constexpr int LPA = 16;
+  constexpr int LPA = kGatherLanes;
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
   const int i = blockIdx.x * (blockDim.x / LPA) + g;
   double sx = 0.0, sy = 0.0, sz = 0.0;
   const int nn = i < n ? nnb[i] : 0;
+  const R* row = pg + (size_t)(i < n ? i : 0) * cap * 3;
 #pragma unroll 4
   for (int e = l; e < nn; e += LPA) {
-    const int r = rev[(size_t)i * cap + e];
-    if (r >= 0) {
-      sx += (double)pg[3 * (size_t)r];
-      sy += (double)pg[3 * (size_t)r + 1];
-      sz += (double)pg[3 * (size_t)r + 2];
-    }
+    sx += (double)row[3 * e];
+    sy += (double)row[3 * e + 1];
+    sz += (double)row[3 * e + 2];
   }
 #pragma unroll
   for (int o = LPA / 2; o > 0; o >>= 1) {
@@ -241,16 +243,16 @@ void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const in
                        boxes, pbc[0], pbc[1], pbc[2], dst);
 }
 
-void launch_force_gather(int prec, int n, int cap, const int* nnb, const int* rev, const void* pg,
+void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
                          const int* species, double half_dt, hipStream_t s) {
   if (n <= 0) return;
-  const dim3 grid(nblk(n, 16)), block(256);
+  const dim3 grid(nblk(n, 256 / kGatherLanes)), block(256);
   if (prec == 0)
-    hipLaunchKernelGGL(k_force_gather<double>, grid, block, 0, s, n, cap, nnb, rev,
+    hipLaunchKernelGGL(k_force_gather<double>, grid, block, 0, s, n, cap, nnb,
                        (const double*)pg, Fself, F, vel, inv_mass_k, species, half_dt);
   else
-    hipLaunchKernelGGL(k_force_gather<float>, grid, block, 0, s, n, cap, nnb, rev,
+    hipLaunchKernelGGL(k_force_gather<float>, grid, block, 0, s, n, cap, nnb,
                        (const float*)pg, Fself, F, vel, inv_mass_k, species, half_dt);
 }
 
