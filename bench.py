@@ -258,6 +258,9 @@ def main():
                     help="oracle energy+force calls on the full box for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--student", action="store_true", help="run the distilled-student pipeline instead")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes 20 times (the reference "
+                         "kernel that scales the HBM counters of a profile)")
     ap.add_argument("--snapshots", type=int, default=20000)
     ap.add_argument("--stride", type=int, default=4)
     ap.add_argument("--train-steps", type=int, default=4000)
@@ -273,6 +276,15 @@ def main():
         sys.exit(2)
     if args.student:
         run_student(args)
+        return
+    if args.copy_bytes > 0:
+        import torch
+        x = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(20):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 8, "launches": 20}))
         return
 
     import numpy as np

@@ -147,9 +147,23 @@ void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const in
 // F_q = Fself_q - sum_{f < nnb[q]} pg[q, f] (pg holds at slot (q, f) the
 // gradient of the entry whose reverse is (q, f)); prec of pg: 0 double,
 // 1 float.  If vel != NULL also v += c*F/m.
+// The opening half kick and drift of the next MD step, fused into the force
+// gather of this one (pos == NULL: none): v += c F (again); r += dt v; the
+// rebuild flag of the next step is raised when an atom moved more than
+// skin/2 since the last build (or always if force_rebuild), and the flag of
+// the step after it is cleared.
+struct DriftArgs {
+  double* pos;
+  const double* pos_ref;
+  double dt, half_skin2;
+  int* rebuild_flag;
+  int* clear_flag;
+  int force_rebuild;
+};
 void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
-                         const int* species, double half_dt, hipStream_t s);
+                         const int* species, double half_dt, const DriftArgs& next,
+                         hipStream_t s);
 void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
                      const double* inv_mass_k, const int* species, double half_dt, double dt,
                      double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild,

@@ -548,7 +548,8 @@ void build_neighbors_timed(aenet_ctx* c, const NbrParams& p, hipStream_t s) {
 }
 
 // descriptors -> networks -> forces (internal order).  vel != NULL applies the closing half kick.
-aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, double half_dt) {
+aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, double half_dt,
+                     const DriftArgs* next = nullptr) {
   if (c->n == 0) return AENET_OK;
   DescParams dp = desc_params(c);
   prof_begin(c, s, AENET_K_DESC_FWD);
@@ -564,7 +565,8 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
     prof_end(c, s);
     prof_begin(c, s, AENET_K_FORCE_GATHER);
     launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nnb.as<int>(), c->d_pg.p, c->d_Fself.as<double>(), c->d_F.as<double>(), vel,
-                        c->d_invmk.as<double>(), c->d_species.as<int>(), half_dt, s);
+                        c->d_invmk.as<double>(), c->d_species.as<int>(), half_dt,
+                        next ? *next : DriftArgs{}, s);
     prof_end(c, s);
   }
   HIP_TRY(c, hipGetLastError());
@@ -955,18 +957,37 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
     HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
     bool force_first = false;
     for (int attempt = 0;; ++attempt) {
+      // the opening half kick and drift of a step are fused into the force
+      // gather of the step before it, except for the first step of a chunk
+      auto drift_args = [&](int step, bool force) {
+        DriftArgs d{};
+        d.pos = c->d_pos.as<double>();
+        d.pos_ref = c->d_pos_ref.as<double>();
+        d.dt = dt;
+        d.half_skin2 = hs2;
+        d.rebuild_flag = flags + 3 + (step & 1);
+        d.clear_flag = flags + 3 + ((step + 1) & 1);
+        d.force_rebuild = force ? 1 : 0;
+        return d;
+      };
       for (int k = 0; k < len; ++k) {
         const int step = t + k + 1;  // 1-based index of this step
         int* rb = flags + 3 + (step & 1);
-        int* other = flags + 3 + ((step + 1) & 1);
-        const int force = (step % K == 0) || (force_first && k == 0);
-        prof_begin(c, s, AENET_K_INTEGRATE);
-        launch_vv_drift(N, c->d_pos.as<double>(), c->d_vel.as<double>(), c->d_F.as<double>(),
-                        c->d_pos_ref.as<double>(), c->d_invmk.as<double>(), c->d_species.as<int>(),
-                        half_dt, dt, hs2, rb, other, force, s);
-        prof_end(c, s);
+        if (k == 0) {
+          const int force = (step % K == 0) || force_first;
+          prof_begin(c, s, AENET_K_INTEGRATE);
+          launch_vv_drift(N, c->d_pos.as<double>(), c->d_vel.as<double>(), c->d_F.as<double>(),
+                          c->d_pos_ref.as<double>(), c->d_invmk.as<double>(), c->d_species.as<int>(),
+                          half_dt, dt, hs2, rb, flags + 3 + ((step + 1) & 1), force, s);
+          prof_end(c, s);
+        }
         build_neighbors_timed(c, nbr_params(c, rb), s);
-        TRY(compute(c, s, true, c->d_vel.as<double>(), half_dt));
+        if (k + 1 < len) {
+          const DriftArgs next = drift_args(step + 1, (step + 1) % K == 0);
+          TRY(compute(c, s, true, c->d_vel.as<double>(), half_dt, &next));
+        } else {
+          TRY(compute(c, s, true, c->d_vel.as<double>(), half_dt));
+        }
       }
       int hf[8];
       TRY(read_flags(c, s, hf));

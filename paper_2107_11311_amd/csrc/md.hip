@@ -69,7 +69,8 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nnb, const R* pg,
                                                       const double* Fself, double* F,
                                                       double* vel, const double* inv_mass_k,
-                                                      const int* species, double half_dt) {
+                                                      const int* species, double half_dt,
+                                                      DriftArgs next) {
   constexpr int LPA = kGatherLanes;
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
   const int i = blockIdx.x * (blockDim.x / LPA) + g;
@@ -88,19 +89,31 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
     sy += __shfl_xor(sy, o, LPA);
     sz += __shfl_xor(sz, o, LPA);
   }
+  if (next.pos && blockIdx.x == 0 && threadIdx.x == 0) {
+    *next.clear_flag = 0;
+    if (next.force_rebuild) *next.rebuild_flag = 1;
+  }
   if (i < n && l == 0) {
-    const double fx = Fself[3 * (size_t)i] - sx;
-    const double fy = Fself[3 * (size_t)i + 1] - sy;
-    const double fz = Fself[3 * (size_t)i + 2] - sz;
-    F[3 * (size_t)i] = fx;
-    F[3 * (size_t)i + 1] = fy;
-    F[3 * (size_t)i + 2] = fz;
-    if (vel) {
-      const double c = half_dt * inv_mass_k[species[i]];
-      vel[3 * (size_t)i] += c * fx;
-      vel[3 * (size_t)i + 1] += c * fy;
-      vel[3 * (size_t)i + 2] += c * fz;
+    const double f[3] = {Fself[3 * (size_t)i] - sx, Fself[3 * (size_t)i + 1] - sy,
+                         Fself[3 * (size_t)i + 2] - sz};
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const size_t k = 3 * (size_t)i + a;
+      F[k] = f[a];
+      if (vel) {
+        const double c = half_dt * inv_mass_k[species[i]];
+        double v = vel[k] + c * f[a];        // closing half kick of this step
+        if (next.pos) {
+          v = v + c * f[a];                  // opening half kick of the next step
+          const double x = next.pos[k] + next.dt * v;
+          next.pos[k] = x;
+          const double dd = x - next.pos_ref[k];
+          d2 += dd * dd;
+        }
+        vel[k] = v;
+      }
     }
+    if (next.pos && !(d2 <= next.half_skin2) && *next.rebuild_flag == 0) *next.rebuild_flag = 1;
   }
 }
 
@@ -245,15 +258,16 @@ void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const in
 
 void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
-                         const int* species, double half_dt, hipStream_t s) {
+                         const int* species, double half_dt, const DriftArgs& next,
+                         hipStream_t s) {
   if (n <= 0) return;
   const dim3 grid(nblk(n, 256 / kGatherLanes)), block(256);
   if (prec == 0)
     hipLaunchKernelGGL(k_force_gather<double>, grid, block, 0, s, n, cap, nnb,
-                       (const double*)pg, Fself, F, vel, inv_mass_k, species, half_dt);
+                       (const double*)pg, Fself, F, vel, inv_mass_k, species, half_dt, next);
   else
     hipLaunchKernelGGL(k_force_gather<float>, grid, block, 0, s, n, cap, nnb,
-                       (const float*)pg, Fself, F, vel, inv_mass_k, species, half_dt);
+                       (const float*)pg, Fself, F, vel, inv_mass_k, species, half_dt, next);
 }
 
 void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,

@@ -158,13 +158,21 @@ __host__ __device__ inline size_t act_offset(const MlpParams& p, int l) {
   return o;
 }
 
+// Forward and input-gradient pass of one 16-atom tile by kMlpWaves
+// wavefronts: the 16-column output blocks of every layer are dealt out over
+// the waves (the MFMA chains of a tile run side by side), with a block
+// barrier between layers.
+constexpr int kMlpWaves = 4;
+
 template <int PREC>
-__global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
   typedef typename Mt<PREC>::T T;
   typedef typename Mt<PREC>::B Bt;
+  constexpr int NT = 64 * kMlpWaves;  // threads per tile
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const TileInfo ti = tile_info(p, blockIdx.x);
   const MlpNet& net = p.net[ti.species];
   const int L = p.n_layers;
@@ -179,17 +187,17 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
     const T* sc = reinterpret_cast<const T*>(net.scale);
     const int w0 = p.wp[0], D = p.w[0];
     // all loads of the tile issued before any use (16 x w0 <= 16 x 64 elements)
-    constexpr int IT = 16 * kMaxWidth / 64;
+    constexpr int IT = 16 * kMaxWidth / NT;
     T v[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int idx = lane + 64 * it;
+      const int idx = tid + NT * it;
       const int r = idx / w0, c = idx % w0;
       v[it] = (idx < 16 * w0 && r < ti.count && c < D) ? G[(size_t)(ti.first + r) * p.ldG + c] : T(0);
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int idx = lane + 64 * it;
+      const int idx = tid + NT * it;
       const int r = idx / w0, c = idx % w0;
       if (idx < 16 * w0) lds[r * (w0 + 1) + c] = (r < ti.count && c < D) ? (v[it] - sh[c]) * sc[c] : T(0);
     }
@@ -204,7 +212,7 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
     const Bt* Bp = reinterpret_cast<const Bt*>(net.wf[l]);
     const T* bias = reinterpret_cast<const T*>(net.bias[l]);
     const int act = p.act[l - 1];
-    for (int nb = 0; nb < N / 16; ++nb) {
+    for (int nb = wave; nb < N / 16; nb += kMlpWaves) {
       auto acc = mfma_block<PREC>(X, K + 1, K, Bp, nb, lane);
       const int col = nb * 16 + (lane & 15);
 #pragma unroll
@@ -220,16 +228,16 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
   const T* XL = lds + act_offset(p, L - 1);
   const int KL = p.wp[L - 1];
   const T* wl = reinterpret_cast<const T*>(net.wlast);
-  if (lane < 16) {
+  if (tid < 16) {
     T e = T(0);
-    for (int k = 0; k < KL; ++k) e += XL[lane * (KL + 1) + k] * wl[k];
-    if (lane < ti.count) p.E[ti.first + lane] = (double)e + net.blast + net.e_offset;
+    for (int k = 0; k < KL; ++k) e += XL[tid * (KL + 1) + k] * wl[k];
+    if (tid < ti.count) p.E[ti.first + tid] = (double)e + net.blast + net.e_offset;
   }
   if (!p.gG) return;
 
   // back-propagation to the input (the output layer is linear; X_{L-1} was
   // produced by the activation of layer L-1, none if L == 1)
-  for (int idx = lane; idx < 16 * KL; idx += 64) {
+  for (int idx = tid; idx < 16 * KL; idx += NT) {
     const int r = idx / KL, c = idx % KL;
     const T x = XL[r * (KL + 1) + c];
     D0[r * DLD + c] = L >= 2 ? wl[c] * act_d1<T>(p.act[L - 2], x) : wl[c];
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
   T* gout = reinterpret_cast<T*>(p.gG);
   const T* sc = reinterpret_cast<const T*>(net.scale);
   if (L == 1) {
-    for (int idx = lane; idx < 16 * p.wp[0]; idx += 64) {
+    for (int idx = tid; idx < 16 * p.wp[0]; idx += NT) {
       const int r = idx / p.wp[0], c = idx % p.wp[0];
       if (r < ti.count && c < p.w[0]) gout[(size_t)(ti.first + r) * p.ldG + c] = Dcur[r * DLD + c] * sc[c];
     }
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(64) void k_mlp(MlpParams p) {
     const Bt* Bp = reinterpret_cast<const Bt*>(net.wb[l]);
     const T* Xp = lds + act_offset(p, l - 1);
     const int actp = l >= 2 ? p.act[l - 2] : 0;
-    for (int nb = 0; nb < N / 16; ++nb) {
+    for (int nb = wave; nb < N / 16; nb += kMlpWaves) {
       auto acc = mfma_block<PREC>(Dcur, DLD, K, Bp, nb, lane);
       const int col = nb * 16 + (lane & 15);
 #pragma unroll
@@ -511,12 +519,13 @@ size_t mlp_train_lds_bytes(int prec, const MlpParams& p) {
 void launch_mlp(int prec, const MlpParams& p, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return;
   const size_t lds = mlp_lds_bytes(prec, p);
+  const dim3 block(64 * kMlpWaves);
   if (prec == 0)
-    hipLaunchKernelGGL(k_mlp<0>, dim3(n_tiles), dim3(64), lds, s, p);
+    hipLaunchKernelGGL(k_mlp<0>, dim3(n_tiles), block, lds, s, p);
   else if (prec == 1)
-    hipLaunchKernelGGL(k_mlp<1>, dim3(n_tiles), dim3(64), lds, s, p);
+    hipLaunchKernelGGL(k_mlp<1>, dim3(n_tiles), block, lds, s, p);
   else
-    hipLaunchKernelGGL(k_mlp<2>, dim3(n_tiles), dim3(64), lds, s, p);
+    hipLaunchKernelGGL(k_mlp<2>, dim3(n_tiles), block, lds, s, p);
 }
 
 void launch_mlp_train(int prec, const MlpParams& p, int n_blocks, hipStream_t s) {
