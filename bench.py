@@ -29,8 +29,10 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK = 78.6e12     # MI355X vector FP64, FLOP/s
 FP32_VALU_PEAK = 157.3e12    # MI355X vector FP32 (packed), FLOP/s
 WORKLOAD = "water4096"
-KERNEL_SOURCES = {"desc_fwd": "desc.hip", "desc_bwd": "desc.hip", "network": "mlp.hip",
-                  "neighbor": "nbr.hip", "force_gather": "md.hip", "integrate": "md.hip"}
+KERNEL_SOURCES = {"desc_fwd": ["desc.hip", "desc_dev.h"], "desc_bwd": ["desc.hip", "desc_dev.h"],
+                  "network": ["mlp.hip", "mlp_dev.h"],
+                  "fwd_network": ["fused.hip", "desc_dev.h", "mlp_dev.h"],
+                  "neighbor": ["nbr.hip"], "force_gather": ["md.hip"], "integrate": ["md.hip"]}
 
 
 def algorithmic_flops(kernel, nr_order, na_order, n_r, n_a, widths):
@@ -50,6 +52,9 @@ def algorithmic_flops(kernel, nr_order, na_order, n_r, n_a, widths):
     if kernel == "network":
         mac = sum(widths[i] * widths[i + 1] for i in range(len(widths) - 1))
         return 4.0 * mac + 4.0 * sum(widths[1:-1])  # forward + input gradient, tanh + derivative
+    if kernel == "fwd_network":
+        return (algorithmic_flops("desc_fwd", nr_order, na_order, n_r, n_a, widths)
+                + algorithmic_flops("network", nr_order, na_order, n_r, n_a, widths))
     if kernel == "force_gather":
         return 3.0 * n_r * 1.0
     return 0.0
@@ -64,9 +69,12 @@ def mean_counts(pos, box, rr, ra):
     return float(nr), float(na)
 
 
-def source_hash(name):
-    with open(os.path.join(ROOT, "paper_2107_11311_amd", "csrc", name), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(names):
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2107_11311_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(kernel, workload, precision):

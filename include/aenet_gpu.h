@@ -205,6 +205,12 @@ typedef struct {
 aenet_status aenet_get_stats(const aenet_ctx* ctx, aenet_stats* out);
 /* rebuild_every >= 1 (default 50). */
 aenet_status aenet_set_rebuild_every(aenet_ctx* ctx, int rebuild_every);
+/* Descriptor forward pass and networks in one kernel, per 16-atom tile
+ * (enable = 1, where it applies: up to 48 expected angular neighbours and
+ * 64 KiB of LDS per tile), or as two kernels (enable = 0).  The results are
+ * bitwise the same.  Default: 1 for AENET_FP32 and AENET_BF16, 0 for
+ * AENET_FP64 (no faster there). */
+aenet_status aenet_set_fused(aenet_ctx* ctx, int enable);
 /* Neighbour-row capacities used from the next call on: row_capacity entries
  * per atom within R_r + skin, ang_capacity of them within R_a + skin
  * (1 <= ang_capacity <= row_capacity, ang_capacity <= 700, row_capacity <=
@@ -227,7 +233,8 @@ typedef enum {
   AENET_K_DESC_BWD = 3,     /* force back-propagation to entry gradients */
   AENET_K_FORCE_GATHER = 4, /* deterministic force gather (+ closing half kick) */
   AENET_K_INTEGRATE = 5,    /* opening half kick + drift */
-  AENET_K_COUNT = 6
+  AENET_K_FWD_NETWORK = 6,  /* descriptor forward and networks in one kernel */
+  AENET_K_COUNT = 7
 } aenet_kernel_class;
 aenet_status aenet_set_profiling(aenet_ctx* ctx, int enable);
 aenet_status aenet_get_kernel_times(aenet_ctx* ctx, double* ms, int64_t* launches);

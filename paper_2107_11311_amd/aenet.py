@@ -28,8 +28,8 @@ EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor
            "aenet_get_params", "aenet_set_params", "aenet_supported_orders", "aenet_energy_forces",
            "aenet_energy_forces_dev", "aenet_energy_forces_batch_dev", "aenet_descriptors",
            "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_get_stats",
-           "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_profiling", "aenet_get_kernel_times"]
-KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate"]
+           "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_profiling", "aenet_get_kernel_times"]
+KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate", "fwd_network"]
 
 
 class AenetError(RuntimeError):
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
     L.aenet_get_stats.argtypes = [ctxp, C.POINTER(Stats)]
     L.aenet_set_rebuild_every.argtypes = [ctxp, C.c_int]
     L.aenet_set_capacity.argtypes = [ctxp, C.c_int, C.c_int]
+    L.aenet_set_fused.argtypes = [ctxp, C.c_int]
     L.aenet_set_profiling.argtypes = [ctxp, C.c_int]
     L.aenet_get_kernel_times.argtypes = [ctxp, _dp, _i64p]
     for name in EXPORTS:
@@ -235,6 +236,10 @@ class Context:
 
     def set_rebuild_every(self, k: int) -> None:
         self._check(self._lib.aenet_set_rebuild_every(self._h, int(k)))
+
+    def set_fused(self, on: bool) -> None:
+        """Descriptor forward pass and networks in one kernel (default) or two."""
+        self._check(self._lib.aenet_set_fused(self._h, 1 if on else 0))
 
     def set_capacity(self, row: int, ang: int) -> None:
         """Starting neighbour-row capacities (0, 0: estimate from the density)."""

@@ -130,6 +130,13 @@ struct MlpParams {
 };
 // prec: 0 fp64 (MFMA f64), 1 fp32 (MFMA f32), 2 bf16 operands (MFMA bf16, fp32 acc)
 size_t mlp_lds_bytes(int prec, const MlpParams& p);
+// descriptors and networks of every tile in one kernel (descriptors in double
+// for prec 0, float otherwise); dp.G may be NULL (descriptors stay on chip).
+// Returns false, launching nothing, where the fused kernel does not apply
+// (crowded angular shells, LDS); the caller then runs the two kernels.
+bool launch_fwd_mlp(int prec, int nr, int na, const DescParams& dp, const MlpParams& mp, int n_tiles,
+                    hipStream_t s);
+bool fwd_mlp_fits(int prec, const DescParams& dp, const MlpParams& mp);
 void launch_mlp(int prec, const MlpParams& p, int n_tiles, hipStream_t s);
 size_t mlp_train_lds_bytes(int prec, const MlpParams& p);
 void launch_mlp_train(int prec, const MlpParams& p, int n_blocks, hipStream_t s);

@@ -1,0 +1,406 @@
+// desc_dev.h -- device code shared by the descriptor kernels and the fused
+// descriptor + network kernel: cross-lane reductions, the cosine cutoff
+// (Eq. 5), neighbour loads, Chebyshev series, and the forward pass of one
+// atom's descriptor (Eqs. 3-6).
+#pragma once
+#include "aenet_internal.h"
+
+// (radial order, angular order) pairs compiled in; every descriptor kernel
+// is instantiated for each pair
+#define AENET_ORDERS(X) \
+  X(10, 4)              \
+  X(16, 8)              \
+  X(18, 6)              \
+  X(6, 2)               \
+  X(5, 3)               \
+  X(4, 2)
+
+namespace aenet {
+
+namespace {
+
+template <int LPA, typename T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+  for (int o = LPA / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPA);
+  return v;
+}
+
+template <int LPA>
+__device__ inline uint64_t group_ballot(bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (LPA == 64) return m;
+  const int g = (threadIdx.x & 63) / LPA;
+  return (m >> (g * LPA)) & ((1ull << LPA) - 1ull);
+}
+
+// Reduce-scatter over a group of LPA lanes: on entry every lane holds N
+// partial sums v[0..N) (N a power of two); on exit lane l holds the group sum
+// of component rs_comp<LPA, N>(l, i) in v[i] for i < max(N / LPA, 1).  Each
+// halving step sends the half the lane gives up to its partner, so about N
+// values cross lanes instead of N log2(LPA) for a full butterfly.  When
+// N < LPA the lanes that differ above bit log2(N) first add their vectors,
+// and lanes l and l + N end with the same component.
+template <int LPA, int N, typename T>
+__device__ inline void group_reduce_scatter(T (&v)[N], int l) {
+  if constexpr (LPA > N) {
+#pragma unroll
+    for (int mask = LPA / 2; mask >= N; mask >>= 1)
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], mask, LPA);
+  }
+  constexpr int W = LPA < N ? LPA : N;
+#pragma unroll
+  for (int mask = W / 2, h = N / 2; mask > 0; mask >>= 1, h >>= 1) {
+    const bool up = (l & mask) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const T send = up ? v[k] : v[k + h];
+      const T keep = up ? v[k + h] : v[k];
+      v[k] = keep + __shfl_xor(send, mask, LPA);
+    }
+  }
+}
+
+template <int LPA, int N>
+__device__ inline int rs_comp(int l, int i) {
+  constexpr int W = LPA < N ? LPA : N;
+  return (N / W) * (l % W) + i;
+}
+
+constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
+
+template <typename R>
+__device__ inline R sqrt_r(R x);
+template <>
+__device__ inline double sqrt_r<double>(double x) { return sqrt(x); }
+template <>
+__device__ inline float sqrt_r<float>(float x) { return sqrtf(x); }
+
+constexpr double kPi = 3.14159265358979323846;
+
+// sin t and cos t for |t| <= pi/2 by their Taylor series in nested (Horner)
+// form; truncation below 1e-19 (double: terms to t^23 / t^24) or 1e-9
+// (float: terms to t^15 / t^14), i.e. under the rounding error of each type.
+template <typename R>
+__device__ inline void sincos_halfpi(R t, R* s, R* c);
+template <>
+__device__ inline void sincos_halfpi<double>(double t, double* s, double* c) {
+  const double u = t * t;
+  double a = 1.0 - u * (1.0 / 506.0);
+  a = 1.0 - u * (1.0 / 420.0) * a;
+  a = 1.0 - u * (1.0 / 342.0) * a;
+  a = 1.0 - u * (1.0 / 272.0) * a;
+  a = 1.0 - u * (1.0 / 210.0) * a;
+  a = 1.0 - u * (1.0 / 156.0) * a;
+  a = 1.0 - u * (1.0 / 110.0) * a;
+  a = 1.0 - u * (1.0 / 72.0) * a;
+  a = 1.0 - u * (1.0 / 42.0) * a;
+  a = 1.0 - u * (1.0 / 20.0) * a;
+  a = 1.0 - u * (1.0 / 6.0) * a;
+  *s = t * a;
+  double b = 1.0 - u * (1.0 / 552.0);
+  b = 1.0 - u * (1.0 / 462.0) * b;
+  b = 1.0 - u * (1.0 / 380.0) * b;
+  b = 1.0 - u * (1.0 / 306.0) * b;
+  b = 1.0 - u * (1.0 / 240.0) * b;
+  b = 1.0 - u * (1.0 / 182.0) * b;
+  b = 1.0 - u * (1.0 / 132.0) * b;
+  b = 1.0 - u * (1.0 / 90.0) * b;
+  b = 1.0 - u * (1.0 / 56.0) * b;
+  b = 1.0 - u * (1.0 / 30.0) * b;
+  b = 1.0 - u * (1.0 / 12.0) * b;
+  *c = 1.0 - u * 0.5 * b;
+}
+template <>
+__device__ inline void sincos_halfpi<float>(float t, float* s, float* c) {
+  const float u = t * t;
+  float a = 1.0f - u * (1.0f / 210.0f);
+  a = 1.0f - u * (1.0f / 156.0f) * a;
+  a = 1.0f - u * (1.0f / 110.0f) * a;
+  a = 1.0f - u * (1.0f / 72.0f) * a;
+  a = 1.0f - u * (1.0f / 42.0f) * a;
+  a = 1.0f - u * (1.0f / 20.0f) * a;
+  a = 1.0f - u * (1.0f / 6.0f) * a;
+  *s = t * a;
+  float b = 1.0f - u * (1.0f / 182.0f);
+  b = 1.0f - u * (1.0f / 132.0f) * b;
+  b = 1.0f - u * (1.0f / 90.0f) * b;
+  b = 1.0f - u * (1.0f / 56.0f) * b;
+  b = 1.0f - u * (1.0f / 30.0f) * b;
+  b = 1.0f - u * (1.0f / 12.0f) * b;
+  *c = 1.0f - u * 0.5f * b;
+}
+
+// sin and cos of pi r / R for 0 <= r < R (the cosine cutoff, Eq. 5): with
+// x = 2r/R - 1 in [-1, 1) and t = pi x / 2, pi r / R = t + pi/2, so
+// sin(pi r/R) = cos t and cos(pi r/R) = -sin t.
+template <typename R>
+__device__ inline void sincos_cut(R r, R two_over_R, R* sn, R* cs) {
+  const R t = R(0.5 * kPi) * (r * two_over_R - R(1));
+  R st, ct;
+  sincos_halfpi<R>(t, &st, &ct);
+  *sn = ct;
+  *cs = -st;
+}
+
+// displacement d = r_j + s L - r_i of a packed entry (always in double)
+__device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double xi0, double xi1,
+                                 double xi2, uint32_t en, double& d0, double& d1, double& d2) {
+  const int q = (int)(en & kAtomMask);
+  const int code = (int)(en >> kImgBits);
+  const double s0 = (double)(code % 3 - 1), s1 = (double)((code / 3) % 3 - 1), s2 = (double)(code / 9 - 1);
+  d0 = p.pos[3 * (size_t)q] + s0 * b.L[0] - xi0;
+  d1 = p.pos[3 * (size_t)q + 1] + s1 * b.L[1] - xi1;
+  d2 = p.pos[3 * (size_t)q + 2] + s2 * b.L[2] - xi2;
+  return q;
+}
+
+// A neighbour entry with its atom's position loaded (issued one loop
+// iteration ahead of its use so the gather latency hides behind the
+// arithmetic of the current iteration).
+struct NbrLoad {
+  int code;
+  double x, y, z, w;  // position and species weight of the neighbour atom
+};
+
+__device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t word) {
+  NbrLoad n;
+  const int q = (int)(word & kAtomMask);
+  n.code = (int)(word >> kImgBits);
+  n.x = p.pos[3 * (size_t)q];
+  n.y = p.pos[3 * (size_t)q + 1];
+  n.z = p.pos[3 * (size_t)q + 2];
+  n.w = p.tw[p.species[q]];
+  return n;
+}
+
+__device__ inline void nbr_disp(const NbrLoad& n, const BoxInfo& b, double xi0, double xi1, double xi2,
+                                double& d0, double& d1, double& d2) {
+  d0 = n.x + (double)(n.code % 3 - 1) * b.L[0] - xi0;
+  d1 = n.y + (double)((n.code / 3) % 3 - 1) * b.L[1] - xi1;
+  d2 = n.z + (double)(n.code / 9 - 1) * b.L[2] - xi2;
+}
+
+// S(x) = sum_{a=0..N} c_a T_a(x) and S'(x) by Clenshaw's recurrence, with
+// c_a = g[a] + w h[a] (the typed and weighted coefficients of one neighbour
+// or pair combined on the fly): b_a = c_a + 2x b_{a+1} - b_{a+2} and its
+// x-derivative b'_a = 2 b_{a+1} + 2x b'_{a+1} - b'_{a+2}, from
+// b_{N+1} = b_{N+2} = 0; then S = c_0 + x b_1 - b_2, S' = b_1 + x b'_1 - b'_2.
+// Five operations per order and only g, h live (instead of the values and
+// derivatives of both channels kept by forward recurrences).
+template <typename R, int N>
+__device__ inline void cheb_series_d(const R (&g)[N + 1], const R (&h)[N + 1], R w, R x, R* S,
+                                     R* dS) {
+  const R x2 = x + x;
+  R b1 = R(0), b2 = R(0), d1 = R(0), d2 = R(0);
+#pragma unroll
+  for (int a = N; a >= 1; --a) {
+    const R c = g[a] + w * h[a];
+    const R bk = x2 * b1 + (c - b2);
+    const R dk = x2 * d1 + (R(2) * b1 - d2);
+    b2 = b1;
+    b1 = bk;
+    d2 = d1;
+    d1 = dk;
+  }
+  *S = x * b1 + ((g[0] + w * h[0]) - b2);
+  *dS = x * d1 + (b1 - d2);
+}
+
+// ------------------------------------------------------------------ forward
+// Descriptor vector of atom i by group g (lanes l = 0..LPA-1) of the block;
+// the group's compaction buffers are at smem + g * 5 * cap_ang elements.  Every
+// group of the block must call it (it holds a block barrier).  The G
+// components are handed to out(c, value) (c < D, one lane per component).
+template <typename R, int NR, int NA, int LPA, typename Out>
+__device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, int g, int l,
+                                      unsigned char* smem, Out&& out) {
+  R* ux = reinterpret_cast<R*>(smem) + (size_t)g * p.cap_ang * 5;
+  R* uy = ux + p.cap_ang;
+  R* uz = uy + p.cap_ang;
+  R* fs = uz + p.cap_ang;
+  R* ws = fs + p.cap_ang;
+
+  R rt[NR + 1], rw[NR + 1], at[NA + 1], aw[NA + 1];
+#pragma unroll
+  for (int a = 0; a <= NR; ++a) rt[a] = rw[a] = R(0);
+#pragma unroll
+  for (int a = 0; a <= NA; ++a) at[a] = aw[a] = R(0);
+
+  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
+  const double xi0 = active ? p.pos[3 * (size_t)i] : 0.0;
+  const double xi1 = active ? p.pos[3 * (size_t)i + 1] : 0.0;
+  const double xi2 = active ? p.pos[3 * (size_t)i + 2] : 0.0;
+  const uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
+  const int nn = active ? p.nnb[i] : 0;
+  const int na = active ? p.nang[i] : 0;
+  const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
+  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
+  const R two_ra = R(2.0 / p.ra);
+
+  // radial terms, Eq. 3.  Two entries per lane per iteration give two
+  // independent recurrence chains; entries beyond R_r (skin) or past the end
+  // of the row are computed with weight 0 instead of branching.
+  // slots past the end of the row repeat its last entry (an empty row reads the
+  // atom itself, always in bounds) and are given weight 0
+  const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
+  auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
+  NbrLoad na_ = load_nbr(p, word(l)), nb_ = load_nbr(p, word(l + LPA));
+  uint32_t wa1 = word(l + 2 * LPA), wb1 = word(l + 3 * LPA);
+  for (int e = l; e < nn; e += 2 * LPA) {
+    const NbrLoad na1 = load_nbr(p, wa1), nb1 = load_nbr(p, wb1);
+    const uint32_t wa2 = word(e + 4 * LPA), wb2 = word(e + 5 * LPA);
+    const bool hb = e + LPA < nn;
+    double a0, a1, a2, b0, b1, b2;
+    nbr_disp(na_, b, xi0, xi1, xi2, a0, a1, a2);
+    nbr_disp(nb_, b, xi0, xi1, xi2, b0, b1, b2);
+    const R twa = R(na_.w), twb = R(nb_.w);
+    na_ = na1;
+    nb_ = nb1;
+    wa1 = wa2;
+    wb1 = wb2;
+    const bool va = a0 * a0 + a1 * a1 + a2 * a2 < rr2;
+    const bool vb = hb && (b0 * b0 + b1 * b1 + b2 * b2 < rr2);
+    const R ra = sqrt_r<R>(R(a0) * R(a0) + R(a1) * R(a1) + R(a2) * R(a2));
+    const R rb = sqrt_r<R>(R(b0) * R(b0) + R(b1) * R(b1) + R(b2) * R(b2));
+    const R xa = ra * inv_rr2 - R(1), xb = rb * inv_rr2 - R(1);
+    R sna, csa, snb, csb;
+    sincos_cut<R>(ra, inv_rr2, &sna, &csa);
+    sincos_cut<R>(rb, inv_rr2, &snb, &csb);
+    const R fa = va ? R(0.5) * (csa + R(1)) : R(0);
+    const R fb = vb ? R(0.5) * (csb + R(1)) : R(0);
+    const R wa = twa * fa, wb = twb * fb;
+    R ta0 = R(1), ta1 = xa, tb0 = R(1), tb1 = xb;
+    rt[0] += fa + fb;
+    rw[0] += wa + wb;
+#pragma unroll
+    for (int a = 1; a <= NR; ++a) {
+      rt[a] += ta1 * fa + tb1 * fb;
+      rw[a] += ta1 * wa + tb1 * wb;
+      const R ta2 = R(2) * xa * ta1 - ta0;
+      const R tb2 = R(2) * xb * tb1 - tb0;
+      ta0 = ta1;
+      ta1 = ta2;
+      tb0 = tb1;
+      tb1 = tb2;
+    }
+  }
+
+  // compact the angular entries into LDS
+  int nv = 0;
+  for (int base = 0; base < na; base += LPA) {
+    const int e = base + l;
+    bool valid = false;
+    R vx = 0, vy = 0, vz = 0, vf = 0, vw = 0;
+    if (e < na) {
+      double d0, d1, d2;
+      const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      if (r2 < ra2) {
+        valid = true;
+        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
+        const R ir = R(1) / r;
+        vx = R(d0) * ir;
+        vy = R(d1) * ir;
+        vz = R(d2) * ir;
+        R sn, cs;
+        sincos_cut<R>(r, two_ra, &sn, &cs);
+        vf = R(0.5) * (cs + R(1));
+        vw = R(p.tw[p.species[q]]);
+      }
+    }
+    const uint64_t m = group_ballot<LPA>(valid);
+    if (valid) {
+      const int at_ = nv + __popcll(m & ((1ull << l) - 1ull));
+      ux[at_] = vx;
+      uy[at_] = vy;
+      uz[at_] = vz;
+      fs[at_] = vf;
+      ws[at_] = vw;
+    }
+    nv += __popcll(m);
+  }
+  __syncthreads();
+
+  // angular terms, Eq. 6: unordered pairs j < k, lanes strided over the pair
+  // index, two pairs per iteration (the second with weight 0 past the end)
+  if (nv >= 2) {
+    int j = 0, rem = l;
+    while (j < nv - 1 && rem >= nv - 1 - j) {
+      rem -= nv - 1 - j;
+      ++j;
+    }
+    int k = j + 1 + rem;
+    while (j < nv - 1) {
+      int j2 = j, k2 = k + LPA;
+      while (j2 < nv - 1 && k2 >= nv) {
+        k2 = k2 - nv + j2 + 2;
+        ++j2;
+      }
+      const bool v2 = j2 < nv - 1;
+      const int jb = v2 ? j2 : j, kb = v2 ? k2 : k;
+      const R ca = ux[j] * ux[k] + uy[j] * uy[k] + uz[j] * uz[k];
+      const R cb = ux[jb] * ux[kb] + uy[jb] * uy[kb] + uz[jb] * uz[kb];
+      const R fa = fs[j] * fs[k];
+      const R fb = v2 ? fs[jb] * fs[kb] : R(0);
+      const R wa = ws[j] * ws[k] * fa, wb = ws[jb] * ws[kb] * fb;
+      R ta0 = R(1), ta1 = ca, tb0 = R(1), tb1 = cb;
+      at[0] += fa + fb;
+      aw[0] += wa + wb;
+#pragma unroll
+      for (int a = 1; a <= NA; ++a) {
+        at[a] += ta1 * fa + tb1 * fb;
+        aw[a] += ta1 * wa + tb1 * wb;
+        const R ta2 = R(2) * ca * ta1 - ta0;
+        const R tb2 = R(2) * cb * tb1 - tb0;
+        ta0 = ta1;
+        ta1 = ta2;
+        tb0 = tb1;
+        tb1 = tb2;
+      }
+      if (!v2) break;
+      j = j2;
+      k = k2 + LPA;
+      while (j < nv - 1 && k >= nv) {
+        k = k - nv + j + 2;
+        ++j;
+      }
+    }
+  }
+
+  // G layout [rad_typ | ang_typ | rad_wt | ang_wt] (ordered angular pairs =
+  // 2 x unordered).  Each half (typed, weighted) is packed into a vector of
+  // NV = 2^k >= T2 partial sums and reduce-scattered over the group on its
+  // own, so only one such vector is live at a time.
+  constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+  constexpr int NV = pow2_at_least(T2);
+  constexpr int PER = NV / LPA > 0 ? NV / LPA : 1;
+  const bool writer = active && l < NV;
+  {
+    R v[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] = a <= NR ? rt[a] : (a < T2 ? R(2) * at[a - T1] : R(0));
+    group_reduce_scatter<LPA, NV, R>(v, l);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = rs_comp<LPA, NV>(l, k);
+      if (writer && c < T2) out(c, v[k]);
+    }
+  }
+  if (p.weighted) {
+    R v[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] = a <= NR ? rw[a] : (a < T2 ? R(2) * aw[a - T1] : R(0));
+    group_reduce_scatter<LPA, NV, R>(v, l);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = rs_comp<LPA, NV>(l, k);
+      if (writer && c < T2) out(T2 + c, v[k]);
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace aenet

@@ -74,6 +74,11 @@ struct aenet_ctx {
   int n_cells = 0;
   int cap = 0, cap_ang = 0;
   int cap_user = 0, cap_ang_user = 0;  // capacities set by the caller (0: estimate)
+  // descriptor forward + networks in one kernel: on by default for the FP32
+  // and BF16 networks; with FP64 descriptors all blocks of the water
+  // workload run in one round and the network phase cannot overlap other
+  // blocks' descriptor work, so two kernels are as fast
+  bool fused = true;
   int ang_mean = 0;  // expected mean number of neighbours within R_a (densest structure)
   bool nbr_valid = false;
 
@@ -548,17 +553,26 @@ void build_neighbors_timed(aenet_ctx* c, const NbrParams& p, hipStream_t s) {
 }
 
 // descriptors -> networks -> forces (internal order).  vel != NULL applies the closing half kick.
+// keep_G: the descriptors are needed in HBM afterwards (training)
 aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, double half_dt,
-                     const DriftArgs* next = nullptr) {
+                     const DriftArgs* next = nullptr, bool keep_G = false) {
   if (c->n == 0) return AENET_OK;
   DescParams dp = desc_params(c);
-  prof_begin(c, s, AENET_K_DESC_FWD);
-  launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s);
-  prof_end(c, s);
   MlpParams mp = mlp_params(c, forces);
-  prof_begin(c, s, AENET_K_NETWORK);
-  launch_mlp(c->prec, mp, n_tiles(mp), s);
-  prof_end(c, s);
+  if (c->fused && fwd_mlp_fits(c->prec, dp, mp)) {
+    DescParams dq = dp;
+    if (!keep_G) dq.G = nullptr;
+    prof_begin(c, s, AENET_K_FWD_NETWORK);
+    launch_fwd_mlp(c->prec, c->nr, c->na, dq, mp, n_tiles(mp), s);
+    prof_end(c, s);
+  } else {
+    prof_begin(c, s, AENET_K_DESC_FWD);
+    launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s);
+    prof_end(c, s);
+    prof_begin(c, s, AENET_K_NETWORK);
+    launch_mlp(c->prec, mp, n_tiles(mp), s);
+    prof_end(c, s);
+  }
   if (forces) {
     prof_begin(c, s, AENET_K_DESC_BWD);
     launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s);
@@ -685,6 +699,7 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
   c->skin = m->skin;
   c->rlist = std::max(c->rr, c->ra) + c->skin;
   c->prec = m->precision;
+  c->fused = c->prec != AENET_FP64;
   c->device = m->device;
   const int typed = c->nr + 1 + c->na + 1;
   c->D = c->S > 1 ? 2 * typed : typed;
@@ -1097,7 +1112,7 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
   launch_gather_in(n, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
   TRY(build_checked(c, s));
-  TRY(compute(c, s, true, nullptr, 0.0));
+  TRY(compute(c, s, true, nullptr, 0.0, nullptr, true));
   // structure energies (caller order makes every structure contiguous)
   launch_scatter_out(n, c->d_perm.as<int>(), nullptr, nullptr, c->d_E.as<double>(), c->d_Eorig.as<double>(), s);
   launch_segment_sum(n_struct, c->d_segoff.as<int64_t>(), c->d_Eorig.as<double>(), c->d_estruct.as<double>(), s);
@@ -1149,6 +1164,12 @@ aenet_status aenet_get_stats(const aenet_ctx* c, aenet_stats* out) {
 aenet_status aenet_set_rebuild_every(aenet_ctx* c, int k) {
   if (!c || k < 1) return AENET_E_INVALID;
   c->rebuild_every = k;
+  return AENET_OK;
+}
+
+aenet_status aenet_set_fused(aenet_ctx* c, int enable) {
+  TRY(check_ctx(c));
+  c->fused = enable != 0;
   return AENET_OK;
 }
 

@@ -158,6 +158,29 @@ def test_error_paths(A):
     assert np.isfinite(E)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_fused_forward_network_is_bitwise_the_two_kernels(A, precision):
+    """Descriptors + networks in one kernel per 16-atom tile give the bits of
+    the separate kernels: water64 (full tiles and a partial one per species)
+    and a three-species cluster (short tiles at every species boundary)."""
+    g = np.random.default_rng(5)
+    pos = I.rsa(60, 14.0, 1.6, 77) + 30.0
+    sp = g.integers(0, 3, size=60).astype(np.int32)
+    s3 = I.System(pos, sp, np.array([80.0, 80.0, 80.0]), np.zeros(3, dtype=np.uint8))
+    m3 = small_model(S=3, nr=4, na=2, rr=5.0, ra=4.0, tw=(1.0, 2.0, 3.0))
+    cases = [("water64", I.load_model("water64"), I.make_system("water64")), ("cluster3", m3, s3)]
+    for name, m, s in cases:
+        out = []
+        for fused in (True, False):
+            ctx = A.Context(m, precision)
+            ctx.set_fused(fused)
+            out.append(ctx.energy_forces(s.pos, s.species, s.box, s.pbc))
+            ctx.close()
+        (E1, Ea1, F1), (E0, Ea0, F0) = out
+        assert E1 == E0, name
+        assert np.array_equal(Ea1, Ea0) and np.array_equal(F1, F0), name
+
+
 def test_nonfinite_device_input(A):
     """A NaN in device-resident positions is reported, not computed with."""
     import torch
