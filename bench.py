@@ -261,7 +261,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--modes", default="fp64,fp32,bf16")
     ap.add_argument("--equil", type=int, default=4000,
-                    help="untimed equilibration steps with velocity rescaling before the NVE run")
+                    help="equilibration steps (velocity rescaling to 300 K) before the extra "
+                         "'fp64_equilibrated' run; 0 skips that run")
     ap.add_argument("--cpu-sample-calls", type=int, default=5,
                     help="oracle energy+force calls on the full box for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -308,12 +309,20 @@ def main():
     dt = cfg["dt_fs"] * 1e-3
     A.load()
 
-    pos_eq, vel_eq = equilibrate(A, model, sysm, vel0, dt, args.equil, cfg["T"])
-    sys_eq = I.System(pos_eq, sysm.species, sysm.box, sysm.pbc) if args.equil > 0 else sysm
+    # the workload as specified: Maxwell-Boltzmann velocities at 300 K on the
+    # synthetic structure, then NVE
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for m in modes:
-        res[m] = run_mode(A, model, sys_eq, vel_eq, m, args.steps, args.warmup, dt, profile=(m == "fp64"))
+        res[m] = run_mode(A, model, sysm, vel0, m, args.steps, args.warmup, dt, profile=(m == "fp64"))
+    # extra: the same FP64 path from an equilibrated state (the random-weight
+    # network heats the synthetic structure far above 300 K in NVE, which makes
+    # the neighbour list rebuild every few steps)
+    if args.equil > 0 and "fp64" in modes:
+        pos_eq, vel_eq = equilibrate(A, model, sysm, vel0, dt, args.equil, cfg["T"])
+        sys_eq = I.System(pos_eq, sysm.species, sysm.box, sysm.pbc)
+        res["fp64_equilibrated"] = run_mode(A, model, sys_eq, vel_eq, "fp64", args.steps, args.warmup, dt,
+                                            profile=False)
     main_mode = "fp64" if "fp64" in res else modes[0]
     r = res[main_mode]
 
@@ -387,8 +396,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "water4096: 4096 H2O (12288 atoms) at 1.0 g/cm3 in a 49.67 A periodic box; "
                                "radial order 16 / 6.5 A, angular order 8 / 4.0 A (D=52); 52-25-25-1 tanh; "
-                               f"NVE velocity Verlet, dt 0.25 fs, skin 0.5 A, from {args.equil} steps of "
-                               "equilibration at 300 K",
+                               "NVE velocity Verlet from Maxwell-Boltzmann velocities at 300 K, dt 0.25 fs, "
+                               "skin 0.5 A",
                    "atoms": n, "mode": main_mode},
         "modes": modes_out,
         "roofline": roofline,

@@ -40,8 +40,11 @@ struct NbrParams {
   double* pos_ref;       // [n*3] positions at the last build
   const int* seg;        // [n] structure id
   const BoxInfo* boxes;  // [n_struct]
+  int n_struct;
   int pbc[3];
   int n_cells;
+  int tp;                // candidates per cell neighbourhood held in LDS (power of
+                         // two) by the per-cell row kernel; 0: per-atom kernels
   double r_list2;        // (max(R_r,R_a) + skin)^2
   double r_ang2;         // (R_a + skin)^2
   int cap, cap_ang;
@@ -51,14 +54,24 @@ struct NbrParams {
   int* cell_atoms;       // [n]
   int* atom_cell;        // [n]
   uint32_t* nbr;         // [n*cap]
-  uint32_t* key;         // [n*cap] search keys (stencil cell << 27 | atom), sorted per row part
+  uint16_t* segs;        // [n*kSegWords] row position where each stencil cell's
+                         // entries start, per row part (see nbr.hip)
   int* nnb;              // [n]
   int* nang;             // [n]
   int* rev;              // [n*cap] global index of the reverse entry
   int* flags;
   int* maxcnt;           // [2] largest row, largest angular prefix
   int* cond;             // build only if *cond != 0 (NULL = always)
+  int* go;               // [1] the decision of this build, for its later kernels
+  int* ticket;           // [1] block counter of the binning kernel (0 between builds)
 };
+constexpr int kSegWords = 56;  // 2 row parts x 28 segment boundaries
+constexpr int kCellAtomsMax = 64;  // atoms per cell the per-cell row kernel handles
+constexpr int kRowWaves = 16;      // wavefronts per block of the per-cell row kernel
+// LDS bytes of the per-cell row kernel for a candidate capacity tp
+inline size_t cell_rows_lds(int tp, int cap) {
+  return (size_t)tp * (4 + 24 + 2 * (kCellAtomsMax / 32) * 4) + (size_t)kRowWaves * cap * 4;
+}
 void launch_build_neighbors(const NbrParams& p, hipStream_t s);
 void launch_set_int(int* dst, int value, hipStream_t s);
 

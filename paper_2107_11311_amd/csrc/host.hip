@@ -74,6 +74,7 @@ struct aenet_ctx {
   int n_cells = 0;
   int cap = 0, cap_ang = 0;
   int cap_user = 0, cap_ang_user = 0;  // capacities set by the caller (0: estimate)
+  int tp = 0;  // candidate capacity of the per-cell row kernel (0: per-atom row kernels)
   // descriptor forward + networks in one kernel: on by default for the FP32
   // and BF16 networks; with FP64 descriptors all blocks of the water
   // workload run in one round and the network phase cannot overlap other
@@ -85,7 +86,8 @@ struct aenet_ctx {
   DevMem d_perm, d_species, d_seg, d_segoff, d_segcount, d_boxes;
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
       d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
-  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_key, d_nnb, d_nang, d_rev;
+  DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_segs, d_nnb, d_nang, d_rev;
+  DevMem d_build;  // [2] ints: decision of the current build, block counter
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
 
@@ -364,6 +366,18 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
   TRY(ensure(c, c->d_atom_cell, nb * 4));
   TRY(ensure(c, c->d_nnb, nb * 4));
   TRY(ensure(c, c->d_nang, nb * 4));
+  TRY(ensure(c, c->d_segs, nb * kSegWords * 2));
+  TRY(ensure(c, c->d_build, 2 * 4));
+  // the binning kernel expects zero cell counters and block counter (each
+  // build leaves them so for the next one)
+  HIP_TRY(c, hipMemsetAsync(c->d_cell_count.p, 0, (size_t)std::max(cells, (int64_t)1) * 4, st));
+  HIP_TRY(c, hipMemsetAsync(c->d_cell_fill.p, 0, (size_t)std::max(cells, (int64_t)1) * 4, st));
+  HIP_TRY(c, hipMemsetAsync(c->d_build.p, 0, 2 * 4, st));
+  // empty rows until a build writes them (a cell the per-cell row kernel
+  // cannot hold leaves its atoms' rows unwritten until the retry)
+  HIP_TRY(c, hipMemsetAsync(c->d_nnb.p, 0, nb * 4, st));
+  HIP_TRY(c, hipMemsetAsync(c->d_nang.p, 0, nb * 4, st));
+  HIP_TRY(c, hipStreamSynchronize(st));  // before work on the caller's stream
   // initial row capacities from the density of the densest structure
   if (c->cap == 0) {
     double est = 0.0, est_a = 0.0;
@@ -387,6 +401,15 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
       c->cap = c->cap_user;
       c->cap_ang = c->cap_ang_user;
     }
+    // rows by cell when the 27-cell neighbourhoods fit in LDS (grown, or
+    // given up for the per-atom kernels, if a build finds otherwise)
+    double per_cell = 0.0;
+    for (int s = 0; s < n_struct; ++s) {
+      const double ncell = (double)bx[s].nc[0] * bx[s].nc[1] * bx[s].nc[2];
+      per_cell = std::max(per_cell, (double)(offsets[s + 1] - offsets[s]) / ncell);
+    }
+    c->tp = per_cell * 1.5 + 8 > kCellAtomsMax ? 0 : pad_to((int)(27.0 * per_cell * 1.2) + 64, 64);
+    if (c->tp > 0 && cell_rows_lds(c->tp, c->cap) > 150 * 1024) c->tp = 0;
   }
   return AENET_OK;
 }
@@ -394,7 +417,7 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
 aenet_status ensure_rows(aenet_ctx* c) {
   const size_t nb = (size_t)std::max<int64_t>(c->n, 1);
   TRY(ensure(c, c->d_nbr, nb * c->cap * 4));
-  TRY(ensure(c, c->d_key, nb * c->cap * 4));
+
   TRY(ensure(c, c->d_rev, nb * c->cap * 4));
   TRY(ensure(c, c->d_pg, nb * c->cap * 3 * real_size(c)));
   return AENET_OK;
@@ -407,8 +430,10 @@ NbrParams nbr_params(aenet_ctx* c, int* cond) {
   p.pos_ref = c->d_pos_ref.as<double>();
   p.seg = c->d_seg.as<int>();
   p.boxes = c->d_boxes.as<BoxInfo>();
+  p.n_struct = c->n_struct;
   for (int a = 0; a < 3; ++a) p.pbc[a] = c->pbc[a];
   p.n_cells = c->n_cells;
+  p.tp = c->tp;
   p.r_list2 = c->rlist * c->rlist;
   p.r_ang2 = (c->ra + c->skin) * (c->ra + c->skin);
   p.cap = c->cap;
@@ -419,13 +444,15 @@ NbrParams nbr_params(aenet_ctx* c, int* cond) {
   p.cell_atoms = c->d_cell_atoms.as<int>();
   p.atom_cell = c->d_atom_cell.as<int>();
   p.nbr = c->d_nbr.as<uint32_t>();
-  p.key = c->d_key.as<uint32_t>();
+  p.segs = c->d_segs.as<uint16_t>();
   p.nnb = c->d_nnb.as<int>();
   p.nang = c->d_nang.as<int>();
   p.rev = c->d_rev.as<int>();
   p.flags = c->d_flags.as<int>();
   p.maxcnt = c->d_flags.as<int>() + 1;
   p.cond = cond;
+  p.go = c->d_build.as<int>();
+  p.ticket = c->d_build.as<int>() + 1;
   return p;
 }
 
@@ -478,6 +505,13 @@ int n_tiles(const MlpParams& p) { return p.tile_off[p.n_species]; }
 
 // grow capacities from what the last build saw
 aenet_status grow_caps(aenet_ctx* c, const int* hf) {
+  // the per-cell row kernel: a neighbourhood or a cell larger than it holds
+  if (c->tp > 0 && (hf[5] > c->tp || hf[6] > kCellAtomsMax)) {
+    c->tp = hf[6] > kCellAtomsMax ? 0 : pad_to((int)(hf[5] * 1.15) + 64, 64);
+    if (c->tp > 0 && cell_rows_lds(c->tp, c->cap) > 150 * 1024) c->tp = 0;
+    c->stats.n_capacity_retries++;
+    if (hf[1] <= c->cap && hf[2] <= c->cap_ang) return AENET_OK;
+  }
   const int need = hf[1], need_a = hf[2];
   int cap = std::max(c->cap, pad_to((int)(need * 1.2) + 16, 16));
   int cap_a = std::max(c->cap_ang, pad_to((int)(need_a * 1.15) + 8, 8));
@@ -485,6 +519,7 @@ aenet_status grow_caps(aenet_ctx* c, const int* hf) {
   if (cap_a > 700) return fail(c, AENET_E_INVALID, "angular neighbour shell too crowded (" + std::to_string(need_a) + " entries)");
   c->cap = cap;
   c->cap_ang = cap_a;
+  if (c->tp > 0 && cell_rows_lds(c->tp, c->cap) > 150 * 1024) c->tp = 0;
   c->stats.n_capacity_retries++;
   return ensure_rows(c);
 }

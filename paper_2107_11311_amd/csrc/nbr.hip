@@ -11,9 +11,17 @@
 // Rows are deterministic: cells are sorted by atom index and scanned in a
 // fixed order.  A row holds first the entries within R_a + skin (the angular
 // candidates), then the remaining ones within max(R_r, R_a) + skin; both
-// parts are ordered by (stencil cell, atom).  That order makes the reverse
-// entry (j -> i, -s) of every (i -> j, s) findable by binary search, which the
-// deterministic force gather uses instead of atomics.
+// parts are ordered by (stencil cell, atom), and the row position where each
+// stencil cell's entries start is kept per part (segs).  The reverse entry
+// (j -> i, -s) of an entry (i -> j, s) found in stencil cell k of i lies in
+// the segment of stencil cell 26 - k of j's row, where it is found by binary
+// search on the atom index; the deterministic force gather uses these
+// reverse entries instead of atomics.
+//
+// A build is five kernels: binning (whose last block also scans the cell
+// counts and resets them for the next build), scatter into cells, per-cell
+// sort, rows, reverse entries.  In MD each of them first checks the device
+// flag of the step, so a step without a rebuild costs five empty launches.
 #include <climits>
 
 #include "aenet_internal.h"
@@ -29,7 +37,9 @@ __device__ inline double wrap_coord(double x, double L) {
   return w;
 }
 
-__device__ inline bool skip(const NbrParams& p) { return p.cond && *p.cond == 0; }
+// the decision of this build, taken by the binning kernel: later kernels of
+// the build follow it
+__device__ inline bool skip(const NbrParams& p) { return p.cond && *p.go == 0; }
 
 __device__ inline void cell_coords(const BoxInfo& b, int cell, int c[3]) {
   int local = cell - b.cell_base;
@@ -46,74 +56,74 @@ __global__ void k_set_int(int* dst, int v) {
   if (threadIdx.x == 0) *dst = v;
 }
 
-__global__ void k_zero(NbrParams p) {
-  if (skip(p)) return;
-  // Inside an MD chunk an overflowed build means the chunk is redone with
-  // longer rows: later builds of the chunk are dropped (their request is
-  // withdrawn, so the rest of this build skips too), which keeps the row
-  // maxima that size the retry those of the build that overflowed.
-  if (p.cond && (p.flags[0] & kFlagOverflow)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *p.cond = 0;
-    return;
+// Binning: wrap positions into the box (periodic axes), remember them as the
+// reference of the skin test, count atoms per cell.  The last block to finish
+// scans the counts into cell_start and zeroes the counters for the scatter
+// and the next build.
+__global__ __launch_bounds__(256) void k_bin(NbrParams p) {
+  // In MD a build runs if the step asked for it, unless an earlier build of
+  // the chunk overflowed (the chunk is then redone with longer rows, and the
+  // row maxima that size the retry stay those of that build).  Every block
+  // decides alike: nothing it reads is written before the later kernels.
+  const bool go = !p.cond || (*p.cond != 0 && !(p.flags[0] & kFlagOverflow));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && p.cond) {
+    *p.go = go ? 1 : 0;
+    if (go) atomicAdd(p.flags + 8, 1);  // builds triggered on the device (MD)
   }
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < p.n_cells) {
-    p.cell_count[c] = 0;
-    p.cell_fill[c] = 0;
-  }
-  if (c == 0) {
-    p.maxcnt[0] = 0;
-    p.maxcnt[1] = 0;
-    if (p.cond) atomicAdd(p.flags + 8, 1);  // builds triggered on the device (MD)
-  }
-}
-
-__global__ void k_bin(NbrParams p) {
-  if (skip(p)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const BoxInfo b = p.boxes[p.seg[i]];
-  int c[3];
-  for (int a = 0; a < 3; ++a) {
-    double x = p.pos[3 * (size_t)i + a];
-    if (p.pbc[a]) {
-      x = wrap_coord(x, b.L[a]);
-      p.pos[3 * (size_t)i + a] = x;
+  if (!go) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p.n) {
+    const BoxInfo b = p.boxes[p.seg[i]];
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+      double x = p.pos[3 * (size_t)i + a];
+      if (p.pbc[a]) {
+        x = wrap_coord(x, b.L[a]);
+        p.pos[3 * (size_t)i + a] = x;
+      }
+      p.pos_ref[3 * (size_t)i + a] = x;
+      double fc = floor(x * (double)b.nc[a] / b.L[a]);
+      fc = fmin(fmax(fc, 0.0), (double)(b.nc[a] - 1));
+      c[a] = (int)fc;
     }
-    p.pos_ref[3 * (size_t)i + a] = x;
-    double fc = floor(x * (double)b.nc[a] / b.L[a]);
-    fc = fmin(fmax(fc, 0.0), (double)(b.nc[a] - 1));
-    c[a] = (int)fc;
+    const int cell = b.cell_base + (c[2] * b.nc[1] + c[1]) * b.nc[0] + c[0];
+    p.atom_cell[i] = cell;
+    atomicAdd(&p.cell_count[cell], 1);
   }
-  int cell = b.cell_base + (c[2] * b.nc[1] + c[1]) * b.nc[0] + c[0];
-  p.atom_cell[i] = cell;
-  atomicAdd(&p.cell_count[cell], 1);
-}
-
-// exclusive scan of cell counts, one block of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan(NbrParams p) {
-  if (skip(p)) return;
-  __shared__ int s[1024];
+  // last block: exclusive scan of the counts
+  __shared__ int last;
+  __shared__ int s[256];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(p.ticket, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
   const int n = p.n_cells;
   const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
+  const int per = (n + 255) / 256;
   const int lo = min(t * per, n), hi = min(lo + per, n);
   int sum = 0;
-  for (int k = lo; k < hi; ++k) sum += p.cell_count[k];
+  for (int k = lo; k < hi; ++k)
+    sum += __hip_atomic_load(&p.cell_count[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   s[t] = sum;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = t >= off ? s[t - off] : 0;
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = t >= off ? s[t - off] : 0;
     __syncthreads();
     s[t] += v;
     __syncthreads();
   }
   int run = t ? s[t - 1] : 0;
   for (int k = lo; k < hi; ++k) {
+    const int cnt = __hip_atomic_load(&p.cell_count[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     p.cell_start[k] = run;
-    run += p.cell_count[k];
+    run += cnt;
+    p.cell_count[k] = 0;
+    p.cell_fill[k] = 0;
   }
-  if (t == 1023) p.cell_start[n] = s[1023];
+  if (t == 255) p.cell_start[n] = s[255];
+  if (t == 0) *p.ticket = 0;
 }
 
 __global__ void k_scatter(NbrParams p) {
@@ -136,7 +146,7 @@ __global__ __launch_bounds__(256) void k_sort_cells(NbrParams p) {
   __shared__ int v[kSortMax];
   const int c = blockIdx.x;
   int* a = p.cell_atoms + p.cell_start[c];
-  const int m = p.cell_count[c];
+  const int m = p.cell_start[c + 1] - p.cell_start[c];
   if (m <= 1) return;
   if (m > kSortMax) {
     if (threadIdx.x == 0) {
@@ -182,7 +192,8 @@ __global__ __launch_bounds__(256) void k_sort_cells(NbrParams p) {
 __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
   if (skip(p)) return;
   __shared__ int s_start[4][27], s_count[4][27], s_code[4][27], s_pref[4][28];
-  extern __shared__ uint32_t s_rad[];  // per wave: radial-only entries, then their keys
+  __shared__ int s_na[4][27], s_nr[4][27];  // accepted entries per stencil cell and row part
+  extern __shared__ uint32_t s_rad[];        // per wave: the radial-only entries
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int i = blockIdx.x * (blockDim.x >> 6) + wv;
@@ -208,8 +219,10 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
     }
     const int cell = out ? 0 : b.cell_base + (w[2] * b.nc[1] + w[1]) * b.nc[0] + w[0];
     s_start[wv][lane] = out ? 0 : p.cell_start[cell];
-    s_count[wv][lane] = out ? 0 : p.cell_count[cell];
+    s_count[wv][lane] = out ? 0 : p.cell_start[cell + 1] - p.cell_start[cell];
     s_code[wv][lane] = (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1);
+    s_na[wv][lane] = 0;
+    s_nr[wv][lane] = 0;
   }
   __syncthreads();
   if (lane == 0) {
@@ -222,17 +235,14 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
   }
   __syncthreads();
   const int total = s_pref[wv][27];
-  const size_t rbase = (size_t)(active ? i : 0) * p.cap;
-  uint32_t* row = p.nbr + rbase;
-  uint32_t* key = p.key + rbase;
-  uint32_t* rad_e = s_rad + (size_t)wv * 2 * p.cap;
-  uint32_t* rad_k = rad_e + p.cap;
+  uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
+  uint32_t* rad_e = s_rad + (size_t)wv * p.cap;
   int cnt_a = 0, cnt_r = 0;
   int k_cell = 0;  // stencil cell of this lane's candidate (candidates advance monotonically)
   for (int base = 0; base < total; base += 64) {
     const int t = base + lane;
     bool ang = false, rad = false;
-    uint32_t entry = 0, ekey = 0;
+    uint32_t entry = 0;
     if (t < total) {
       while (k_cell < 26 && t >= s_pref[wv][k_cell + 1]) ++k_cell;
       const int q = p.cell_atoms[s_start[wv][k_cell] + (t - s_pref[wv][k_cell])];
@@ -255,25 +265,19 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
         ang = r2 < p.r_ang2;
         rad = !ang && r2 < p.r_list2;
         entry = (uint32_t)q | ((uint32_t)code << kImgBits);
-        // search key of the entry: (stencil cell, atom); rows are sorted by it
-        ekey = (uint32_t)q | ((uint32_t)k_cell << kImgBits);
       }
     }
     const uint64_t below = (1ull << lane) - 1ull;
     const uint64_t ma = __ballot(ang), mr = __ballot(rad);
     if (ang) {
       const int at = cnt_a + __popcll(ma & below);
-      if (at < p.cap) {
-        row[at] = entry;
-        key[at] = ekey;
-      }
+      if (at < p.cap) row[at] = entry;
+      atomicAdd(&s_na[wv][k_cell], 1);
     }
     if (rad) {
       const int at = cnt_r + __popcll(mr & below);
-      if (at < p.cap) {
-        rad_e[at] = entry;
-        rad_k[at] = ekey;
-      }
+      if (at < p.cap) rad_e[at] = entry;
+      atomicAdd(&s_nr[wv][k_cell], 1);
     }
     cnt_a += __popcll(ma);
     cnt_r += __popcll(mr);
@@ -282,10 +286,7 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
   // append the radial-only entries after the angular ones
   for (int k = lane; k < cnt_r; k += 64) {
     const int at = cnt_a + k;
-    if (at < p.cap && k < p.cap) {
-      row[at] = rad_e[k];
-      key[at] = rad_k[k];
-    }
+    if (at < p.cap && k < p.cap) row[at] = rad_e[k];
   }
   if (active && lane == 0) {
     const int count = cnt_a + cnt_r;
@@ -297,46 +298,315 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
     // maxima for capacity planning; the plain read first keeps the atomics rare
     if (count > p.maxcnt[0]) atomicMax(&p.maxcnt[0], count);
     if (cnt_a > p.maxcnt[1]) atomicMax(&p.maxcnt[1], cnt_a);
+    // where each stencil cell's entries start in the two row parts (clamped
+    // to the row like nnb / nang)
+    uint16_t* sg = p.segs + (size_t)i * kSegWords;
+    int ra = 0, rr = cnt_a;
+    for (int k = 0; k < 27; ++k) {
+      sg[k] = (uint16_t)min(ra, nang);
+      sg[28 + k] = (uint16_t)min(rr, p.nnb[i]);
+      ra += s_na[wv][k];
+      rr += s_nr[wv][k];
+    }
+    sg[27] = (uint16_t)nang;
+    sg[55] = (uint16_t)p.nnb[i];
   }
 }
 
-// reverse entry of every row entry, one wavefront per atom: the reverse of
-// (i -> q) found in stencil cell k of i is (q -> i) in stencil cell 26 - k of q
+// Reverse entry of every row entry, one wavefront per atom: the reverse of
+// (i -> q) found in stencil cell k of i is (q -> i) in stencil cell 26 - k of
+// q, in the same row part (the r^2 of both agree bit for bit); it is found by
+// binary search on the atom index inside that segment of q's row.
 __global__ __launch_bounds__(256) void k_reverse(NbrParams p) {
   if (skip(p)) return;
+  __shared__ uint16_t s_seg[4][kSegWords];
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= p.n) return;
+  const int wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * (blockDim.x >> 6) + wv;
+  const bool active = i < p.n;
+  if (active && lane < kSegWords) s_seg[wv][lane] = p.segs[(size_t)i * kSegWords + lane];
+  __syncthreads();
+  if (!active) return;
   const int nn = p.nnb[i], na = p.nang[i];
-  const uint32_t* krow = p.key + (size_t)i * p.cap;
+  const uint32_t* row = p.nbr + (size_t)i * p.cap;
+  int k = 0, part = 0;  // stencil cell and row part of this lane's entry (advance monotonically)
   for (int e = lane; e < nn; e += 64) {
-    const uint32_t k = krow[e];
-    const int q = (int)(k & kAtomMask);
-    const uint32_t target = ((26u - (k >> kImgBits)) << kImgBits) | (uint32_t)i;
-    const uint32_t* kq = p.key + (size_t)q * p.cap;
-    int lo, hi;
-    if (e < na) {
-      lo = 0;
-      hi = p.nang[q];
-    } else {
-      lo = p.nang[q];
-      hi = p.nnb[q];
+    if (part == 0 && e >= na) {
+      part = 1;
+      k = 0;
     }
+    const uint16_t* sg = s_seg[wv] + 28 * part;
+    while (k < 26 && e >= sg[k + 1]) ++k;
+    const int q = (int)(row[e] & kAtomMask);
+    const uint16_t* sq = p.segs + (size_t)q * kSegWords + 28 * part;
+    int lo = sq[26 - k], hi = sq[27 - k];
+    const uint32_t* rq = p.nbr + (size_t)q * p.cap;
     int found = -1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      const uint32_t km = kq[mid];
-      if (km == target) {
+      const int am = (int)(rq[mid] & kAtomMask);
+      if (am == i) {
         found = mid;
         break;
       }
-      if (km < target) lo = mid + 1; else hi = mid;
+      if (am < i) lo = mid + 1; else hi = mid;
     }
     if (found < 0) {
       atomicOr(p.flags, kFlagReverse);
       p.rev[(size_t)i * p.cap + e] = -1;
     } else {
       p.rev[(size_t)i * p.cap + e] = q * p.cap + found;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ per-cell rows
+// One block per cell.  The atoms of the 27 stencil cells (the candidates of
+// every atom of the central cell) are loaded into LDS once, ordered by
+// (stencil cell, atom) there, and every central atom's row is built from
+// LDS.  While doing so
+// the block records, per candidate and row part, which central atoms accepted
+// it (a bitmask).  The reverse of (i -> q) found in stencil cell k of i is
+// (q -> i) in stencil cell 26 - k of q, whose segment of q's row holds
+// exactly the central atoms that accepted q there, ordered by index: its
+// position inside the segment is the number of set bits below i's.  The
+// block stores that rank with k in rev; k_reverse_rank adds the segment start
+// once every row is built.
+constexpr int kMaskWords = kCellAtomsMax / 32;
+
+__global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
+  if (skip(p)) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tp = p.tp;
+  double* s_pos = reinterpret_cast<double*>(smem);                          // [tp][3]
+  uint32_t* s_key = reinterpret_cast<uint32_t*>(s_pos + 3 * (size_t)tp);      // [tp] atom of each candidate
+  uint32_t* s_mask = s_key + tp;                                              // [tp][2][kMaskWords]
+  uint32_t* s_rad = s_mask + (size_t)tp * 2 * kMaskWords;                     // [waves][cap]
+  __shared__ int s_start[27], s_cnt[27], s_code[27], s_pref[28];
+  __shared__ double s_shift[27][3];                             // image shift s L of each stencil cell
+  __shared__ int s_sa[kRowWaves][28], s_sr[kRowWaves][28];      // segment starts of the row being built
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = blockIdx.x;
+  // the structure owning cell c
+  int st = 0;
+  while (st + 1 < p.n_struct && c >= p.boxes[st + 1].cell_base) ++st;
+  const BoxInfo b = p.boxes[st];
+  int ci[3];
+  cell_coords(b, c, ci);
+  if (tid < 27) {
+    const int o[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+    int w[3], sh[3];
+    bool out = false;
+    for (int a = 0; a < 3; ++a) {
+      const int u = ci[a] + o[a];
+      if (p.pbc[a]) {
+        sh[a] = u < 0 ? -1 : (u >= b.nc[a] ? 1 : 0);
+        w[a] = u - sh[a] * b.nc[a];
+      } else {
+        sh[a] = 0;
+        w[a] = u;
+        out |= (u < 0 || u >= b.nc[a]);
+      }
+      s_shift[tid][a] = (double)sh[a] * b.L[a];
+    }
+    const int cell = out ? 0 : b.cell_base + (w[2] * b.nc[1] + w[1]) * b.nc[0] + w[0];
+    s_start[tid] = out ? 0 : p.cell_start[cell];
+    s_cnt[tid] = out ? 0 : p.cell_start[cell + 1] - p.cell_start[cell];
+    s_code[tid] = (sh[0] + 1) + 3 * (sh[1] + 1) + 9 * (sh[2] + 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int k = 0; k < 27; ++k) {
+      s_pref[k] = run;
+      run += s_cnt[k];
+    }
+    s_pref[27] = run;
+  }
+  __syncthreads();
+  const int total = s_pref[27];
+  const int ncen = s_cnt[13];
+  int cmax = 0;
+  for (int k = 0; k < 27; ++k) cmax = max(cmax, s_cnt[k]);
+  if (total > tp || cmax > kCellAtomsMax) {
+    // does not fit: the host enlarges tp (or takes the per-atom kernels) and
+    // builds again; nothing of this cell's rows is written
+    if (tid == 0) {
+      atomicOr(p.flags, kFlagOverflow);
+      atomicMax(p.flags + 5, total);
+      atomicMax(p.flags + 6, cmax);
+    }
+    return;
+  }
+  if (ncen == 0) return;
+  // candidates: each stencil cell's atoms sorted by index (one wavefront per
+  // cell, a bitonic network across its lanes), so the scatter's atomic order
+  // does not reach the rows
+  for (int k = wv; k < 27; k += kRowWaves) {
+    const int cnt = s_cnt[k];
+    uint32_t v = lane < cnt ? (uint32_t)p.cell_atoms[s_start[k] + lane] : 0xffffffffu;
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, stride, 64);
+        const bool up = (lane & size) == 0, lower = (lane & stride) == 0;
+        v = (lower == up) ? min(v, o) : max(v, o);
+      }
+    }
+    if (lane < cnt) {
+      const int t = s_pref[k] + lane;
+      s_key[t] = v;
+      s_pos[3 * t] = p.pos[3 * (size_t)v];
+      s_pos[3 * t + 1] = p.pos[3 * (size_t)v + 1];
+      s_pos[3 * t + 2] = p.pos[3 * (size_t)v + 2];
+    }
+  }
+  for (int t = tid; t < total * 2 * kMaskWords; t += 64 * kRowWaves) s_mask[t] = 0u;
+  __syncthreads();
+
+  // rows of the central atoms (stencil cell 13, sorted by atom index), one
+  // wavefront per atom; the radial-only entries are staged as (slot, stencil)
+  const int c0 = s_pref[13];
+  uint32_t* rad_t = s_rad + (size_t)wv * p.cap;
+  for (int ai = wv; ai < ncen; ai += kRowWaves) {
+    const int i = (int)s_key[c0 + ai];
+    const double xi0 = s_pos[3 * (c0 + ai)], xi1 = s_pos[3 * (c0 + ai) + 1], xi2 = s_pos[3 * (c0 + ai) + 2];
+    uint32_t* row = p.nbr + (size_t)i * p.cap;
+    int* slot = p.rev + (size_t)i * p.cap;  // (candidate slot, stencil cell) of each entry, then (rank, cell)
+    int cnt_a = 0, cnt_r = 0;
+    int k_cell = 0;
+    uint32_t* mA = s_mask + (ai >> 5);
+    const uint32_t mbit = 1u << (ai & 31);
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + lane;
+      const bool in = t < total;
+      if (in)
+        while (t >= s_pref[k_cell + 1]) ++k_cell;  // s_pref[27] = total > t ends it
+      const int tt = in ? t : 0;
+      const int q = (int)s_key[tt];
+      const double qx = s_pos[3 * tt], qy = s_pos[3 * tt + 1], qz = s_pos[3 * tt + 2];
+      const double sx = s_shift[k_cell][0], sy = s_shift[k_cell][1], sz = s_shift[k_cell][2];
+      // displacement from the lower-index atom (image shifts counted from
+      // it), so that an entry and its reverse agree bit for bit on r^2
+      const bool iq = i < q || (i == q && (sz > 0.0 || (sz == 0.0 && (sy > 0.0 || (sy == 0.0 && sx > 0.0)))));
+      const double d0 = iq ? (qx + sx) - xi0 : (xi0 - sx) - qx;
+      const double d1 = iq ? (qy + sy) - xi1 : (xi1 - sy) - qy;
+      const double d2 = iq ? (qz + sz) - xi2 : (xi2 - sz) - qz;
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const bool self = q == i && k_cell == 13;
+      const bool ok = in && !self;
+      if (ok && r2 == 0.0) atomicOr(p.flags, kFlagOverlap);
+      const bool ang = ok && r2 < p.r_ang2;
+      const bool rad = ok && !ang && r2 < p.r_list2;
+      const uint64_t below = (1ull << lane) - 1ull;
+      const uint64_t ma = __ballot(ang), mr = __ballot(rad);
+      const int pa = cnt_a + __popcll(ma & below), pr = cnt_r + __popcll(mr & below);
+      // the first candidate of a stencil cell fixes where its entries start
+      if (in && t == s_pref[k_cell]) {
+        s_sa[wv][k_cell] = pa;
+        s_sr[wv][k_cell] = pr;
+      }
+      if (ang) {
+        if (pa < p.cap) {
+          row[pa] = (uint32_t)q | ((uint32_t)s_code[k_cell] << kImgBits);
+          slot[pa] = tt | (k_cell << 16);
+        }
+        atomicOr(mA + (2 * (size_t)tt) * kMaskWords, mbit);
+      }
+      if (rad) {
+        if (pr < p.cap) rad_t[pr] = (uint32_t)tt | ((uint32_t)k_cell << 16);
+        atomicOr(mA + (2 * (size_t)tt + 1) * kMaskWords, mbit);
+      }
+      cnt_a += __popcll(ma);
+      cnt_r += __popcll(mr);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // the radial-only entries after the angular ones
+    for (int k = lane; k < cnt_r; k += 64) {
+      const int at = cnt_a + k;
+      if (at < p.cap && k < p.cap) {
+        const uint32_t v = rad_t[k];
+        row[at] = s_key[v & 0xffffu] | ((uint32_t)s_code[v >> 16] << kImgBits);
+        slot[at] = (int)v;
+      }
+    }
+    const int nang = min(cnt_a, min(p.cap_ang, p.cap));
+    const int nnb = max(min(cnt_a + cnt_r, p.cap), nang);
+    if (lane < 28) {
+      // stencil cells without candidates start where the next one does
+      int sa = cnt_a, sr = cnt_r;
+      for (int k = lane; k < 27; ++k)
+        if (s_cnt[k] > 0) {
+          sa = s_sa[wv][k];
+          sr = s_sr[wv][k];
+          break;
+        }
+      uint16_t* sg = p.segs + (size_t)i * kSegWords;
+      sg[lane] = (uint16_t)(lane == 27 ? nang : min(sa, nang));
+      sg[28 + lane] = (uint16_t)(lane == 27 ? nnb : min(cnt_a + sr, nnb));
+    }
+    if (lane == 0) {
+      const int count = cnt_a + cnt_r;
+      if (count > p.cap || cnt_a > p.cap_ang) atomicOr(p.flags, kFlagOverflow);
+      p.nnb[i] = nnb;
+      p.nang[i] = nang;
+      if (count > p.maxcnt[0]) atomicMax(&p.maxcnt[0], count);
+      if (cnt_a > p.maxcnt[1]) atomicMax(&p.maxcnt[1], cnt_a);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();  // every central atom's acceptances are in the masks
+
+  // ranks: position of i among the central atoms in the segment of q's row
+  for (int ai = wv; ai < ncen; ai += kRowWaves) {
+    const int i = (int)s_key[c0 + ai];
+    const int nn = p.nnb[i], na = p.nang[i];
+    int* slot = p.rev + (size_t)i * p.cap;
+    for (int e = lane; e < nn; e += 64) {
+      const int v = slot[e];
+      const int t = v & 0xffff, k = v >> 16;
+      const uint32_t* m = s_mask + (2 * (size_t)t + (e < na ? 0 : 1)) * kMaskWords;
+      int rank = 0;
+#pragma unroll
+      for (int w = 0; w < kMaskWords; ++w) {
+        const int lo = 32 * w;
+        const uint32_t below = ai >= lo + 32 ? 0xffffffffu : (ai <= lo ? 0u : ((1u << (ai - lo)) - 1u));
+        rank += __popc(m[w] & below);
+      }
+      slot[e] = rank | (k << 16);
+    }
+  }
+}
+
+// rev = q * cap + (start of the segment of stencil cell 26 - k in q's row
+// part) + rank, from the (rank, k) left by k_rows_cell
+__global__ __launch_bounds__(256) void k_reverse_rank(NbrParams p) {
+  if (skip(p)) return;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= p.n) return;
+  const int nn = p.nnb[i], na = p.nang[i];
+  const uint32_t* row = p.nbr + (size_t)i * p.cap;
+  int* rv = p.rev + (size_t)i * p.cap;
+  for (int e = lane; e < nn; e += 64) {
+    const int q = (int)(row[e] & kAtomMask);
+    const int info = rv[e];
+    const int rank = info & 0xffff, k = info >> 16;
+    bool ok = k >= 0 && k <= 26;  // (a cell whose rows were not built this time leaves junk)
+    int pos = 0;
+    if (ok) {
+      const uint16_t* sq = p.segs + (size_t)q * kSegWords + (e < na ? 0 : 28);
+      pos = (int)sq[26 - k] + rank;
+      ok = pos < (int)sq[27 - k];
+    }
+    if (!ok) {
+      atomicOr(p.flags, kFlagReverse);
+      rv[e] = -1;
+    } else {
+      rv[e] = q * p.cap + pos;
     }
   }
 }
@@ -351,13 +621,16 @@ void launch_set_int(int* dst, int value, hipStream_t s) {
 
 void launch_build_neighbors(const NbrParams& p, hipStream_t s) {
   if (p.n <= 0) return;
-  hipLaunchKernelGGL(k_zero, dim3(blocks_for(p.n_cells, 256)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_bin, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, p);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(k_sort_cells, dim3(p.n_cells), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(k_rows, dim3(blocks_for(p.n, 4)), dim3(256), (size_t)4 * 2 * p.cap * sizeof(uint32_t), s, p);
-  hipLaunchKernelGGL(k_reverse, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
+  if (p.tp > 0) {
+    hipLaunchKernelGGL(k_rows_cell, dim3(p.n_cells), dim3(64 * kRowWaves), cell_rows_lds(p.tp, p.cap), s, p);
+    hipLaunchKernelGGL(k_reverse_rank, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
+  } else {
+    hipLaunchKernelGGL(k_sort_cells, dim3(p.n_cells), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_rows, dim3(blocks_for(p.n, 4)), dim3(256), (size_t)4 * p.cap * sizeof(uint32_t), s, p);
+    hipLaunchKernelGGL(k_reverse, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
+  }
 }
 
 }  // namespace aenet
