@@ -2,17 +2,15 @@
 // force back-propagation to per-entry displacement gradients, and the
 // Jacobian-vector product used by the training gradient.
 //
-// Mapping: a group of LPA lanes of one wavefront works on one centre atom.
-//   radial terms (Eq. 3): lanes stride over the atom's neighbour entries;
-//   angular terms (Eq. 6): the entries within R_a are compacted into LDS
-//     (unit vector, f_c, species weight, ...); the forward pass and the JVP
-//     stride lanes over the unordered pairs j < k (the ordered-pair sum of
-//     Eq. 6 is twice that), the force pass gives each lane one entry k and
-//     loops over all j != k, so every lane owns the gradient of its entry and
-//     no atomics are needed.
-// Accumulators live in registers (orders are compile-time) and are summed
-// over the group with cross-lane shuffles.  R is the arithmetic type
-// (double, or float with the displacement taken in double).
+// Forward and JVP: a group of LPA lanes of one wavefront works on one centre
+// atom; lanes stride over the atom's neighbour entries for the radial terms
+// (Eq. 3), the entries within R_a are compacted into LDS (unit vector, f_c,
+// species weight, ...) and lanes stride over the unordered pairs j < k for the
+// angular terms (the ordered-pair sum of Eq. 6 is twice that).  Accumulators
+// live in registers (orders are compile-time) and are summed over the group
+// with cross-lane shuffles.  The force pass takes a wavefront per atom (see
+// k_desc_bwd).  R is the arithmetic type (double, or float with the
+// displacement taken in double).
 #include "desc_dev.h"
 
 namespace aenet {
