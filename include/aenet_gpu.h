@@ -52,8 +52,10 @@ typedef enum {
 /* Arithmetic of the hot path.  AENET_FP64: everything in float64.
  * AENET_FP32: descriptor terms and the networks in float32 (networks on FP32
  * MFMA), displacements, per-atom force sums, energies and the integrator in
- * float64.  AENET_BF16: as FP32, with network operands rounded to bfloat16
- * (round to nearest even) on BF16 MFMA with float32 accumulation. */
+ * float64.  AENET_BF16: as FP32, with the network weights rounded to
+ * bfloat16 (round to nearest even) on BF16 MFMA with float32 accumulation;
+ * the float32 activations and deltas enter the MFMA as a pair of bfloat16
+ * values (the value rounded, and its rounding error rounded). */
 typedef enum { AENET_FP64 = 0, AENET_FP32 = 1, AENET_BF16 = 2 } aenet_precision;
 
 typedef enum { AENET_ACT_LINEAR = 0, AENET_ACT_TANH = 1 } aenet_act;

@@ -8,8 +8,9 @@
 // and, for forces, back-propagates to the input:
 //   D_{L-1} = w_L * f'(X_{L-1});  D_{l-1} = (D_l W_l) * f'(X_{l-1});  dE/dG = (D_1 W_1) * scale.
 // Activations stay in LDS between layers.  Precisions: 0 = FP64 MFMA
-// (16x16x4), 1 = FP32 MFMA (16x16x4), 2 = BF16 operands rounded to nearest
-// even on the 16x16x32 BF16 MFMA with FP32 accumulation (tanh, biases and
+// (16x16x4), 1 = FP32 MFMA (16x16x4), 2 = BF16 weights (rounded to nearest
+// even) on the 16x16x32 BF16 MFMA with FP32 accumulation, the FP32
+// activations entering as a hi + lo pair of BF16 values (tanh, biases and
 // normalisation in FP32).
 //
 // The training kernel runs the same forward pass plus the tangent pass

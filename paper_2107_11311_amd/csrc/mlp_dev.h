@@ -89,20 +89,32 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
     }
     acc += acc1;
   } else {
+    // BF16 weights; the FP32 activations (or deltas) enter as a compensated
+    // pair hi + lo of BF16 values (lo = the rounding error of hi), two
+    // products per k-step on the BF16 MFMA, FP32 accumulation
     constexpr int MAXKS = kMaxWidth / 32;
-    v8bf a[MAXKS], b[MAXKS];
+    v8bf ah[MAXKS], al[MAXKS], b[MAXKS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks) {
       if (ks < ksteps) {
         const float* ap = A + r * ld + ks * 32 + 8 * kq;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) a[ks][t] = (__bf16)ap[t];
+        for (int t = 0; t < 8; ++t) {
+          const __bf16 hi = (__bf16)ap[t];
+          ah[ks][t] = hi;
+          al[ks][t] = (__bf16)(ap[t] - (float)hi);
+        }
         b[ks] = *reinterpret_cast<const v8bf*>(Bp + (((size_t)nb * ksteps + ks) * 64 + lane) * 8);
       }
     }
+    typename M::Acc acc1 = {0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks)
-      if (ks < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], b[ks], acc, 0, 0, 0);
+      if (ks < ksteps) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], b[ks], acc, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], b[ks], acc1, 0, 0, 0);
+      }
+    acc += acc1;
   }
   return acc;
 }
