@@ -55,6 +55,26 @@ def generate_snapshots(teacher, system, vel0, n_snap: int, stride: int, dt_ps: f
     return Snapshots(P, Fs, Es, system.species, system.box, system.pbc, time.perf_counter() - t0)
 
 
+def restrict_to_orders(model, nr: int, na: int):
+    """A copy of a model whose networks ignore every descriptor component of
+    radial order above nr or angular order above na (their first-layer
+    weights set to zero): its energy is a function of the descriptor of a
+    model with orders nr / na and the same cutoffs.  Serves as a teacher that
+    such a student can represent."""
+    import copy
+    out = copy.deepcopy(model)
+    NR, NA = model.radial_order, model.angular_order
+    T1, T2 = NR + 1, NR + NA + 2
+    keep = [a for a in range(NR + 1) if a <= nr] + [T1 + a for a in range(NA + 1) if a <= na]
+    if model.n_species > 1:
+        keep = keep + [T2 + k for k in keep]
+    mask = np.zeros(model.D, dtype=bool)
+    mask[keep] = True
+    for net in out.nets:
+        net.W[0] = np.where(mask[None, :], net.W[0], 0.0)
+    return out
+
+
 @dataclass
 class TrainResult:
     params: np.ndarray

@@ -57,6 +57,40 @@ def test_judge_accepts_good_student_and_replaces_bad_one(orc):
     np.testing.assert_allclose(st.vel, ref.vel, atol=1e-9)
 
 
+def test_restricted_teacher_is_a_function_of_the_smaller_descriptor(orc):
+    """A model restricted to orders (3, 2) computes, through the oracle, what
+    the same networks give on the (3, 2)-order descriptor with the kept
+    first-layer columns (so a student of those orders can represent it)."""
+    nr, na, rr, ra = 6, 4, 5.0, 3.5
+    D = 2 * (nr + 1 + na + 1)
+    g = np.random.default_rng(8)
+    nets = []
+    for t in range(2):
+        n = I.xavier_net([D, 7, 5, 1], 40 + 10 * t)
+        n.shift = g.normal(size=D)
+        n.scale = g.uniform(0.2, 1.0, size=D)
+        nets.append(n)
+    m = I.ModelSpec(2, I.default_type_weights(2), np.array([I.MASS["H"], I.MASS["O"]]), nr, rr, na, ra, nets)
+    r = ST.restrict_to_orders(m, 3, 2)
+    T1, T2 = nr + 1, nr + na + 2
+    keep = [0, 1, 2, 3, T1, T1 + 1, T1 + 2]
+    keep = keep + [T2 + k for k in keep]
+    small_nets = []
+    for n in m.nets:
+        k = I.NetSpec([n.W[0][:, keep], *n.W[1:]], list(n.b), list(n.act), n.shift[keep], n.scale[keep],
+                      n.e_offset)
+        small_nets.append(k)
+    small = I.ModelSpec(2, m.type_weight, m.masses, 3, rr, 2, ra, small_nets)
+    s = I.water_box(12, 21)
+    E1, Ea1, F1 = orc.energy_forces(r, s.pos, s.species, s.box, s.pbc)
+    E0, Ea0, F0 = orc.energy_forces(small, s.pos, s.species, s.box, s.pbc)
+    assert abs(E1 - E0) <= 1e-12 * abs(E0)
+    np.testing.assert_allclose(F1, F0, rtol=0, atol=1e-12)
+    # and it is not the unrestricted model
+    E2, _, _ = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    assert abs(E2 - E0) > 1e-3 * abs(E0)
+
+
 @pytest.mark.gpu
 def test_student_training_improves_forces():
     import torch
