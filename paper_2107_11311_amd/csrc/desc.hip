@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
       if (r2 < ra2) {
         valid = true;
-        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
-        vri = R(1) / r;
+        R r;
+        len_inv<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2), &r, &vri);
         vx = R(d0) * vri;
         vy = R(d1) * vri;
         vz = R(d2) * vri;
@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     nx = n1;
     const R mq = (he && d0 * d0 + d1 * d1 + d2 * d2 < rr2) ? R(1) : R(0);
     const R dx = R(d0), dy = R(d1), dz = R(d2);
-    const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
+    R r, ir;
+    len_inv<R>(dx * dx + dy * dy + dz * dz, &r, &ir);
     const R x = r * inv_rr2 - R(1);
     R sn, cs;
     sincos_cut<R>(r, inv_rr2, &sn, &cs);
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     // dE/dr = S'(x) (2/R_r) f_c + S(x) f_c' with S = sum_a (grt_a + w grw_a) T_a
     R S, dS;
     cheb_series_d<R, NR>(grt, grw, wq, x, &S, &dS);
-    const R sc = mq * (dS * inv_rr2 * fc + S * fcp) / r;
+    const R sc = mq * (dS * inv_rr2 * fc + S * fcp) * ir;
     R px = sc * dx, py = sc * dy, pz = sc * dz;
     if (he && e < na) {
       const int k = kidx[e];
@@ -329,9 +330,10 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
     if (r2 < rr2) {
       const R dx = R(d0), dy = R(d1), dz = R(d2);
-      const R r = sqrt_r<R>(dx * dx + dy * dy + dz * dz);
+      R r, ir;
+      len_inv<R>(dx * dx + dy * dy + dz * dz, &r, &ir);
       const R proj = (dx * R(p.adj[3 * (size_t)q] - ai0) + dy * R(p.adj[3 * (size_t)q + 1] - ai1) +
-                      dz * R(p.adj[3 * (size_t)q + 2] - ai2)) / r;
+                      dz * R(p.adj[3 * (size_t)q + 2] - ai2)) * ir;
       const R x = r * inv_rr2 - R(1);
       R sn, cs;
       sincos_cut<R>(r, inv_rr2, &sn, &cs);
@@ -367,8 +369,8 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
       if (r2 < ra2) {
         valid = true;
-        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
-        vri = R(1) / r;
+        R r;
+        len_inv<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2), &r, &vri);
         vx = R(d0) * vri;
         vy = R(d1) * vri;
         vz = R(d2) * vri;

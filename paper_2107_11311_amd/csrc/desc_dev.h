@@ -55,8 +55,13 @@ __device__ inline void group_reduce_scatter(T (&v)[N], int l) {
     const bool up = (l & mask) != 0;
 #pragma unroll
     for (int k = 0; k < h; ++k) {
-      const T send = up ? v[k] : v[k + h];
-      const T keep = up ? v[k + h] : v[k];
+      // the empty asm hides where lo and hi come from, so the selects stay
+      // selects of values (not a load at a lane-dependent index, which would
+      // put v in scratch memory)
+      T lo = v[k], hi = v[k + h];
+      asm volatile("" : "+v"(lo), "+v"(hi));
+      const T send = up ? lo : hi;
+      const T keep = up ? hi : lo;
       v[k] = keep + __shfl_xor(send, mask, LPA);
     }
   }
@@ -70,66 +75,60 @@ __device__ inline int rs_comp(int l, int i) {
 
 constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
 
+// r = |d| and 1/r from r2 = |d|^2 > 0: the hardware reciprocal square root
+// estimate y refined by Newton's iteration for 1/sqrt, y <- y (3 - r2 y^2)/2,
+// which squares the relative error at each step (two steps in double, one in
+// float, leave a few units in the last place), then r = r2 y.
 template <typename R>
-__device__ inline R sqrt_r(R x);
+__device__ inline void len_inv(R r2, R* r, R* ir);
 template <>
-__device__ inline double sqrt_r<double>(double x) { return sqrt(x); }
+__device__ inline void len_inv<double>(double r2, double* r, double* ir) {
+  const double h = 0.5 * r2;
+  double y = __builtin_amdgcn_rsq(r2);
+  y = y * (1.5 - h * (y * y));
+  y = y * (1.5 - h * (y * y));
+  *ir = y;
+  *r = r2 * y;
+}
 template <>
-__device__ inline float sqrt_r<float>(float x) { return sqrtf(x); }
+__device__ inline void len_inv<float>(float r2, float* r, float* ir) {
+  float y = __builtin_amdgcn_rsqf(r2);
+  y = y * (1.5f - 0.5f * r2 * (y * y));
+  *ir = y;
+  *r = r2 * y;
+}
 
 constexpr double kPi = 3.14159265358979323846;
 
-// sin t and cos t for |t| <= pi/2 by their Taylor series in nested (Horner)
-// form; truncation below 1e-19 (double: terms to t^23 / t^24) or 1e-9
-// (float: terms to t^15 / t^14), i.e. under the rounding error of each type.
-template <typename R>
-__device__ inline void sincos_halfpi(R t, R* s, R* c);
-template <>
-__device__ inline void sincos_halfpi<double>(double t, double* s, double* c) {
-  const double u = t * t;
-  double a = 1.0 - u * (1.0 / 506.0);
-  a = 1.0 - u * (1.0 / 420.0) * a;
-  a = 1.0 - u * (1.0 / 342.0) * a;
-  a = 1.0 - u * (1.0 / 272.0) * a;
-  a = 1.0 - u * (1.0 / 210.0) * a;
-  a = 1.0 - u * (1.0 / 156.0) * a;
-  a = 1.0 - u * (1.0 / 110.0) * a;
-  a = 1.0 - u * (1.0 / 72.0) * a;
-  a = 1.0 - u * (1.0 / 42.0) * a;
-  a = 1.0 - u * (1.0 / 20.0) * a;
-  a = 1.0 - u * (1.0 / 6.0) * a;
-  *s = t * a;
-  double b = 1.0 - u * (1.0 / 552.0);
-  b = 1.0 - u * (1.0 / 462.0) * b;
-  b = 1.0 - u * (1.0 / 380.0) * b;
-  b = 1.0 - u * (1.0 / 306.0) * b;
-  b = 1.0 - u * (1.0 / 240.0) * b;
-  b = 1.0 - u * (1.0 / 182.0) * b;
-  b = 1.0 - u * (1.0 / 132.0) * b;
-  b = 1.0 - u * (1.0 / 90.0) * b;
-  b = 1.0 - u * (1.0 / 56.0) * b;
-  b = 1.0 - u * (1.0 / 30.0) * b;
-  b = 1.0 - u * (1.0 / 12.0) * b;
-  *c = 1.0 - u * 0.5 * b;
+// Taylor coefficient of t^n in sin t (n odd) or cos t (n even): +-1/n!
+constexpr double taylor_sc(int n) {
+  double f = 1.0;
+  for (int k = 2; k <= n; ++k) f /= k;
+  return (n / 2) % 2 ? -f : f;
 }
-template <>
-__device__ inline void sincos_halfpi<float>(float t, float* s, float* c) {
-  const float u = t * t;
-  float a = 1.0f - u * (1.0f / 210.0f);
-  a = 1.0f - u * (1.0f / 156.0f) * a;
-  a = 1.0f - u * (1.0f / 110.0f) * a;
-  a = 1.0f - u * (1.0f / 72.0f) * a;
-  a = 1.0f - u * (1.0f / 42.0f) * a;
-  a = 1.0f - u * (1.0f / 20.0f) * a;
-  a = 1.0f - u * (1.0f / 6.0f) * a;
-  *s = t * a;
-  float b = 1.0f - u * (1.0f / 182.0f);
-  b = 1.0f - u * (1.0f / 132.0f) * b;
-  b = 1.0f - u * (1.0f / 90.0f) * b;
-  b = 1.0f - u * (1.0f / 56.0f) * b;
-  b = 1.0f - u * (1.0f / 30.0f) * b;
-  b = 1.0f - u * (1.0f / 12.0f) * b;
-  *c = 1.0f - u * 0.5f * b;
+
+// sum_{k=0..K} taylor_sc(N0 + 2k) u^k by Horner's scheme (one fused
+// multiply-add per term, coefficients fixed at compile time)
+template <typename R, int N0, int K>
+__device__ inline R taylor_poly(R u) {
+  constexpr double c = taylor_sc(N0);
+  if constexpr (K == 0)
+    return R(c);
+  else
+    return taylor_poly<R, N0 + 2, K - 1>(u) * u + R(c);
+}
+
+// sin t and cos t for |t| <= pi/2 by their Taylor series in u = t^2; the
+// first omitted term is below 2e-18 (double: terms to t^21 / t^22) or 7e-10
+// (float: to t^13 / t^14).
+template <typename R>
+__device__ inline void sincos_halfpi(R t, R* s, R* c) {
+  constexpr bool dbl = sizeof(R) == 8;
+  const R u = t * t;
+  const R ps = dbl ? taylor_poly<R, 3, 9>(u) : taylor_poly<R, 3, 5>(u);
+  const R pc = dbl ? taylor_poly<R, 2, 10>(u) : taylor_poly<R, 2, 6>(u);
+  *s = (t * u) * ps + t;
+  *c = u * pc + R(1);
 }
 
 // sin and cos of pi r / R for 0 <= r < R (the cosine cutoff, Eq. 5): with
@@ -196,8 +195,9 @@ __device__ inline void cheb_series_d(const R (&g)[N + 1], const R (&h)[N + 1], R
   R b1 = R(0), b2 = R(0), d1 = R(0), d2 = R(0);
 #pragma unroll
   for (int a = N; a >= 1; --a) {
-    const R c = g[a] + w * h[a];
-    const R bk = x2 * b1 + (c - b2);
+    // (w h_a - b2) + g_a: each operation reads at most one wave-uniform
+    // coefficient, so none has to be copied out of the scalar registers
+    const R bk = x2 * b1 + ((w * h[a] - b2) + g[a]);
     const R dk = x2 * d1 + (R(2) * b1 - d2);
     b2 = b1;
     b1 = bk;
@@ -262,8 +262,9 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
     wb1 = wb2;
     const bool va = a0 * a0 + a1 * a1 + a2 * a2 < rr2;
     const bool vb = hb && (b0 * b0 + b1 * b1 + b2 * b2 < rr2);
-    const R ra = sqrt_r<R>(R(a0) * R(a0) + R(a1) * R(a1) + R(a2) * R(a2));
-    const R rb = sqrt_r<R>(R(b0) * R(b0) + R(b1) * R(b1) + R(b2) * R(b2));
+    R ra, rb, ira, irb;
+    len_inv<R>(R(a0) * R(a0) + R(a1) * R(a1) + R(a2) * R(a2), &ra, &ira);
+    len_inv<R>(R(b0) * R(b0) + R(b1) * R(b1) + R(b2) * R(b2), &rb, &irb);
     const R xa = ra * inv_rr2 - R(1), xb = rb * inv_rr2 - R(1);
     R sna, csa, snb, csb;
     sincos_cut<R>(ra, inv_rr2, &sna, &csa);
@@ -299,8 +300,8 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
       if (r2 < ra2) {
         valid = true;
-        const R r = sqrt_r<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2));
-        const R ir = R(1) / r;
+        R r, ir;
+        len_inv<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2), &r, &ir);
         vx = R(d0) * ir;
         vy = R(d1) * ir;
         vz = R(d2) * ir;
