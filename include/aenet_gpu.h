@@ -210,8 +210,7 @@ aenet_status aenet_set_rebuild_every(aenet_ctx* ctx, int rebuild_every);
 /* Descriptor forward pass and networks in one kernel, per 16-atom tile
  * (enable = 1, where it applies: up to 48 expected angular neighbours and
  * 64 KiB of LDS per tile), or as two kernels (enable = 0).  The results are
- * bitwise the same.  Default: 1 for AENET_FP32 and AENET_BF16, 0 for
- * AENET_FP64 (no faster there). */
+ * bitwise the same.  Default: 1. */
 aenet_status aenet_set_fused(aenet_ctx* ctx, int enable);
 /* Neighbour-row capacities used from the next call on: row_capacity entries
  * per atom within R_r + skin, ang_capacity of them within R_a + skin

@@ -66,6 +66,7 @@ struct NbrParams {
   int* ticket;           // [1] block counter of the binning kernel (0 between builds)
 };
 constexpr int kSegWords = 56;  // 2 row parts x 28 segment boundaries
+constexpr int kRevPending = -2;  // rev values <= this are unresolved (rank, k)
 constexpr int kCellAtomsMax = 64;  // atoms per cell the per-cell row kernel handles
 constexpr int kRowWaves = 16;      // wavefronts per block of the per-cell row kernel
 // LDS bytes of the per-cell row kernel for a candidate capacity tp
@@ -93,7 +94,10 @@ struct DescParams {
   int ldG;               // row stride of G / dE/dG
   void* G;               // [n x ldG] (float or double)
   const void* gG;        // dE/dG [n x ldG]
-  const int* rev;        // [n*cap] global index of the reverse entry
+  int* rev;              // [n*cap] global index of the reverse entry, -1 if
+                         // none, or kRevPending - (rank | k << 16) as left by
+                         // the per-cell row build (resolved by the force pass)
+  const uint16_t* segs;  // [n*kSegWords] segment starts of the rows
   void* pg;              // [n*cap*3] dE_i/dd_e, stored at the slot of the
                          // reverse entry: pg[rev(i,e)] (see the force gather)
   double* Fself;         // [n*3]  sum_e dE_i/dd_e

@@ -123,9 +123,9 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     }
     if (nv <= 64) {
       // Unordered pairs by rotation: the lane owning entry e takes at step t
-      // the pair (e, (e + t) mod nv), adds the gradient w.r.t. its own entry
-      // and passes the partner's gradient to the lane owning the partner (a
-      // rotation by t).  Steps t = 1..floor(nv/2) visit every pair once (for
+      // the pair (e, (e + t) mod nv), adds the pair's terms to the sums of its
+      // own entry and passes the partner's terms to the lane owning the
+      // partner (a rotation by t).  Steps t = 1..floor(nv/2) visit every pair once (for
       // even nv the last step is taken by entries e < t only).  With nv <= 32
       // both halves of the wave hold all entries and share the steps: the
       // lower half takes t = 1..T1, the upper half the rest.
@@ -139,8 +139,13 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
       const int cnt = half ? T - Tlo : Tlo;
       const int lane0 = half << 5;  // first lane of this half
       const int k = own ? e : 0;
-      const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
-      R ax = 0, ay = 0, az = 0;
+      const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], wk = ws[k];
+      // With F(c) = sum_a (ga_a + w_j w_k gw_a) T_a(c), A = F, B = F' and
+      // c = u_j . u_k, the pair (j, k) adds to dE/dd_k
+      //   f_j [B f_k (u_j - c u_k) / r_k + A f_k' u_k],
+      // so each lane sums V = sum_j B f_j u_j, s1 = sum_j B f_j c and
+      // s2 = sum_j A f_j over its partners and forms the gradient once.
+      R vx = 0, vy = 0, vz = 0, s1 = 0, s2 = 0;
       for (int st = 1; st <= Tlo; ++st) {
         const int t = t0 + st;
         const bool go = own && st <= cnt;
@@ -148,42 +153,47 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
         if (m >= nv) m -= nv;
         if (!go) m = k;
         const R wgt = (go && (2 * t != nv || e < t)) ? R(1) : R(0);
-        const R jx = ux[m], jy = uy[m], jz = uz[m], fm = fs[m], fpm = fp[m], rim = ri[m];
+        const R jx = ux[m], jy = uy[m], jz = uz[m], fm = fs[m];
         const R c = jx * kx + jy * ky + jz * kz;
         R A, B;
         cheb_series_d<R, NA>(ga, gw, ws[m] * wk, c, &A, &B);
         A *= wgt;
         B *= wgt;
         // own side
-        const R cbk = B * fk * fm * rik, cak = A * fm * fpk;
-        ax += cbk * (jx - c * kx) + cak * kx;
-        ay += cbk * (jy - c * ky) + cak * ky;
-        az += cbk * (jz - c * kz) + cak * kz;
+        const R bj = B * fm;
+        vx += bj * jx;
+        vy += bj * jy;
+        vz += bj * jz;
+        s1 += bj * c;
+        s2 += A * fm;
         // partner side, delivered by rotation: this lane receives from the
         // lane owning entry (e - t) mod nv in the same half
-        const R cbm = B * fk * fm * rim, cam = A * fk * fpm;
-        const R gxm = cbm * (kx - c * jx) + cam * jx;
-        const R gym = cbm * (ky - c * jy) + cam * jy;
-        const R gzm = cbm * (kz - c * jz) + cam * jz;
+        const R bk = B * fk;
         int src = e - t;
         if (src < 0) src += nv;
         src = go ? lane0 + src : l;
-        const R rx = __shfl(gxm, src, 64), ry = __shfl(gym, src, 64), rz = __shfl(gzm, src, 64);
+        const R rx = __shfl(bk * kx, src, 64), ry = __shfl(bk * ky, src, 64), rz = __shfl(bk * kz, src, 64);
+        const R r1 = __shfl(bk * c, src, 64), r2 = __shfl(A * fk, src, 64);
         if (go) {
-          ax += rx;
-          ay += ry;
-          az += rz;
+          vx += rx;
+          vy += ry;
+          vz += rz;
+          s1 += r1;
+          s2 += r2;
         }
       }
       if (split) {
-        ax += __shfl_xor(ax, 32, 64);
-        ay += __shfl_xor(ay, 32, 64);
-        az += __shfl_xor(az, 32, 64);
+        vx += __shfl_xor(vx, 32, 64);
+        vy += __shfl_xor(vy, 32, 64);
+        vz += __shfl_xor(vz, 32, 64);
+        s1 += __shfl_xor(s1, 32, 64);
+        s2 += __shfl_xor(s2, 32, 64);
       }
       if (own && half == 0) {
-        gx[e] = R(2) * ax;
-        gy[e] = R(2) * ay;
-        gz[e] = R(2) * az;
+        const R cb = R(2) * fk * ri[k], ca_ = R(2) * fp[k] * s2 - cb * s1;
+        gx[e] = cb * vx + ca_ * kx;
+        gy[e] = cb * vy + ca_ * ky;
+        gz[e] = cb * vz + ca_ * kz;
       }
     } else {
       // crowded shells: each lane owns entries k = l, l + 64, ... and sums
@@ -219,7 +229,8 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     grw[a] = (active && p.weighted) ? gG[T2 + a] : R(0);
   }
   R* pg = reinterpret_cast<R*>(p.pg);
-  const int* rev = p.rev + (size_t)(active ? i : 0) * p.cap;
+  int* rev = p.rev + (size_t)(active ? i : 0) * p.cap;
+  const int n_slots = p.n * p.cap;
   double sx = 0.0, sy = 0.0, sz = 0.0;
   // one entry per lane per iteration, the next one's position loaded ahead;
   // entries beyond R_r (skin) get a zero gradient through a zero weight, and
@@ -261,8 +272,21 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     if (he) {
       // stored at the reverse entry's slot, where the force gather of the
       // neighbour reads it (no slot if the list was flagged asymmetric)
-      const int dst = rev[e];
-      if (dst >= 0) {
+      int dst = rev[e];
+      if (dst <= kRevPending) {
+        // first use after a per-cell row build: the reverse entry (q -> i)
+        // is the rank-th entry of the segment of stencil cell 26 - k in q's
+        // row part; resolved once and stored back
+        const int info = kRevPending - dst, rank = info & 0xffff, k = info >> 16;
+        const int q = (int)(row[e] & kAtomMask);
+        const uint16_t* sq = p.segs + (size_t)q * kSegWords + (e < na ? 0 : 28);
+        const int at = k <= 26 ? (int)sq[26 - k] + rank : 0;
+        const bool ok = k <= 26 && at < (int)sq[27 - k];
+        dst = ok ? q * p.cap + at : -1;
+        if (!ok) atomicOr(p.flags, kFlagReverse);
+        rev[e] = dst;
+      }
+      if (dst >= 0 && dst < n_slots) {
         pg[3 * (size_t)dst] = px;
         pg[3 * (size_t)dst + 1] = py;
         pg[3 * (size_t)dst + 2] = pz;

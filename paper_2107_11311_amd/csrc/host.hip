@@ -477,6 +477,7 @@ DescParams desc_params(aenet_ctx* c) {
   p.G = c->d_G.p;
   p.gG = c->d_gG.p;
   p.rev = c->d_rev.as<int>();
+  p.segs = c->d_segs.as<uint16_t>();
   p.pg = c->d_pg.p;
   p.Fself = c->d_Fself.as<double>();
   p.adj = c->d_adj.as<double>();
@@ -734,7 +735,7 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
   c->skin = m->skin;
   c->rlist = std::max(c->rr, c->ra) + c->skin;
   c->prec = m->precision;
-  c->fused = c->prec != AENET_FP64;
+  c->fused = true;
   c->device = m->device;
   const int typed = c->nr + 1 + c->na + 1;
   c->D = c->S > 1 ? 2 * typed : typed;

@@ -370,8 +370,9 @@ __global__ __launch_bounds__(256) void k_reverse(NbrParams p) {
 // (q -> i) in stencil cell 26 - k of q, whose segment of q's row holds
 // exactly the central atoms that accepted q there, ordered by index: its
 // position inside the segment is the number of set bits below i's.  The
-// block stores that rank with k in rev; k_reverse_rank adds the segment start
-// once every row is built.
+// block stores that rank with k in rev (as kRevPending - (rank | k << 16));
+// the force pass, which runs after every row is built, adds the segment start
+// on its first use of the entry and stores the result back.
 constexpr int kMaskWords = kCellAtomsMax / 32;
 
 __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
@@ -576,37 +577,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
         const uint32_t below = ai >= lo + 32 ? 0xffffffffu : (ai <= lo ? 0u : ((1u << (ai - lo)) - 1u));
         rank += __popc(m[w] & below);
       }
-      slot[e] = rank | (k << 16);
-    }
-  }
-}
-
-// rev = q * cap + (start of the segment of stencil cell 26 - k in q's row
-// part) + rank, from the (rank, k) left by k_rows_cell
-__global__ __launch_bounds__(256) void k_reverse_rank(NbrParams p) {
-  if (skip(p)) return;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= p.n) return;
-  const int nn = p.nnb[i], na = p.nang[i];
-  const uint32_t* row = p.nbr + (size_t)i * p.cap;
-  int* rv = p.rev + (size_t)i * p.cap;
-  for (int e = lane; e < nn; e += 64) {
-    const int q = (int)(row[e] & kAtomMask);
-    const int info = rv[e];
-    const int rank = info & 0xffff, k = info >> 16;
-    bool ok = k >= 0 && k <= 26;  // (a cell whose rows were not built this time leaves junk)
-    int pos = 0;
-    if (ok) {
-      const uint16_t* sq = p.segs + (size_t)q * kSegWords + (e < na ? 0 : 28);
-      pos = (int)sq[26 - k] + rank;
-      ok = pos < (int)sq[27 - k];
-    }
-    if (!ok) {
-      atomicOr(p.flags, kFlagReverse);
-      rv[e] = -1;
-    } else {
-      rv[e] = q * p.cap + pos;
+      slot[e] = kRevPending - (rank | (k << 16));
     }
   }
 }
@@ -625,7 +596,6 @@ void launch_build_neighbors(const NbrParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
   if (p.tp > 0) {
     hipLaunchKernelGGL(k_rows_cell, dim3(p.n_cells), dim3(64 * kRowWaves), cell_rows_lds(p.tp, p.cap), s, p);
-    hipLaunchKernelGGL(k_reverse_rank, dim3(blocks_for(p.n, 4)), dim3(256), 0, s, p);
   } else {
     hipLaunchKernelGGL(k_sort_cells, dim3(p.n_cells), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_rows, dim3(blocks_for(p.n, 4)), dim3(256), (size_t)4 * p.cap * sizeof(uint32_t), s, p);
