@@ -51,9 +51,12 @@ __global__ __launch_bounds__(256, 3) void k_fwd_mlp(DescParams dp, MlpParams mp,
   // padding columns, and the rows of a tile shorter than 16 atoms, are zero
   for (int c = l; c < w0; c += LPA)
     if (!active || c >= D) xrow[c] = T(0);
+  // the first layer's weights are on their way while the block waits
+  Frag<PREC> b0{};
+  mlp_prefetch<PREC>(mp, net, 0, threadIdx.x >> 6, threadIdx.x & 63, b0);
   __syncthreads();
   // the network's work buffers reuse the descriptor pass's LDS
-  mlp_tile<PREC>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x);
+  mlp_tile<PREC>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x, b0);
 }
 
 template <int PREC, int NR, int NA>

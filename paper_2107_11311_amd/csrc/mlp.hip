@@ -35,6 +35,8 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
   const int tid = threadIdx.x;
   const TileInfo ti = tile_info(p, blockIdx.x);
   const MlpNet& net = p.net[ti.species];
+  Frag<PREC> b0{};
+  mlp_prefetch<PREC>(p, net, 0, tid >> 6, tid & 63, b0);
   {
     const T* G = reinterpret_cast<const T*>(p.G);
     const T* sh = reinterpret_cast<const T*>(net.shift);
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
     }
   }
   __syncthreads();
-  mlp_tile<PREC>(p, ti, lds, lds + act_offset(p, 1), tid);
+  mlp_tile<PREC>(p, ti, lds, lds + act_offset(p, 1), tid, b0);
 }
 
 // ------------------------------------------------------------------ training

@@ -47,13 +47,39 @@ __device__ inline int acc_row(int lane, int i) {
   return PREC == 0 ? (lane >> 4) + 4 * i : 4 * (lane >> 4) + i;
 }
 
-// one 16x16 output block: sum over K of A[16 x K] (LDS, row-major, row stride
-// ld) times the packed B operand block nb (K/KS k-steps).  All operands of the
-// block are loaded before the MFMA chain so their latencies overlap.
+// The B operand of one 16-column output block held by one wavefront: K/KS
+// k-steps of one packed element (FP64/FP32) or eight BF16 values per lane.
 template <int PREC>
-__device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* A, int ld, int K,
-                                                     const typename Mt<PREC>::B* Bp, int nb,
-                                                     int lane) {
+struct Frag {
+  typename Mt<PREC>::B b[kMaxWidth / Mt<PREC>::KS][Mt<PREC>::BV];
+};
+
+// issue the loads of output block nb's B operand (K/KS k-steps)
+template <int PREC>
+__device__ inline void load_frag(Frag<PREC>& f, const typename Mt<PREC>::B* Bp, int nb, int K, int lane) {
+  typedef Mt<PREC> M;
+  constexpr int MAXKS = kMaxWidth / M::KS;
+  const int ksteps = K / M::KS;
+#pragma unroll
+  for (int ks = 0; ks < MAXKS; ++ks) {
+    if (ks < ksteps) {
+      if constexpr (PREC == 2) {
+        const v8bf v = *reinterpret_cast<const v8bf*>(Bp + (((size_t)nb * ksteps + ks) * 64 + lane) * 8);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) f.b[ks][t] = v[t];
+      } else {
+        f.b[ks][0] = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
+      }
+    }
+  }
+}
+
+// one 16x16 output block: sum over K of A[16 x K] (LDS, row-major, row stride
+// ld) times the B operand in f.  All A operands are loaded before the MFMA
+// chain so their latencies overlap.
+template <int PREC>
+__device__ inline typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A, int ld, int K,
+                                                    const Frag<PREC>& f, int lane) {
   typedef Mt<PREC> M;
   typename M::Acc acc = {0, 0, 0, 0};
   const int ksteps = K / M::KS;
@@ -61,14 +87,10 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
   if constexpr (PREC == 0 || PREC == 1) {
     typedef typename M::T T;
     constexpr int MAXKS = kMaxWidth / 4;
-    T a[MAXKS], b[MAXKS];
+    T a[MAXKS];
 #pragma unroll
-    for (int ks = 0; ks < MAXKS; ++ks) {
-      if (ks < ksteps) {
-        a[ks] = A[r * ld + ks * 4 + kq];
-        b[ks] = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
-      }
-    }
+    for (int ks = 0; ks < MAXKS; ++ks)
+      if (ks < ksteps) a[ks] = A[r * ld + ks * 4 + kq];
     // two independent accumulation chains (even / odd k-steps) halve the
     // dependent MFMA latency
     typename M::Acc acc1 = {0, 0, 0, 0};
@@ -76,15 +98,15 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
     for (int ks = 0; ks < MAXKS; ks += 2) {
       if (ks < ksteps) {
         if constexpr (PREC == 0)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], f.b[ks][0], acc, 0, 0, 0);
         else
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], b[ks], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], f.b[ks][0], acc, 0, 0, 0);
       }
       if (ks + 1 < ksteps) {
         if constexpr (PREC == 0)
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks + 1], b[ks + 1], acc1, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks + 1], f.b[ks + 1][0], acc1, 0, 0, 0);
         else
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks + 1], b[ks + 1], acc1, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks + 1], f.b[ks + 1][0], acc1, 0, 0, 0);
       }
     }
     acc += acc1;
@@ -93,7 +115,7 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
     // pair hi + lo of BF16 values (lo = the rounding error of hi), two
     // products per k-step on the BF16 MFMA, FP32 accumulation
     constexpr int MAXKS = kMaxWidth / 32;
-    v8bf ah[MAXKS], al[MAXKS], b[MAXKS];
+    v8bf ah[MAXKS], al[MAXKS], bb[MAXKS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks) {
       if (ks < ksteps) {
@@ -103,25 +125,54 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
           const __bf16 hi = (__bf16)ap[t];
           ah[ks][t] = hi;
           al[ks][t] = (__bf16)(ap[t] - (float)hi);
+          bb[ks][t] = f.b[ks][t];
         }
-        b[ks] = *reinterpret_cast<const v8bf*>(Bp + (((size_t)nb * ksteps + ks) * 64 + lane) * 8);
       }
     }
     typename M::Acc acc1 = {0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks)
       if (ks < ksteps) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], b[ks], acc, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], b[ks], acc1, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bb[ks], acc, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], bb[ks], acc1, 0, 0, 0);
       }
     acc += acc1;
   }
   return acc;
 }
 
+template <int PREC>
+__device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* A, int ld, int K,
+                                                     const typename Mt<PREC>::B* Bp, int nb,
+                                                     int lane) {
+  Frag<PREC> f;
+  load_frag<PREC>(f, Bp, nb, K, lane);
+  return mfma_frag<PREC>(A, ld, K, f, lane);
+}
+
+// tanh z = 1 - 2 / (e^{2z} + 1) with z clamped to [-20, 20] (tanh is +-1 there
+// to double precision); the reciprocal is the hardware estimate refined by two
+// Newton steps.  The absolute error is a few units of 1e-16 (the relative
+// error grows for |z| << 1, which the network's sums do not see).
+__device__ inline double tanh_act(double z) {
+  const double zc = fmin(fmax(z, -20.0), 20.0);
+  const double d = exp(2.0 * zc) + 1.0;
+  double y = __builtin_amdgcn_rcp(d);
+  y = y * (2.0 - d * y);
+  y = y * (2.0 - d * y);
+  return 1.0 - 2.0 * y;
+}
+// single precision: e^{2z} = 2^{2 z log2(e)} and 1 / (e^{2z} + 1) from the
+// hardware exp2 and reciprocal (about 1 ulp each), z clamped to [-10, 10]
+__device__ inline float tanh_act(float z) {
+  const float zc = fminf(fmaxf(z, -10.0f), 10.0f);
+  const float e = __builtin_amdgcn_exp2f(zc * 2.88539008177792681f);
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 template <typename T>
 __device__ inline T act_fn(int act, T z) {
-  return act == 1 ? tanh(z) : z;
+  return act == 1 ? tanh_act(z) : z;
 }
 template <typename T>
 __device__ inline T act_d1(int act, T x) {
@@ -165,16 +216,44 @@ __host__ __device__ inline size_t mlp_work_elems(const MlpParams& p) {
 
 constexpr int kMlpWaves = 4;  // wavefronts per tile
 
+// The matrix products of a tile in order: the hidden layers 1..L-1 forward
+// (stages 0..L-2), then, for the input gradient, layers L-1..1 backward.
+// Stage s multiplies a 16 x K operand by the B operand of `Bp` (K x N).
+struct MlpStage {
+  const void* Bp;
+  int K, N;
+};
+__device__ inline MlpStage mlp_stage(const MlpParams& p, const MlpNet& net, int s) {
+  const int H = p.n_layers - 1;
+  if (s < H) return MlpStage{net.wf[s + 1], p.wp[s], p.wp[s + 1]};
+  const int l = H - (s - H);
+  return MlpStage{net.wb[l], p.wp[l], p.wp[l - 1]};
+}
+__device__ inline int mlp_n_stages(const MlpParams& p) { return (p.n_layers - 1) * (p.gG ? 2 : 1); }
+
+// Issue wavefront `wave`'s B-operand loads of stage s (it owns the 16-column
+// block nb = wave; a layer is at most kMaxWidth = 16 * kMlpWaves wide).
+template <int PREC>
+__device__ inline void mlp_prefetch(const MlpParams& p, const MlpNet& net, int s, int wave, int lane,
+                                    Frag<PREC>& f) {
+  if (s >= mlp_n_stages(p)) return;
+  const MlpStage st = mlp_stage(p, net, s);
+  if (wave < st.N / 16)
+    load_frag<PREC>(f, reinterpret_cast<const typename Mt<PREC>::B*>(st.Bp), wave, st.K, lane);
+}
+
 // Hidden layers, energy and (if p.gG) input gradient of one 16-atom tile
 // whose normalised input is in X0, by kMlpWaves wavefronts (tid < 64 *
-// kMlpWaves): the 16-column output blocks of every layer are dealt out over
-// the waves, with a block barrier between layers.
+// kMlpWaves): wavefront w computes the 16-column output block w of every
+// layer, with a block barrier between layers.  `b0` holds the wavefront's
+// B operand of the first stage (mlp_prefetch(p, net, 0, ...)); each stage
+// issues the loads of the next one before its own products.
 template <int PREC>
 __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename Mt<PREC>::T* X0,
-                                typename Mt<PREC>::T* work, int tid) {
+                                typename Mt<PREC>::T* work, int tid, const Frag<PREC>& b0) {
   typedef typename Mt<PREC>::T T;
-  typedef typename Mt<PREC>::B Bt;
   constexpr int NT = 64 * kMlpWaves;
+  static_assert(16 * kMlpWaves == kMaxWidth, "one output block per wavefront and layer");
   const int lane = tid & 63, wave = tid >> 6;
   const MlpNet& net = p.net[ti.species];
   const int L = p.n_layers;
@@ -183,35 +262,43 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
   auto X = [&](int l) { return l == 0 ? X0 : work + (act_offset(p, l) - base1); };
   T* D0 = work + (act_offset(p, L) - base1);
   T* D1 = D0 + 16 * DLD;
+  Frag<PREC> cur = b0, nxt{};
+  int s = 0;
 
   // hidden layers
-  for (int l = 1; l < L; ++l) {
+  for (int l = 1; l < L; ++l, ++s) {
+    mlp_prefetch<PREC>(p, net, s + 1, wave, lane, nxt);
     const T* Xin = X(l - 1);
     T* Y = X(l);
     const int K = p.wp[l - 1], N = p.wp[l];
-    const Bt* Bp = reinterpret_cast<const Bt*>(net.wf[l]);
     const T* bias = reinterpret_cast<const T*>(net.bias[l]);
     const int act = p.act[l - 1];
-    for (int nb = wave; nb < N / 16; nb += kMlpWaves) {
-      auto acc = mfma_block<PREC>(Xin, K + 1, K, Bp, nb, lane);
-      const int col = nb * 16 + (lane & 15);
+    if (wave < N / 16) {
+      auto acc = mfma_frag<PREC>(Xin, K + 1, K, cur, lane);
+      const int col = wave * 16 + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = acc_row<PREC>(lane, i);
         Y[row * (N + 1) + col] = act_fn<T>(act, T(acc[i]) + bias[col]);
       }
     }
+    cur = nxt;
     __syncthreads();
   }
 
-  // output layer and per-atom energy
+  // output layer and per-atom energy: 16 lanes per row, each summing every
+  // 16th column, then a 16-lane tree
   const T* XL = X(L - 1);
   const int KL = p.wp[L - 1];
   const T* wl = reinterpret_cast<const T*>(net.wlast);
-  if (tid < 16) {
+  {
+    static_assert(NT == 256, "16 rows x 16 lanes");
+    const int r = tid >> 4, c0 = tid & 15;
     T e = T(0);
-    for (int k = 0; k < KL; ++k) e += XL[tid * (KL + 1) + k] * wl[k];
-    if (tid < ti.count) p.E[ti.first + tid] = (double)e + net.blast + net.e_offset;
+    for (int k = c0; k < KL; k += 16) e += XL[r * (KL + 1) + k] * wl[k];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) e += __shfl_xor(e, o, 16);
+    if (c0 == 0 && r < ti.count) p.E[ti.first + r] = (double)e + net.blast + net.e_offset;
   }
   if (!p.gG) return;
 
@@ -234,14 +321,14 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
     }
     return;
   }
-  for (int l = L - 1; l >= 1; --l) {
+  for (int l = L - 1; l >= 1; --l, ++s) {
+    mlp_prefetch<PREC>(p, net, s + 1, wave, lane, nxt);
     const int K = p.wp[l], N = p.wp[l - 1];
-    const Bt* Bp = reinterpret_cast<const Bt*>(net.wb[l]);
     const T* Xp = X(l - 1);
     const int actp = l >= 2 ? p.act[l - 2] : 0;
-    for (int nb = wave; nb < N / 16; nb += kMlpWaves) {
-      auto acc = mfma_block<PREC>(Dcur, DLD, K, Bp, nb, lane);
-      const int col = nb * 16 + (lane & 15);
+    if (wave < N / 16) {
+      auto acc = mfma_frag<PREC>(Dcur, DLD, K, cur, lane);
+      const int col = wave * 16 + (lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = acc_row<PREC>(lane, i);
@@ -253,6 +340,7 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
         }
       }
     }
+    cur = nxt;
     __syncthreads();
     T* t = Dcur;
     Dcur = Dnext;
