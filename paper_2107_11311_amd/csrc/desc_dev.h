@@ -324,48 +324,40 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
   }
   __syncthreads();
 
-  // angular terms, Eq. 6: unordered pairs j < k, lanes strided over the pair
-  // index, two pairs per iteration (the second with weight 0 past the end)
-  if (nv >= 2) {
-    int j = 0, rem = l;
-    while (j < nv - 1 && rem >= nv - 1 - j) {
-      rem -= nv - 1 - j;
-      ++j;
-    }
-    int k = j + 1 + rem;
-    while (j < nv - 1) {
-      int j2 = j, k2 = k + LPA;
-      while (j2 < nv - 1 && k2 >= nv) {
-        k2 = k2 - nv + j2 + 2;
-        ++j2;
-      }
-      const bool v2 = j2 < nv - 1;
-      const int jb = v2 ? j2 : j, kb = v2 ? k2 : k;
-      const R ca = ux[j] * ux[k] + uy[j] * uy[k] + uz[j] * uz[k];
-      const R cb = ux[jb] * ux[kb] + uy[jb] * uy[kb] + uz[jb] * uz[kb];
-      const R fa = fs[j] * fs[k];
-      const R fb = v2 ? fs[jb] * fs[kb] : R(0);
-      const R wa = ws[j] * ws[k] * fa, wb = ws[jb] * ws[kb] * fb;
-      R ta0 = R(1), ta1 = ca, tb0 = R(1), tb1 = cb;
-      at[0] += fa + fb;
-      aw[0] += wa + wb;
+  // angular terms, Eq. 6, over the unordered pairs {e, (e + t) mod nv},
+  // t = 1..floor(nv/2) (for even nv the pairs at t = nv/2 are counted from
+  // e < nv/2 only): the lane owning entry e (entries l, l + LPA, ...) keeps
+  // it in registers and reads the partners from LDS, two steps per iteration
+  // (the second with weight 0 past the last step)
+  {
+    const int T = nv >> 1;
+    for (int e = l; e < nv; e += LPA) {
+      const R kx = ux[e], ky = uy[e], kz = uz[e], fk = fs[e], wk = ws[e];
+      int m = e;
+      for (int t = 1; t <= T; t += 2) {
+        const int ma = m + 1 == nv ? 0 : m + 1;
+        const int mb = ma + 1 == nv ? 0 : ma + 1;
+        m = mb;
+        const bool hb = t + 1 <= T;
+        const R ca = ux[ma] * kx + uy[ma] * ky + uz[ma] * kz;
+        const R cb = ux[mb] * kx + uy[mb] * ky + uz[mb] * kz;
+        const R fa = (2 * t != nv || e < t) ? fk * fs[ma] : R(0);
+        const R fb = (hb && (2 * (t + 1) != nv || e < t + 1)) ? fk * fs[mb] : R(0);
+        const R wa = wk * ws[ma] * fa, wb = wk * ws[mb] * fb;
+        R ta0 = R(1), ta1 = ca, tb0 = R(1), tb1 = cb;
+        at[0] += fa + fb;
+        aw[0] += wa + wb;
 #pragma unroll
-      for (int a = 1; a <= NA; ++a) {
-        at[a] += ta1 * fa + tb1 * fb;
-        aw[a] += ta1 * wa + tb1 * wb;
-        const R ta2 = R(2) * ca * ta1 - ta0;
-        const R tb2 = R(2) * cb * tb1 - tb0;
-        ta0 = ta1;
-        ta1 = ta2;
-        tb0 = tb1;
-        tb1 = tb2;
-      }
-      if (!v2) break;
-      j = j2;
-      k = k2 + LPA;
-      while (j < nv - 1 && k >= nv) {
-        k = k - nv + j + 2;
-        ++j;
+        for (int a = 1; a <= NA; ++a) {
+          at[a] += ta1 * fa + tb1 * fb;
+          aw[a] += ta1 * wa + tb1 * wb;
+          const R ta2 = R(2) * ca * ta1 - ta0;
+          const R tb2 = R(2) * cb * tb1 - tb0;
+          ta0 = ta1;
+          ta1 = ta2;
+          tb0 = tb1;
+          tb1 = tb2;
+        }
       }
     }
   }
