@@ -33,6 +33,27 @@ struct BoxInfo {
   int cell_base;  // first global cell id of this structure
 };
 
+// x wrapped into [0, L); a wrapped value maps to itself exactly
+__device__ inline double wrap_coord(double x, double L) {
+  double w = x - L * floor(x / L);
+  if (w >= L) w -= L;
+  if (w < 0.0) w = 0.0;
+  return w;
+}
+
+// global cell of a position (periodic axes wrapped first; non-finite or
+// outside coordinates are clamped into the grid)
+__device__ inline int cell_of(const BoxInfo& b, const int pbc[3], const double x[3]) {
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    const double w = pbc[a] ? wrap_coord(x[a], b.L[a]) : x[a];
+    double fc = floor(w * (double)b.nc[a] / b.L[a]);
+    fc = fmin(fmax(fc, 0.0), (double)(b.nc[a] - 1));
+    c[a] = (int)fc;
+  }
+  return b.cell_base + (c[2] * b.nc[1] + c[1]) * b.nc[0] + c[0];
+}
+
 // ---------------------------------------------------------------- neighbour list
 struct NbrParams {
   int n;                 // atoms
@@ -64,6 +85,13 @@ struct NbrParams {
   int* cond;             // build only if *cond != 0 (NULL = always)
   int* go;               // [1] the decision of this build, for its later kernels
   int* ticket;           // [1] block counter of the binning kernel (0 between builds)
+  // MD with the per-cell row kernel: the integrator has already put every
+  // atom into a fixed-capacity cell bin (kCellAtomsMax slots), so the build is
+  // the row kernel alone; it wraps the positions itself
+  int binned;
+  int* bin_count;        // [2][n_cells] atoms per cell, one half per step parity
+  const int* bin_atoms;  // [n_cells][kCellAtomsMax]
+  int bin_sel;           // half read by this build (the row kernel clears the other)
 };
 constexpr int kSegWords = 56;  // 2 row parts x 28 segment boundaries
 constexpr int kRevPending = -2;  // rev values <= this are unresolved (rank, k)
@@ -183,15 +211,19 @@ struct DriftArgs {
   int* rebuild_flag;
   int* clear_flag;
   int force_rebuild;
+  // cell binning of the drifted positions for the next build (bin_count ==
+  // NULL: none): bin_count is the half of the counts that build reads
+  int* bin_count;
+  int* bin_atoms;
+  const BoxInfo* box;
+  int pbc[3];
 };
 void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
                          const int* species, double half_dt, const DriftArgs& next,
                          hipStream_t s);
-void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
-                     const double* inv_mass_k, const int* species, double half_dt, double dt,
-                     double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild,
-                     hipStream_t s);
+void launch_vv_drift(int n, double* vel, const double* F, const double* inv_mass_k,
+                     const int* species, double half_dt, const DriftArgs& d, hipStream_t s);
 // deterministic sums: out[0] = sum x ; partials has >= reduce_blocks(n) doubles
 int reduce_blocks(int64_t n);
 void launch_sum(int64_t n, const double* x, double* partials, double* out, hipStream_t s);

@@ -87,6 +87,7 @@ struct aenet_ctx {
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
       d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
   DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_segs, d_nnb, d_nang, d_rev;
+  DevMem d_bin_count, d_bin_atoms;  // MD: cell bins filled by the integrator
   DevMem d_build;  // [2] ints: decision of the current build, block counter
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
@@ -1008,6 +1009,16 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
     HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
     bool force_first = false;
     for (int attempt = 0;; ++attempt) {
+      // With the per-cell row kernel the integrator bins the atoms for the
+      // next build as it moves them (two halves of counts by step parity:
+      // the build of step t reads half t & 1 and clears the other).
+      const bool binned = c->tp > 0;
+      const int64_t nc = std::max<int64_t>(c->n_cells, 1);
+      if (binned) {
+        TRY(ensure(c, c->d_bin_count, (size_t)2 * nc * sizeof(int)));
+        TRY(ensure(c, c->d_bin_atoms, (size_t)nc * kCellAtomsMax * sizeof(int)));
+        HIP_TRY(c, hipMemsetAsync(c->d_bin_count.p, 0, (size_t)2 * nc * sizeof(int), s));
+      }
       // the opening half kick and drift of a step are fused into the force
       // gather of the step before it, except for the first step of a chunk
       auto drift_args = [&](int step, bool force) {
@@ -1019,6 +1030,12 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
         d.rebuild_flag = flags + 3 + (step & 1);
         d.clear_flag = flags + 3 + ((step + 1) & 1);
         d.force_rebuild = force ? 1 : 0;
+        if (binned) {
+          d.bin_count = c->d_bin_count.as<int>() + (size_t)(step & 1) * nc;
+          d.bin_atoms = c->d_bin_atoms.as<int>();
+          d.box = c->d_boxes.as<BoxInfo>();
+          for (int a = 0; a < 3; ++a) d.pbc[a] = c->pbc[a];
+        }
         return d;
       };
       for (int k = 0; k < len; ++k) {
@@ -1027,12 +1044,18 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
         if (k == 0) {
           const int force = (step % K == 0) || force_first;
           prof_begin(c, s, AENET_K_INTEGRATE);
-          launch_vv_drift(N, c->d_pos.as<double>(), c->d_vel.as<double>(), c->d_F.as<double>(),
-                          c->d_pos_ref.as<double>(), c->d_invmk.as<double>(), c->d_species.as<int>(),
-                          half_dt, dt, hs2, rb, flags + 3 + ((step + 1) & 1), force, s);
+          launch_vv_drift(N, c->d_vel.as<double>(), c->d_F.as<double>(), c->d_invmk.as<double>(),
+                          c->d_species.as<int>(), half_dt, drift_args(step, force != 0), s);
           prof_end(c, s);
         }
-        build_neighbors_timed(c, nbr_params(c, rb), s);
+        NbrParams np = nbr_params(c, rb);
+        if (binned) {
+          np.binned = 1;
+          np.bin_count = c->d_bin_count.as<int>();
+          np.bin_atoms = c->d_bin_atoms.as<int>();
+          np.bin_sel = step & 1;
+        }
+        build_neighbors_timed(c, np, s);
         if (k + 1 < len) {
           const DriftArgs next = drift_args(step + 1, (step + 1) % K == 0);
           TRY(compute(c, s, true, c->d_vel.as<double>(), half_dt, &next));

@@ -59,6 +59,15 @@ __global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, co
   }
 }
 
+// put atom i at position x into its cell bin for the next build (a bin holds
+// kCellAtomsMax atoms; the count goes on beyond that, and the build then
+// reports the overflow)
+__device__ inline void bin_atom(const DriftArgs& d, int i, const double x[3]) {
+  const int cell = cell_of(*d.box, d.pbc, x);
+  const int rank = atomicAdd(&d.bin_count[cell], 1);
+  if (rank < kCellAtomsMax) d.bin_atoms[(size_t)cell * kCellAtomsMax + rank] = i;
+}
+
 // F_q = sum_e dE_q/dd_e - sum over the entries (i -> q) of dE_i/dd: the first
 // sum was formed by the force pass (Fself); the second is row q of pg, where
 // the force pass stored the gradient of every entry at the slot of its reverse
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
   if (i < n && l == 0) {
     const double f[3] = {Fself[3 * (size_t)i] - sx, Fself[3 * (size_t)i + 1] - sy,
                          Fself[3 * (size_t)i + 2] - sz};
-    double d2 = 0.0;
+    double d2 = 0.0, xn[3];
     for (int a = 0; a < 3; ++a) {
       const size_t k = 3 * (size_t)i + a;
       F[k] = f[a];
@@ -107,6 +116,7 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
           v = v + c * f[a];                  // opening half kick of the next step
           const double x = next.pos[k] + next.dt * v;
           next.pos[k] = x;
+          xn[a] = x;
           const double dd = x - next.pos_ref[k];
           d2 += dd * dd;
         }
@@ -114,32 +124,34 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
       }
     }
     if (next.pos && !(d2 <= next.half_skin2) && *next.rebuild_flag == 0) *next.rebuild_flag = 1;
+    if (next.pos && vel && next.bin_count) bin_atom(next, i, xn);
   }
 }
 
 // first half kick + drift; flags a neighbour-list rebuild when an atom has
 // moved more than skin/2 since the last build
-__global__ void k_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
-                           const double* inv_mass_k, const int* species, double half_dt, double dt,
-                           double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild) {
+__global__ void k_vv_drift(int n, double* vel, const double* F, const double* inv_mass_k,
+                           const int* species, double half_dt, DriftArgs d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    *clear_flag = 0;
-    if (force_rebuild) *rebuild_flag = 1;
+    *d.clear_flag = 0;
+    if (d.force_rebuild) *d.rebuild_flag = 1;
   }
   if (i >= n) return;
   const double c = half_dt * inv_mass_k[species[i]];
-  double d2 = 0.0;
+  double d2 = 0.0, xn[3];
   for (int a = 0; a < 3; ++a) {
     const size_t k = 3 * (size_t)i + a;
     const double v = vel[k] + c * F[k];
     vel[k] = v;
-    const double x = pos[k] + dt * v;
-    pos[k] = x;
-    const double dd = x - pos_ref[k];
+    const double x = d.pos[k] + d.dt * v;
+    d.pos[k] = x;
+    xn[a] = x;
+    const double dd = x - d.pos_ref[k];
     d2 += dd * dd;
   }
-  if (!(d2 <= half_skin2) && *rebuild_flag == 0) *rebuild_flag = 1;
+  if (!(d2 <= d.half_skin2) && *d.rebuild_flag == 0) *d.rebuild_flag = 1;
+  if (d.bin_count) bin_atom(d, i, xn);
 }
 
 constexpr int kRedChunk = 2048;  // elements per partial sum (fixed: results depend only on n)
@@ -270,13 +282,10 @@ void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* p
                        (const float*)pg, Fself, F, vel, inv_mass_k, species, half_dt, next);
 }
 
-void launch_vv_drift(int n, double* pos, double* vel, const double* F, const double* pos_ref,
-                     const double* inv_mass_k, const int* species, double half_dt, double dt,
-                     double half_skin2, int* rebuild_flag, int* clear_flag, int force_rebuild,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_vv_drift, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, s, n, pos, vel, F,
-                     pos_ref, inv_mass_k, species, half_dt, dt, half_skin2, rebuild_flag,
-                     clear_flag, force_rebuild);
+void launch_vv_drift(int n, double* vel, const double* F, const double* inv_mass_k,
+                     const int* species, double half_dt, const DriftArgs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_vv_drift, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, s, n, vel, F,
+                     inv_mass_k, species, half_dt, d);
 }
 
 int reduce_blocks(int64_t n) { return (int)((n + kRedChunk - 1) / kRedChunk); }

@@ -18,10 +18,13 @@
 // search on the atom index; the deterministic force gather uses these
 // reverse entries instead of atomics.
 //
-// A build is five kernels: binning (whose last block also scans the cell
-// counts and resets them for the next build), scatter into cells, per-cell
-// sort, rows, reverse entries.  In MD each of them first checks the device
-// flag of the step, so a step without a rebuild costs five empty launches.
+// A build is binning (whose last block also scans the cell counts and
+// resets them for the next build) and scatter into cells, then either the
+// per-cell row kernel (cells of up to kCellAtomsMax atoms) or per-cell sort,
+// per-atom rows and reverse entries.  In MD each kernel first checks the
+// device flag of the step; with the per-cell row kernel the integrator bins
+// the atoms into fixed-capacity cells as it moves them, and the row kernel is
+// the only launch of the build.
 #include <climits>
 
 #include "aenet_internal.h"
@@ -29,13 +32,6 @@
 namespace aenet {
 
 namespace {
-
-__device__ inline double wrap_coord(double x, double L) {
-  double w = x - L * floor(x / L);
-  if (w >= L) w -= L;
-  if (w < 0.0) w = 0.0;
-  return w;
-}
 
 // the decision of this build, taken by the binning kernel: later kernels of
 // the build follow it
@@ -376,7 +372,14 @@ __global__ __launch_bounds__(256) void k_reverse(NbrParams p) {
 constexpr int kMaskWords = kCellAtomsMax / 32;
 
 __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
-  if (skip(p)) return;
+  if (p.binned) {
+    // every step: clear this cell's count in the half the integrator fills next
+    if (threadIdx.x == 0) p.bin_count[(size_t)(1 - p.bin_sel) * p.n_cells + blockIdx.x] = 0;
+    if (*p.cond == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(p.flags + 8, 1);  // builds triggered on the device
+  } else if (skip(p)) {
+    return;
+  }
   extern __shared__ __align__(16) unsigned char smem[];
   const int tp = p.tp;
   double* s_pos = reinterpret_cast<double*>(smem);                          // [tp][3]
@@ -411,8 +414,13 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
       s_shift[tid][a] = (double)sh[a] * b.L[a];
     }
     const int cell = out ? 0 : b.cell_base + (w[2] * b.nc[1] + w[1]) * b.nc[0] + w[0];
-    s_start[tid] = out ? 0 : p.cell_start[cell];
-    s_cnt[tid] = out ? 0 : p.cell_start[cell + 1] - p.cell_start[cell];
+    if (p.binned) {
+      s_start[tid] = cell * kCellAtomsMax;
+      s_cnt[tid] = out ? 0 : p.bin_count[(size_t)p.bin_sel * p.n_cells + cell];
+    } else {
+      s_start[tid] = out ? 0 : p.cell_start[cell];
+      s_cnt[tid] = out ? 0 : p.cell_start[cell + 1] - p.cell_start[cell];
+    }
     s_code[tid] = (sh[0] + 1) + 3 * (sh[1] + 1) + 9 * (sh[2] + 1);
   }
   __syncthreads();
@@ -443,9 +451,10 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
   // candidates: each stencil cell's atoms sorted by index (one wavefront per
   // cell, a bitonic network across its lanes), so the scatter's atomic order
   // does not reach the rows
+  const int* cell_src = p.binned ? p.bin_atoms : p.cell_atoms;
   for (int k = wv; k < 27; k += kRowWaves) {
     const int cnt = s_cnt[k];
-    uint32_t v = lane < cnt ? (uint32_t)p.cell_atoms[s_start[k] + lane] : 0xffffffffu;
+    uint32_t v = lane < cnt ? (uint32_t)cell_src[s_start[k] + lane] : 0xffffffffu;
 #pragma unroll
     for (int size = 2; size <= 64; size <<= 1) {
 #pragma unroll
@@ -458,9 +467,22 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
     if (lane < cnt) {
       const int t = s_pref[k] + lane;
       s_key[t] = v;
-      s_pos[3 * t] = p.pos[3 * (size_t)v];
-      s_pos[3 * t + 1] = p.pos[3 * (size_t)v + 1];
-      s_pos[3 * t + 2] = p.pos[3 * (size_t)v + 2];
+      double x[3];
+      for (int a = 0; a < 3; ++a) {
+        x[a] = p.pos[3 * (size_t)v + a];
+        // binned: the positions were last wrapped at the previous build; the
+        // block of the atom's own cell stores the wrapped position and the
+        // skin-test reference (other blocks may read either value: wrapping
+        // is idempotent)
+        if (p.binned && p.pbc[a]) x[a] = wrap_coord(x[a], b.L[a]);
+        s_pos[3 * t + a] = x[a];
+      }
+      if (p.binned && k == 13) {
+        for (int a = 0; a < 3; ++a) {
+          p.pos[3 * (size_t)v + a] = x[a];
+          p.pos_ref[3 * (size_t)v + a] = x[a];
+        }
+      }
     }
   }
   for (int t = tid; t < total * 2 * kMaskWords; t += 64 * kRowWaves) s_mask[t] = 0u;
@@ -592,6 +614,10 @@ void launch_set_int(int* dst, int value, hipStream_t s) {
 
 void launch_build_neighbors(const NbrParams& p, hipStream_t s) {
   if (p.n <= 0) return;
+  if (p.binned) {
+    hipLaunchKernelGGL(k_rows_cell, dim3(p.n_cells), dim3(64 * kRowWaves), cell_rows_lds(p.tp, p.cap), s, p);
+    return;
+  }
   hipLaunchKernelGGL(k_bin, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.n, 256)), dim3(256), 0, s, p);
   if (p.tp > 0) {
