@@ -53,9 +53,10 @@ typedef enum {
  * AENET_FP32: descriptor terms and the networks in float32 (networks on FP32
  * MFMA), displacements, per-atom force sums, energies and the integrator in
  * float64.  AENET_BF16: as FP32, with the network weights rounded to
- * bfloat16 (round to nearest even) on BF16 MFMA with float32 accumulation;
- * the float32 activations and deltas enter the MFMA as a pair of bfloat16
- * values (the value rounded, and its rounding error rounded). */
+ * bfloat16 (round to nearest even) on BF16 MFMA with float32 accumulation,
+ * except the input layer, whose weights are kept as a pair of bfloat16 values
+ * (the weight rounded, and its rounding error rounded); the float32
+ * activations and deltas enter the MFMA as such a pair too. */
 typedef enum { AENET_FP64 = 0, AENET_FP32 = 1, AENET_BF16 = 2 } aenet_precision;
 
 typedef enum { AENET_ACT_LINEAR = 0, AENET_ACT_TANH = 1 } aenet_act;

@@ -149,6 +149,10 @@ struct MlpNet {          // device pointers of one species (compute type T = dou
   const void* shift;            // [ldG] compute type (zero padded)
   const void* scale;            // [ldG] compute type (zero padded)
   const void* wfull[kMaxLayers + 1];  // plain row-major W_l (compute type) for training
+  // BF16: layer 1 (the input layer) is held as a pair hi + lo of BF16
+  // operands; these are the packed lo parts (NULL otherwise)
+  const void* wf_lo;
+  const void* wb_lo;
   double blast;
   double e_offset;
 };
@@ -187,7 +191,9 @@ size_t mlp_train_lds_bytes(int prec, const MlpParams& p);
 void launch_mlp_train(int prec, const MlpParams& p, int n_blocks, hipStream_t s);
 // packs B operands for the MFMA layouts; returns element count (host side)
 size_t pack_b_operand_count(int prec, int K, int N);
-void pack_b_operand(int prec, const double* B, int K, int N, int ldb, void* out);
+// part 0: the operand (BF16: rounded to nearest even); part 1 (BF16 only):
+// the BF16 rounding of what part 0 leaves over
+void pack_b_operand(int prec, const double* B, int K, int N, int ldb, void* out, int part = 0);
 
 // ---------------------------------------------------------------- MD, reductions, gathers
 void launch_gather_in(int n, const int* perm, const double* src, double* dst, int* flags,

@@ -67,8 +67,7 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
   const int nn = active ? p.nnb[i] : 0;
   const int na = active ? p.nang[i] : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
-  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
-  const R two_ra = R(2.0 / p.ra);
+  const R inv_rr2 = R(2.0 / p.rr), pi_2rr = R(0.5 * kPi / p.rr), pi_2ra = R(0.5 * kPi / p.ra);
   const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)(active ? i : 0) * p.ldG;
   constexpr int T1 = NR + 1, T2 = NR + NA + 2;
 
@@ -89,10 +88,7 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
         vx = R(d0) * vri;
         vy = R(d1) * vri;
         vz = R(d2) * vri;
-        R sn, cs;
-        sincos_cut<R>(r, two_ra, &sn, &cs);
-        vf = R(0.5) * (cs + R(1));
-        vfp = R(-0.5) * pi_ra * sn;
+        cutoff_d<R>(r, pi_2ra, &vf, &vfp);
         vw = R(p.tw[p.species[q]]);
       }
     }
@@ -253,9 +249,8 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     R r, ir;
     len_inv<R>(dx * dx + dy * dy + dz * dz, &r, &ir);
     const R x = r * inv_rr2 - R(1);
-    R sn, cs;
-    sincos_cut<R>(r, inv_rr2, &sn, &cs);
-    const R fc = R(0.5) * (cs + R(1)), fcp = R(-0.5) * pi_rr * sn;
+    R fc, fcp;
+    cutoff_d<R>(r, pi_2rr, &fc, &fcp);
     // dE/dr = S'(x) (2/R_r) f_c + S(x) f_c' with S = sum_a (grt_a + w grw_a) T_a
     R S, dS;
     cheb_series_d<R, NR>(grt, grw, wq, x, &S, &dS);

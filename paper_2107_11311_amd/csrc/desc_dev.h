@@ -143,6 +143,25 @@ __device__ inline void sincos_cut(R r, R two_over_R, R* sn, R* cs) {
   *cs = -st;
 }
 
+// The cosine cutoff (Eq. 5) and its derivative for 0 <= r < R,
+// f_c = (1 + cos(pi r/R))/2 and f_c' = -(pi/(2R)) sin(pi r/R), from sin and
+// cos of psi = pi r/(2R) - pi/4 in [-pi/4, pi/4) (Taylor series to psi^15 /
+// psi^16 in double, psi^9 / psi^10 in float; the first omitted term is below
+// 5e-17 or 2e-9): pi r/R = 2 psi + pi/2 gives f_c = 1/2 - sin psi cos psi and
+// f_c' = -(pi/(2R)) (cos psi - sin psi)(cos psi + sin psi).
+template <typename R>
+__device__ inline void cutoff_d(R r, R pi_2R, R* fc, R* dfc) {
+  constexpr bool dbl = sizeof(R) == 8;
+  const R psi = r * pi_2R - R(0.25 * kPi);
+  const R u = psi * psi;
+  const R ps = dbl ? taylor_poly<R, 3, 6>(u) : taylor_poly<R, 3, 3>(u);
+  const R pc = dbl ? taylor_poly<R, 2, 7>(u) : taylor_poly<R, 2, 4>(u);
+  const R sn = (psi * u) * ps + psi;
+  const R cs = u * pc + R(1);
+  *fc = R(0.5) - sn * cs;
+  *dfc = -pi_2R * ((cs - sn) * (cs + sn));
+}
+
 // displacement d = r_j + s L - r_i of a packed entry (always in double)
 __device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double xi0, double xi1,
                                  double xi2, uint32_t en, double& d0, double& d1, double& d2) {

@@ -157,14 +157,20 @@ aenet_status pack_networks(aenet_ctx* c) {
     return o;
   };
   struct SpOff {
-    size_t wf[kMaxLayers], wb[kMaxLayers], bias[kMaxLayers], wlast, shift, scale;
+    size_t wf[kMaxLayers], wb[kMaxLayers], bias[kMaxLayers], wlast, shift, scale, wf_lo, wb_lo;
   };
+  // BF16: the input layer as a hi + lo pair of BF16 operands
+  const bool pair1 = prec == 2 && L >= 2;
   std::vector<SpOff> so(S);
   for (int s = 0; s < S; ++s) {
     for (int l = 1; l < L; ++l) {
       so[s].wf[l] = take(pack_b_operand_count(prec, c->wp[l - 1], c->wp[l]) * bel);
       so[s].wb[l] = take(pack_b_operand_count(prec, c->wp[l], c->wp[l - 1]) * bel);
       so[s].bias[l] = take((size_t)c->wp[l] * el);
+    }
+    if (pair1) {
+      so[s].wf_lo = take(pack_b_operand_count(prec, c->wp[0], c->wp[1]) * bel);
+      so[s].wb_lo = take(pack_b_operand_count(prec, c->wp[1], c->wp[0]) * bel);
     }
     so[s].wlast = take((size_t)c->wp[L - 1] * el);
     so[s].shift = take((size_t)c->ldG * el);
@@ -195,6 +201,10 @@ aenet_status pack_networks(aenet_ctx* c) {
           }
         pack_b_operand(prec, Bf.data(), Kp, Np, Np, host.data() + so[s].wf[l]);
         pack_b_operand(prec, Bb.data(), Np, Kp, Kp, host.data() + so[s].wb[l]);
+        if (pair1 && l == 1) {
+          pack_b_operand(prec, Bf.data(), Kp, Np, Np, host.data() + so[s].wf_lo, 1);
+          pack_b_operand(prec, Bb.data(), Np, Kp, Kp, host.data() + so[s].wb_lo, 1);
+        }
         for (int q = 0; q < out; ++q) put(so[s].bias[l], q, b[q]);
       } else {
         for (int k = 0; k < in; ++k) put(so[s].wlast, k, W[k]);
@@ -220,6 +230,8 @@ aenet_status pack_networks(aenet_ctx* c) {
     nt.wlast = base + so[s].wlast;
     nt.shift = base + so[s].shift;
     nt.scale = base + so[s].scale;
+    nt.wf_lo = pair1 ? base + so[s].wf_lo : nullptr;
+    nt.wb_lo = pair1 ? base + so[s].wb_lo : nullptr;
   }
   return AENET_OK;
 }

@@ -331,7 +331,7 @@ size_t pack_b_operand_count(int prec, int K, int N) {
 }
 
 // B is K x N (row-major, ldb), already zero padded to multiples of 32 / 16
-void pack_b_operand(int prec, const double* B, int K, int N, int ldb, void* out) {
+void pack_b_operand(int prec, const double* B, int K, int N, int ldb, void* out, int part) {
   if (prec == 0 || prec == 1) {
     const int ksteps = K / 4;
     for (int nb = 0; nb < N / 16; ++nb)
@@ -352,7 +352,9 @@ void pack_b_operand(int prec, const double* B, int K, int N, int ldb, void* out)
           for (int t = 0; t < 8; ++t) {
             const double v = B[(size_t)(ks * 32 + 8 * (lane / 16) + t) * ldb + nb * 16 + lane % 16];
             const size_t o = (((size_t)nb * ksteps + ks) * 64 + lane) * 8 + t;
-            reinterpret_cast<__hip_bfloat16*>(out)[o] = __float2bfloat16((float)v);
+            const __hip_bfloat16 hi = __float2bfloat16((float)v);
+            reinterpret_cast<__hip_bfloat16*>(out)[o] =
+                part == 0 ? hi : __float2bfloat16((float)(v - (double)__bfloat162float(hi)));
           }
   }
 }

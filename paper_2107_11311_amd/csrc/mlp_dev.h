@@ -49,24 +49,37 @@ __device__ inline int acc_row(int lane, int i) {
 
 // The B operand of one 16-column output block held by one wavefront: K/KS
 // k-steps of one packed element (FP64/FP32) or eight BF16 values per lane.
+// BF16 also holds an optional second operand: the low parts of a layer kept
+// as a BF16 pair (has_lo, wave-uniform).
 template <int PREC>
 struct Frag {
   typename Mt<PREC>::B b[kMaxWidth / Mt<PREC>::KS][Mt<PREC>::BV];
+  typename Mt<PREC>::B lo[PREC == 2 ? kMaxWidth / 32 : 1][PREC == 2 ? 8 : 1];
+  bool has_lo;
 };
 
-// issue the loads of output block nb's B operand (K/KS k-steps)
+// issue the loads of output block nb's B operand (K/KS k-steps), and of its
+// low parts if Blo is not NULL (BF16 only)
 template <int PREC>
-__device__ inline void load_frag(Frag<PREC>& f, const typename Mt<PREC>::B* Bp, int nb, int K, int lane) {
+__device__ inline void load_frag(Frag<PREC>& f, const typename Mt<PREC>::B* Bp, const typename Mt<PREC>::B* Blo,
+                                 int nb, int K, int lane) {
   typedef Mt<PREC> M;
   constexpr int MAXKS = kMaxWidth / M::KS;
   const int ksteps = K / M::KS;
+  f.has_lo = PREC == 2 && Blo != nullptr;
 #pragma unroll
   for (int ks = 0; ks < MAXKS; ++ks) {
     if (ks < ksteps) {
       if constexpr (PREC == 2) {
-        const v8bf v = *reinterpret_cast<const v8bf*>(Bp + (((size_t)nb * ksteps + ks) * 64 + lane) * 8);
+        const size_t o = (((size_t)nb * ksteps + ks) * 64 + lane) * 8;
+        const v8bf v = *reinterpret_cast<const v8bf*>(Bp + o);
 #pragma unroll
         for (int t = 0; t < 8; ++t) f.b[ks][t] = v[t];
+        if (f.has_lo) {
+          const v8bf w = *reinterpret_cast<const v8bf*>(Blo + o);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) f.lo[ks][t] = w[t];
+        }
       } else {
         f.b[ks][0] = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
       }
@@ -113,9 +126,11 @@ __device__ inline typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A
   } else {
     // BF16 weights; the FP32 activations (or deltas) enter as a compensated
     // pair hi + lo of BF16 values (lo = the rounding error of hi), two
-    // products per k-step on the BF16 MFMA, FP32 accumulation
+    // products per k-step on the BF16 MFMA, FP32 accumulation; a layer held
+    // as a weight pair adds the product of the activations' hi part with the
+    // weights' lo part
     constexpr int MAXKS = kMaxWidth / 32;
-    v8bf ah[MAXKS], al[MAXKS], bb[MAXKS];
+    v8bf ah[MAXKS], al[MAXKS], bb[MAXKS], bl[MAXKS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks) {
       if (ks < ksteps) {
@@ -126,6 +141,7 @@ __device__ inline typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A
           ah[ks][t] = hi;
           al[ks][t] = (__bf16)(ap[t] - (float)hi);
           bb[ks][t] = f.b[ks][t];
+          bl[ks][t] = f.lo[ks][t];
         }
       }
     }
@@ -136,6 +152,11 @@ __device__ inline typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bb[ks], acc, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], bb[ks], acc1, 0, 0, 0);
       }
+    if (f.has_lo) {
+#pragma unroll
+      for (int ks = 0; ks < MAXKS; ++ks)
+        if (ks < ksteps) acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], bl[ks], acc1, 0, 0, 0);
+    }
     acc += acc1;
   }
   return acc;
@@ -146,7 +167,7 @@ __device__ inline typename Mt<PREC>::Acc mfma_block(const typename Mt<PREC>::T* 
                                                      const typename Mt<PREC>::B* Bp, int nb,
                                                      int lane) {
   Frag<PREC> f;
-  load_frag<PREC>(f, Bp, nb, K, lane);
+  load_frag<PREC>(f, Bp, nullptr, nb, K, lane);
   return mfma_frag<PREC>(A, ld, K, f, lane);
 }
 
@@ -221,13 +242,14 @@ constexpr int kMlpWaves = 4;  // wavefronts per tile
 // Stage s multiplies a 16 x K operand by the B operand of `Bp` (K x N).
 struct MlpStage {
   const void* Bp;
+  const void* Blo;  // low parts of a BF16 weight pair, or NULL
   int K, N;
 };
 __device__ inline MlpStage mlp_stage(const MlpParams& p, const MlpNet& net, int s) {
   const int H = p.n_layers - 1;
-  if (s < H) return MlpStage{net.wf[s + 1], p.wp[s], p.wp[s + 1]};
+  if (s < H) return MlpStage{net.wf[s + 1], s == 0 ? net.wf_lo : nullptr, p.wp[s], p.wp[s + 1]};
   const int l = H - (s - H);
-  return MlpStage{net.wb[l], p.wp[l], p.wp[l - 1]};
+  return MlpStage{net.wb[l], l == 1 ? net.wb_lo : nullptr, p.wp[l], p.wp[l - 1]};
 }
 __device__ inline int mlp_n_stages(const MlpParams& p) { return (p.n_layers - 1) * (p.gG ? 2 : 1); }
 
@@ -238,8 +260,10 @@ __device__ inline void mlp_prefetch(const MlpParams& p, const MlpNet& net, int s
                                     Frag<PREC>& f) {
   if (s >= mlp_n_stages(p)) return;
   const MlpStage st = mlp_stage(p, net, s);
+  typedef typename Mt<PREC>::B Bt;
   if (wave < st.N / 16)
-    load_frag<PREC>(f, reinterpret_cast<const typename Mt<PREC>::B*>(st.Bp), wave, st.K, lane);
+    load_frag<PREC>(f, reinterpret_cast<const Bt*>(st.Bp), reinterpret_cast<const Bt*>(st.Blo), wave, st.K,
+                    lane);
 }
 
 // Hidden layers, energy and (if p.gG) input gradient of one 16-atom tile
