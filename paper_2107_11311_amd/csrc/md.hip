@@ -59,13 +59,28 @@ __global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, co
   }
 }
 
-// put atom i at position x into its cell bin for the next build (a bin holds
-// kCellAtomsMax atoms; the count goes on beyond that, and the build then
-// reports the overflow)
-__device__ inline void bin_atom(const DriftArgs& d, int i, const double x[3]) {
-  const int cell = cell_of(*d.box, d.pbc, x);
-  const int rank = atomicAdd(&d.bin_count[cell], 1);
-  if (rank < kCellAtomsMax) d.bin_atoms[(size_t)cell * kCellAtomsMax + rank] = i;
+// Put the atoms of the wavefront's lanes with `mine` set (atom i at position
+// x) into their cell bins for the next build.  Lanes with the same cell take
+// one atomic together (consecutive atoms mostly share a cell).  A bin holds
+// kCellAtomsMax atoms; the count goes on beyond that and the build then
+// reports the overflow.  Every lane of the wavefront calls it.
+__device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const double x[3]) {
+  const int lane = threadIdx.x & 63;
+  const int cell = mine ? cell_of(*d.box, d.pbc, x) : -1;
+  uint64_t pending = __ballot(mine);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int lc = __shfl(cell, leader, 64);
+    const uint64_t same = __ballot(cell == lc) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&d.bin_count[lc], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull) {
+      const int rank = base + __popcll(same & ((1ull << lane) - 1ull));
+      if (rank < kCellAtomsMax) d.bin_atoms[(size_t)lc * kCellAtomsMax + rank] = i;
+    }
+    pending &= ~same;
+  }
 }
 
 // F_q = sum_e dE_q/dd_e - sum over the entries (i -> q) of dE_i/dd: the first
@@ -102,10 +117,11 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
     *next.clear_flag = 0;
     if (next.force_rebuild) *next.rebuild_flag = 1;
   }
+  double xn[3] = {0.0, 0.0, 0.0};
   if (i < n && l == 0) {
     const double f[3] = {Fself[3 * (size_t)i] - sx, Fself[3 * (size_t)i + 1] - sy,
                          Fself[3 * (size_t)i + 2] - sz};
-    double d2 = 0.0, xn[3];
+    double d2 = 0.0;
     for (int a = 0; a < 3; ++a) {
       const size_t k = 3 * (size_t)i + a;
       F[k] = f[a];
@@ -124,8 +140,8 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
       }
     }
     if (next.pos && !(d2 <= next.half_skin2) && *next.rebuild_flag == 0) *next.rebuild_flag = 1;
-    if (next.pos && vel && next.bin_count) bin_atom(next, i, xn);
   }
+  if (next.pos && vel && next.bin_count) bin_wave(next, i < n && l == 0, i, xn);
 }
 
 // first half kick + drift; flags a neighbour-list rebuild when an atom has
@@ -137,21 +153,23 @@ __global__ void k_vv_drift(int n, double* vel, const double* F, const double* in
     *d.clear_flag = 0;
     if (d.force_rebuild) *d.rebuild_flag = 1;
   }
-  if (i >= n) return;
-  const double c = half_dt * inv_mass_k[species[i]];
-  double d2 = 0.0, xn[3];
-  for (int a = 0; a < 3; ++a) {
-    const size_t k = 3 * (size_t)i + a;
-    const double v = vel[k] + c * F[k];
-    vel[k] = v;
-    const double x = d.pos[k] + d.dt * v;
-    d.pos[k] = x;
-    xn[a] = x;
-    const double dd = x - d.pos_ref[k];
-    d2 += dd * dd;
+  double xn[3] = {0.0, 0.0, 0.0};
+  if (i < n) {
+    const double c = half_dt * inv_mass_k[species[i]];
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const size_t k = 3 * (size_t)i + a;
+      const double v = vel[k] + c * F[k];
+      vel[k] = v;
+      const double x = d.pos[k] + d.dt * v;
+      d.pos[k] = x;
+      xn[a] = x;
+      const double dd = x - d.pos_ref[k];
+      d2 += dd * dd;
+    }
+    if (!(d2 <= d.half_skin2) && *d.rebuild_flag == 0) *d.rebuild_flag = 1;
   }
-  if (!(d2 <= d.half_skin2) && *d.rebuild_flag == 0) *d.rebuild_flag = 1;
-  if (d.bin_count) bin_atom(d, i, xn);
+  if (d.bin_count) bin_wave(d, i < n, i, xn);
 }
 
 constexpr int kRedChunk = 2048;  // elements per partial sum (fixed: results depend only on n)
