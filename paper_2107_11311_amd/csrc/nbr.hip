@@ -383,7 +383,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tp = p.tp;
   double* s_pos = reinterpret_cast<double*>(smem);                          // [tp][3]
-  uint32_t* s_key = reinterpret_cast<uint32_t*>(s_pos + 3 * (size_t)tp);      // [tp] atom of each candidate
+  uint32_t* s_key = reinterpret_cast<uint32_t*>(s_pos + 3 * (size_t)tp);      // [tp] atom | stencil cell << kImgBits
   uint32_t* s_mask = s_key + tp;                                              // [tp][2][kMaskWords]
   uint32_t* s_rad = s_mask + (size_t)tp * 2 * kMaskWords;                     // [waves][cap]
   __shared__ int s_start[27], s_cnt[27], s_code[27], s_pref[28];
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
     }
     if (lane < cnt) {
       const int t = s_pref[k] + lane;
-      s_key[t] = v;
+      s_key[t] = v | ((uint32_t)k << kImgBits);
       double x[3];
       for (int a = 0; a < 3; ++a) {
         x[a] = p.pos[3 * (size_t)v + a];
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
   const int c0 = s_pref[13];
   uint32_t* rad_t = s_rad + (size_t)wv * p.cap;
   for (int ai = wv; ai < ncen; ai += kRowWaves) {
-    const int i = (int)s_key[c0 + ai];
+    const int i = (int)(s_key[c0 + ai] & kAtomMask);
     const double xi0 = s_pos[3 * (c0 + ai)], xi1 = s_pos[3 * (c0 + ai) + 1], xi2 = s_pos[3 * (c0 + ai) + 2];
     uint32_t* row = p.nbr + (size_t)i * p.cap;
     int* slot = p.rev + (size_t)i * p.cap;  // (candidate slot, stencil cell) of each entry, then (rank, cell)
@@ -504,15 +504,17 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
     for (int base = 0; base < total; base += 64) {
       const int t = base + lane;
       const bool in = t < total;
-      if (in)
-        while (t >= s_pref[k_cell + 1]) ++k_cell;  // s_pref[27] = total > t ends it
       const int tt = in ? t : 0;
-      const int q = (int)s_key[tt];
+      const uint32_t key = s_key[tt];
+      k_cell = (int)(key >> kImgBits);
+      const int q = (int)(key & kAtomMask);
       const double qx = s_pos[3 * tt], qy = s_pos[3 * tt + 1], qz = s_pos[3 * tt + 2];
       const double sx = s_shift[k_cell][0], sy = s_shift[k_cell][1], sz = s_shift[k_cell][2];
       // displacement from the lower-index atom (image shifts counted from
       // it), so that an entry and its reverse agree bit for bit on r^2
-      const bool iq = i < q || (i == q && (sz > 0.0 || (sz == 0.0 && (sy > 0.0 || (sy == 0.0 && sx > 0.0)))));
+      // (bitwise operators: no short-circuit branches)
+      const bool pshift = (sz > 0.0) | ((sz == 0.0) & ((sy > 0.0) | ((sy == 0.0) & (sx > 0.0))));
+      const bool iq = (i < q) | ((i == q) & pshift);
       const double d0 = iq ? (qx + sx) - xi0 : (xi0 - sx) - qx;
       const double d1 = iq ? (qy + sy) - xi1 : (xi1 - sy) - qy;
       const double d2 = iq ? (qz + sz) - xi2 : (xi2 - sz) - qz;
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
       const int at = cnt_a + k;
       if (at < p.cap && k < p.cap) {
         const uint32_t v = rad_t[k];
-        row[at] = s_key[v & 0xffffu] | ((uint32_t)s_code[v >> 16] << kImgBits);
+        row[at] = (s_key[v & 0xffffu] & kAtomMask) | ((uint32_t)s_code[v >> 16] << kImgBits);
         slot[at] = (int)v;
       }
     }
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
 
   // ranks: position of i among the central atoms in the segment of q's row
   for (int ai = wv; ai < ncen; ai += kRowWaves) {
-    const int i = (int)s_key[c0 + ai];
+    const int i = (int)(s_key[c0 + ai] & kAtomMask);
     const int nn = p.nnb[i], na = p.nang[i];
     int* slot = p.rev + (size_t)i * p.cap;
     for (int e = lane; e < nn; e += 64) {
