@@ -126,6 +126,16 @@ struct DescParams {
                          // none, or kRevPending - (rank | k << 16) as left by
                          // the per-cell row build (resolved by the force pass)
   const uint16_t* segs;  // [n*kSegWords] segment starts of the rows
+  // written by the forward pass, read by the force pass and the force
+  // gather: per atom the row positions of the entries that contribute
+  // (within R_r, or in the angular part; n_keep of them, from the front of
+  // the atom's ridx row), and of those just beyond R_r (within a relative
+  // margin of 1e-9 in r^2; n_margin of them, from the back), whose gradient
+  // is zero but is still stored: the gather sums over its own n_keep entries,
+  // and the reverse of each of them is among the stored ones even where the
+  // two directions round r^2 differently.
+  uint16_t* ridx;        // [n*cap]
+  int* nrad;             // [n] n_keep | n_margin << 16
   void* pg;              // [n*cap*3] dE_i/dd_e, stored at the slot of the
                          // reverse entry: pg[rev(i,e)] (see the force gather)
   double* Fself;         // [n*3]  sum_e dE_i/dd_e
@@ -224,7 +234,7 @@ struct DriftArgs {
   const BoxInfo* box;
   int pbc[3];
 };
-void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
+void launch_force_gather(int prec, int n, int cap, const int* nrad, const uint16_t* ridx, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
                          const int* species, double half_dt, const DriftArgs& next,
                          hipStream_t s);

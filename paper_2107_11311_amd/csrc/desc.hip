@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
 //   radial terms, one entry per lane per iteration, adding the angular
 //     gradient of the entry and writing pg.
 template <typename R, int NR, int NA>
-__global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
+__global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int apb = blockDim.x >> 6;
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -228,22 +228,59 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
   int* rev = p.rev + (size_t)(active ? i : 0) * p.cap;
   const int n_slots = p.n * p.cap;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  // one entry per lane per iteration, the next one's position loaded ahead;
-  // entries beyond R_r (skin) get a zero gradient through a zero weight, and
-  // slots past the end of the row repeat its last entry (an empty row reads
-  // the atom itself, always in bounds)
+  // The reverse slot of entry e: on first use after a per-cell row build rev
+  // holds (rank, stencil cell k) and the reverse entry (q -> i) is the rank-th
+  // entry of the segment of stencil cell 26 - k in q's row part; resolved once
+  // and stored back (-1: no slot, the list is flagged asymmetric).
+  auto reverse_slot = [&](int e) {
+    int dst = rev[e];
+    if (dst <= kRevPending) {
+      const int info = kRevPending - dst, rank = info & 0xffff, k = info >> 16;
+      const int q = (int)(row[e] & kAtomMask);
+      const uint16_t* sq = p.segs + (size_t)q * kSegWords + (e < na ? 0 : 28);
+      const int at = k <= 26 ? (int)sq[26 - k] + rank : 0;
+      const bool ok = k <= 26 && at < (int)sq[27 - k];
+      dst = ok ? q * p.cap + at : -1;
+      if (!ok) atomicOr(p.flags, kFlagReverse);
+      rev[e] = dst;
+    }
+    return dst < n_slots ? dst : -1;
+  };
+  // The entries the forward pass listed (the contributing ones from the
+  // front of ridx, then the margin ones from its back: nk in all), one per
+  // lane per iteration with the next one's position loaded ahead; a slot past
+  // the end repeats the last entry (an empty list reads the atom itself,
+  // always in bounds).  Their pg is stored at the reverse entry's slot, where
+  // the force gather of the neighbour reads it.
+  const uint16_t* ridx = p.ridx + (size_t)(active ? i : 0) * p.cap;
+  const int nr_code = active ? p.nrad[i] : 0;
+  const int nkeep = nr_code & 0xffff;
+  const int nk = nkeep + (nr_code >> 16);
   const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
-  auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
-  NbrLoad nx = load_nbr(p, word(l));
-  uint32_t w1 = word(l + 64);
-  for (int e = l; e - l < nn; e += 64) {
-    const NbrLoad n1 = load_nbr(p, w1);
-    w1 = word(e + 128);
-    const bool he = e < nn;
+  // (three dependent loads per entry: its row position, its row word, the
+  // neighbour's position; each is issued one iteration before it is needed)
+  auto entry = [&](int k) {
+    const int kk = k < nk ? k : nk - 1;
+    return nk > 0 ? (int)ridx[kk < nkeep ? kk : p.cap - 1 - (kk - nkeep)] : 0;
+  };
+  auto word = [&](int e) { return nk > 0 ? row[e] : self_word; };
+  int ea = entry(l), eb = entry(l + 64), ec = entry(l + 128);
+  NbrLoad nx = load_nbr(p, word(ea));
+  uint32_t wb = word(eb);
+  for (int k = l; k - l < nk; k += 64) {
+    const NbrLoad n1 = load_nbr(p, wb);
+    wb = word(ec);
+    const int ed = entry(k + 192);
+    const int e = ea;
+    ea = eb;
+    eb = ec;
+    ec = ed;
+    const bool he = k < nk;
     double d0, d1, d2;
     nbr_disp(nx, b, xi0, xi1, xi2, d0, d1, d2);
     const R wq = R(nx.w);
     nx = n1;
+    // angular entries beyond R_r (R_a + skin > R_r) have no radial term
     const R mq = (he && d0 * d0 + d1 * d1 + d2 * d2 < rr2) ? R(1) : R(0);
     const R dx = R(d0), dy = R(d1), dz = R(d2);
     R r, ir;
@@ -257,31 +294,16 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
     const R sc = mq * (dS * inv_rr2 * fc + S * fcp) * ir;
     R px = sc * dx, py = sc * dy, pz = sc * dz;
     if (he && e < na) {
-      const int k = kidx[e];
-      if (k >= 0) {
-        px += gx[k];
-        py += gy[k];
-        pz += gz[k];
+      const int ka = kidx[e];
+      if (ka >= 0) {
+        px += gx[ka];
+        py += gy[ka];
+        pz += gz[ka];
       }
     }
     if (he) {
-      // stored at the reverse entry's slot, where the force gather of the
-      // neighbour reads it (no slot if the list was flagged asymmetric)
-      int dst = rev[e];
-      if (dst <= kRevPending) {
-        // first use after a per-cell row build: the reverse entry (q -> i)
-        // is the rank-th entry of the segment of stencil cell 26 - k in q's
-        // row part; resolved once and stored back
-        const int info = kRevPending - dst, rank = info & 0xffff, k = info >> 16;
-        const int q = (int)(row[e] & kAtomMask);
-        const uint16_t* sq = p.segs + (size_t)q * kSegWords + (e < na ? 0 : 28);
-        const int at = k <= 26 ? (int)sq[26 - k] + rank : 0;
-        const bool ok = k <= 26 && at < (int)sq[27 - k];
-        dst = ok ? q * p.cap + at : -1;
-        if (!ok) atomicOr(p.flags, kFlagReverse);
-        rev[e] = dst;
-      }
-      if (dst >= 0 && dst < n_slots) {
+      const int dst = reverse_slot(e);
+      if (dst >= 0) {
         pg[3 * (size_t)dst] = px;
         pg[3 * (size_t)dst + 1] = py;
         pg[3 * (size_t)dst + 2] = pz;
@@ -291,6 +313,9 @@ __global__ __launch_bounds__(256, 4) void k_desc_bwd(DescParams p) {
       sz += (double)pz;
     }
   }
+  // The other entries (the skin shell) store nothing: no gather reads their
+  // slots.  (An entry that later moves inside R_r resolves its reverse slot
+  // on that first use.)
   sx = group_sum<64>(sx);
   sy = group_sum<64>(sy);
   sz = group_sum<64>(sz);

@@ -267,6 +267,11 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
   auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
   NbrLoad na_ = load_nbr(p, word(l)), nb_ = load_nbr(p, word(l + LPA));
   uint32_t wa1 = word(l + 2 * LPA), wb1 = word(l + 3 * LPA);
+  // for the force pass and the gather: the contributing entries from the
+  // front of ridx, the margin entries from the back (see DescParams)
+  uint16_t* ridx = p.ridx + (size_t)(active ? i : 0) * p.cap;
+  const double rr2m = rr2 * (1.0 + 1e-9);
+  int n_keep = 0, n_marg = 0;
   for (int e = l; e < nn; e += 2 * LPA) {
     const NbrLoad na1 = load_nbr(p, wa1), nb1 = load_nbr(p, wb1);
     const uint32_t wa2 = word(e + 4 * LPA), wb2 = word(e + 5 * LPA);
@@ -279,8 +284,22 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
     nb_ = nb1;
     wa1 = wa2;
     wb1 = wb2;
-    const bool va = a0 * a0 + a1 * a1 + a2 * a2 < rr2;
-    const bool vb = hb && (b0 * b0 + b1 * b1 + b2 * b2 < rr2);
+    const double ra2_ = a0 * a0 + a1 * a1 + a2 * a2, rb2_ = b0 * b0 + b1 * b1 + b2 * b2;
+    const bool va = ra2_ < rr2;
+    const bool vb = hb && (rb2_ < rr2);
+    {
+      const bool ka = va || e < na, kb = hb && (vb || e + LPA < na);
+      const bool sa = !ka && ra2_ < rr2m, sb = hb && !kb && rb2_ < rr2m;
+      const uint64_t ma = group_ballot<LPA>(ka), mb = group_ballot<LPA>(kb);
+      const uint64_t za = group_ballot<LPA>(sa), zb = group_ballot<LPA>(sb);
+      const uint64_t below = (1ull << l) - 1ull;
+      if (ka) ridx[n_keep + __popcll(ma & below)] = (uint16_t)e;
+      if (kb) ridx[n_keep + __popcll(ma) + __popcll(mb & below)] = (uint16_t)(e + LPA);
+      if (sa) ridx[p.cap - 1 - (n_marg + __popcll(za & below))] = (uint16_t)e;
+      if (sb) ridx[p.cap - 1 - (n_marg + __popcll(za) + __popcll(zb & below))] = (uint16_t)(e + LPA);
+      n_keep += __popcll(ma) + __popcll(mb);
+      n_marg += __popcll(za) + __popcll(zb);
+    }
     R ra, rb, ira, irb;
     len_inv<R>(R(a0) * R(a0) + R(a1) * R(a1) + R(a2) * R(a2), &ra, &ira);
     len_inv<R>(R(b0) * R(b0) + R(b1) * R(b1) + R(b2) * R(b2), &rb, &irb);
@@ -306,6 +325,8 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
       tb1 = tb2;
     }
   }
+
+  if (active && l == 0) p.nrad[i] = n_keep | (n_marg << 16);
 
   // compact the angular entries into LDS
   int nv = 0;

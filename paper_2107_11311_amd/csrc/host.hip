@@ -88,6 +88,7 @@ struct aenet_ctx {
       d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
   DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_segs, d_nnb, d_nang, d_rev;
   DevMem d_bin_count, d_bin_atoms;  // MD: cell bins filled by the integrator
+  DevMem d_ridx, d_nrad;            // contributing entries, from the forward pass
   DevMem d_build;  // [2] ints: decision of the current build, block counter
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
@@ -428,11 +429,15 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
 }
 
 aenet_status ensure_rows(aenet_ctx* c) {
+  // row positions are stored in 16 bits (the forward pass's list for the force pass)
+  if (c->cap > 65535) return fail(c, AENET_E_INVALID, "neighbour rows longer than 65535 entries");
   const size_t nb = (size_t)std::max<int64_t>(c->n, 1);
   TRY(ensure(c, c->d_nbr, nb * c->cap * 4));
 
   TRY(ensure(c, c->d_rev, nb * c->cap * 4));
   TRY(ensure(c, c->d_pg, nb * c->cap * 3 * real_size(c)));
+  TRY(ensure(c, c->d_ridx, nb * c->cap * 2));
+  TRY(ensure(c, c->d_nrad, nb * 4));
   return AENET_OK;
 }
 
@@ -491,6 +496,8 @@ DescParams desc_params(aenet_ctx* c) {
   p.gG = c->d_gG.p;
   p.rev = c->d_rev.as<int>();
   p.segs = c->d_segs.as<uint16_t>();
+  p.ridx = c->d_ridx.as<uint16_t>();
+  p.nrad = c->d_nrad.as<int>();
   p.pg = c->d_pg.p;
   p.Fself = c->d_Fself.as<double>();
   p.adj = c->d_adj.as<double>();
@@ -627,7 +634,8 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
     launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s);
     prof_end(c, s);
     prof_begin(c, s, AENET_K_FORCE_GATHER);
-    launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nnb.as<int>(), c->d_pg.p, c->d_Fself.as<double>(), c->d_F.as<double>(), vel,
+    launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nrad.as<int>(), c->d_ridx.as<uint16_t>(), c->d_pg.p,
+                        c->d_Fself.as<double>(), c->d_F.as<double>(), vel,
                         c->d_invmk.as<double>(), c->d_species.as<int>(), half_dt,
                         next ? *next : DriftArgs{}, s);
     prof_end(c, s);

@@ -85,13 +85,14 @@ __device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const doub
 
 // F_q = sum_e dE_q/dd_e - sum over the entries (i -> q) of dE_i/dd: the first
 // sum was formed by the force pass (Fself); the second is row q of pg, where
-// the force pass stored the gradient of every entry at the slot of its reverse
-// entry, so this gather reads each row contiguously.
+// the force pass stored the gradient of every contributing entry at the slot
+// of its reverse entry, so this gather reads within one row: the slots of q's
+// own contributing entries, listed by the forward pass.
 constexpr int kGatherLanes = 16;  // lanes per atom in the force gather
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nnb, const R* pg,
-                                                      const double* Fself, double* F,
+__global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nrad, const uint16_t* ridx,
+                                                      const R* pg, const double* Fself, double* F,
                                                       double* vel, const double* inv_mass_k,
                                                       const int* species, double half_dt,
                                                       DriftArgs next) {
@@ -99,10 +100,12 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
   const int i = blockIdx.x * (blockDim.x / LPA) + g;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  const int nn = i < n ? nnb[i] : 0;
+  const int nk = i < n ? (nrad[i] & 0xffff) : 0;
   const R* row = pg + (size_t)(i < n ? i : 0) * cap * 3;
+  const uint16_t* ri = ridx + (size_t)(i < n ? i : 0) * cap;
 #pragma unroll 4
-  for (int e = l; e < nn; e += LPA) {
+  for (int k = l; k < nk; k += LPA) {
+    const int e = ri[k];
     sx += (double)row[3 * e];
     sy += (double)row[3 * e + 1];
     sz += (double)row[3 * e + 2];
@@ -286,17 +289,17 @@ void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const in
                        boxes, pbc[0], pbc[1], pbc[2], dst);
 }
 
-void launch_force_gather(int prec, int n, int cap, const int* nnb, const void* pg,
+void launch_force_gather(int prec, int n, int cap, const int* nrad, const uint16_t* ridx, const void* pg,
                          const double* Fself, double* F, double* vel, const double* inv_mass_k,
                          const int* species, double half_dt, const DriftArgs& next,
                          hipStream_t s) {
   if (n <= 0) return;
   const dim3 grid(nblk(n, 256 / kGatherLanes)), block(256);
   if (prec == 0)
-    hipLaunchKernelGGL(k_force_gather<double>, grid, block, 0, s, n, cap, nnb,
+    hipLaunchKernelGGL(k_force_gather<double>, grid, block, 0, s, n, cap, nrad, ridx,
                        (const double*)pg, Fself, F, vel, inv_mass_k, species, half_dt, next);
   else
-    hipLaunchKernelGGL(k_force_gather<float>, grid, block, 0, s, n, cap, nnb,
+    hipLaunchKernelGGL(k_force_gather<float>, grid, block, 0, s, n, cap, nrad, ridx,
                        (const float*)pg, Fself, F, vel, inv_mass_k, species, half_dt, next);
 }
 
