@@ -64,9 +64,8 @@ __global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, co
 // one atomic together (consecutive atoms mostly share a cell).  A bin holds
 // kCellAtomsMax atoms; the count goes on beyond that and the build then
 // reports the overflow.  Every lane of the wavefront calls it.
-__device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const double x[3]) {
+__device__ inline void bin_wave_cells(const DriftArgs& d, bool mine, int i, int cell) {
   const int lane = threadIdx.x & 63;
-  const int cell = mine ? cell_of(*d.box, d.pbc, x) : -1;
   uint64_t pending = __ballot(mine);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -81,6 +80,9 @@ __device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const doub
     }
     pending &= ~same;
   }
+}
+__device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const double x[3]) {
+  bin_wave_cells(d, mine, i, mine ? cell_of(*d.box, d.pbc, x) : -1);
 }
 
 // F_q = sum_e dE_q/dd_e - sum over the entries (i -> q) of dE_i/dd: the first
@@ -144,7 +146,21 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
     }
     if (next.pos && !(d2 <= next.half_skin2) && *next.rebuild_flag == 0) *next.rebuild_flag = 1;
   }
-  if (next.pos && vel && next.bin_count) bin_wave(next, i < n && l == 0, i, xn);
+  if (next.pos && vel && next.bin_count) {
+    // the block's 16 atoms are binned by its first wavefront, so atoms of one
+    // cell share one atomic across the block
+    __shared__ int s_cell[256 / LPA], s_atom[256 / LPA];
+    if (l == 0) {
+      s_cell[g] = i < n ? cell_of(*next.box, next.pbc, xn) : -1;
+      s_atom[g] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int t = threadIdx.x;
+      const bool mine = t < 256 / LPA && s_cell[t] >= 0;
+      bin_wave_cells(next, mine, mine ? s_atom[t] : 0, mine ? s_cell[t] : -1);
+    }
+  }
 }
 
 // first half kick + drift; flags a neighbour-list rebuild when an atom has
