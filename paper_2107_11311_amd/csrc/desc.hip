@@ -20,6 +20,7 @@ namespace {
 template <typename R, int NR, int NA, int LPA>
 __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __builtin_amdgcn_s_setprio(3);
   const int apb = blockDim.x / LPA;
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
   const int i = blockIdx.x * apb + g;
