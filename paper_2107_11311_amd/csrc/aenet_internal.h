@@ -136,6 +136,7 @@ struct DescParams {
   // two directions round r^2 differently.
   uint16_t* ridx;        // [n*cap]
   int* nrad;             // [n] n_keep | n_margin << 16
+  int prio;              // set by the launcher: phase-wise wave priorities (see desc_dev.h)
   void* pg;              // [n*cap*3] dE_i/dd_e, stored at the slot of the
                          // reverse entry: pg[rev(i,e)] (see the force gather)
   double* Fself;         // [n*3]  sum_e dE_i/dd_e
@@ -144,6 +145,9 @@ struct DescParams {
   int* flags;
 };
 // prec: 0 = double arithmetic, 1 = float arithmetic
+// true if `grid` blocks of the kernel are all resident at once on the current
+// device (occupancy from the runtime, cached per kernel, block size and LDS)
+bool fits_one_round(const void* kernel, int threads, size_t lds, int grid);
 bool desc_supported(int nr, int na);
 int desc_supported_list(int* orders, int max_pairs);
 void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s);

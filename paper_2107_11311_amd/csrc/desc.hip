@@ -11,6 +11,10 @@
 // with cross-lane shuffles.  The force pass takes a wavefront per atom (see
 // k_desc_bwd).  R is the arithmetic type (double, or float with the
 // displacement taken in double).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "desc_dev.h"
 
 namespace aenet {
@@ -20,7 +24,7 @@ namespace {
 template <typename R, int NR, int NA, int LPA>
 __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __builtin_amdgcn_s_setprio(3);
+  if (p.prio) __builtin_amdgcn_s_setprio(3);
   const int apb = blockDim.x / LPA;
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
   const int i = blockIdx.x * apb + g;
@@ -528,10 +532,13 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
   const size_t lds = (size_t)apb * per_atom;
   const int blocks = (p.n + apb - 1) / apb;
   const dim3 grid(blocks), block(apb * LPA);
-  if (kind == FWD)
-    hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA>), grid, block, lds, s, p);
-  else
+  if (kind == FWD) {
+    DescParams q = p;
+    q.prio = fits_one_round(reinterpret_cast<const void*>(&k_desc_fwd<R, NR, NA, LPA>), apb * LPA, lds, blocks);
+    hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA>), grid, block, lds, s, q);
+  } else {
     hipLaunchKernelGGL((k_desc_jvp<R, NR, NA, LPA>), grid, block, lds, s, p);
+  }
 }
 
 // the force pass: one wavefront per atom, up to four atoms per block
@@ -582,6 +589,30 @@ void launch_any(int kind, int prec, int nr, int na, const DescParams& p, hipStre
 }
 
 }  // namespace
+
+bool fits_one_round(const void* kernel, int threads, size_t lds, int grid) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int, size_t>, int> cache;  // -> resident blocks per device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  const auto key = std::make_tuple(dev, kernel, threads, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int per_cu = 0, cus = 0;
+    // (a failed query only switches the priorities off; its error is cleared)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess) {
+      per_cu = 0;
+      (void)hipGetLastError();
+    }
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      cus = 0;
+      (void)hipGetLastError();
+    }
+    it = cache.emplace(key, per_cu * cus).first;
+  }
+  return grid <= it->second;
+}
 
 bool desc_supported(int nr, int na) {
 #define AENET_CHECK(A, B) \

@@ -328,11 +328,13 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
 
   if (active && l == 0) p.nrad[i] = n_keep | (n_marg << 16);
 
+  // With p.prio (set where every block of the grid is resident at once) the
   // wave priority falls phase by phase (radial 3, angular 2, reduction 1,
   // network 0): of the blocks sharing a CU, which all start together, the
   // ones behind get the issue slots, so they finish close together instead
-  // of the last one running alone at the end
-  __builtin_amdgcn_s_setprio(2);
+  // of the last one running alone at the end.  (Where blocks arrive over
+  // several rounds, new blocks would starve the old ones.)
+  if (p.prio) __builtin_amdgcn_s_setprio(2);
 
   // compact the angular entries into LDS
   int nv = 0;
@@ -408,7 +410,7 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
     }
   }
 
-  __builtin_amdgcn_s_setprio(1);
+  if (p.prio) __builtin_amdgcn_s_setprio(1);
   // G layout [rad_typ | ang_typ | rad_wt | ang_wt] (ordered angular pairs =
   // 2 x unordered).  Each half (typed, weighted) is packed into a vector of
   // NV = 2^k >= T2 partial sums and reduce-scattered over the group on its

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256, 3) void k_fwd_mlp(DescParams dp, MlpParams mp,
   T* X0 = reinterpret_cast<T*>(smem + x0_off);
   T* xrow = X0 + g * (w0 + 1);
   R* G = dp.G ? reinterpret_cast<R*>(dp.G) + (size_t)(active ? i : 0) * dp.ldG : nullptr;
-  __builtin_amdgcn_s_setprio(3);
+  if (dp.prio) __builtin_amdgcn_s_setprio(3);
   desc_fwd_group<R, NR, NA, LPA>(dp, i, active, g, l, smem, [&](int c, R v) {
     xrow[c] = (T(v) - sh[c]) * sc[c];
     if (G) G[c] = v;
@@ -57,14 +57,17 @@ __global__ __launch_bounds__(256, 3) void k_fwd_mlp(DescParams dp, MlpParams mp,
   mlp_prefetch<PREC>(mp, net, 0, threadIdx.x >> 6, threadIdx.x & 63, b0);
   __syncthreads();
   // the network's work buffers reuse the descriptor pass's LDS
-  __builtin_amdgcn_s_setprio(0);
+  if (dp.prio) __builtin_amdgcn_s_setprio(0);
   mlp_tile<PREC>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x, b0);
 }
 
 template <int PREC, int NR, int NA>
 void launch_fused(const DescParams& dp, const MlpParams& mp, int n_tiles, size_t lds, int x0_off,
                   hipStream_t s) {
-  hipLaunchKernelGGL((k_fwd_mlp<PREC, NR, NA>), dim3(n_tiles), dim3(16 * kFusedLanes), lds, s, dp, mp,
+  DescParams q = dp;
+  q.prio = fits_one_round(reinterpret_cast<const void*>(&k_fwd_mlp<PREC, NR, NA>), 16 * kFusedLanes, lds,
+                          n_tiles);
+  hipLaunchKernelGGL((k_fwd_mlp<PREC, NR, NA>), dim3(n_tiles), dim3(16 * kFusedLanes), lds, s, q, mp,
                      x0_off);
 }
 
