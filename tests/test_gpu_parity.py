@@ -276,6 +276,57 @@ def test_md_long_with_rebuilds(A, orc):
     assert de < 1e-10, de
 
 
+def test_md_cell_bins_matches_oracle(A, orc):
+    """MD on a box of 4 x 4 x 4 list cells (the per-cell row kernel with the
+    integrator's cell bins, every stencil cell distinct) and a small skin, so
+    the list is rebuilt often: the trajectory stays on the oracle's."""
+    s = I.water_box(256, 71)
+    m = small_model(nr=5, na=3, rr=4.5, ra=3.5)
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 8)
+    ctx = A.Context(m, "fp64", skin=0.15)
+    ctx.set_rebuild_every(12)
+    p1, v1, ep, ek, F = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 40)
+    st = ctx.stats()
+    p0, v0, ep0, ek0, F0 = orc.md_vv(m, s.pos, v, s.species, m.masses, s.box, s.pbc, 5e-4, 40)
+    dp = float(np.abs((p1 - p0 + s.box / 2) % s.box - s.box / 2).max())
+    dv = float(np.abs(v1 - v0).max() / np.abs(v0).max())
+    de = abs(ep + ek - ep0 - ek0) / abs(ep0 + ek0)
+    print(f"md cell bins: atoms={s.pos.shape[0]} box={s.box[0]:.2f} rebuilds={st['n_rebuilds']} "
+          f"dpos={dp:.3e} rel dvel={dv:.3e} rel dE={de:.3e}")
+    assert s.box[0] / (4.5 + 0.15) >= 4  # at least 4 cells per axis
+    assert st["n_rebuilds"] > 40 // 12
+    assert dp < 1e-9, dp
+    assert dv < 1e-9, dv
+    assert de < 1e-10, de
+
+
+def test_capacity_retry_md_cell_bins(A):
+    """A capacity retry inside an MD chunk on the per-cell path (cell bins
+    filled by the integrator): the redone chunk ends where the run with
+    estimated rows ends."""
+    s = I.water_box(256, 71)
+    m = small_model(nr=5, na=3, rr=4.5, ra=3.5)
+    v = I.maxwell_boltzmann(m.masses[s.species], 600.0, 13)
+    probe = A.Context(m, "fp64", skin=0.3)
+    probe.energy_forces(s.pos, s.species, s.box, s.pbc)
+    st0 = probe.stats()
+    ref = A.Context(m, "fp64", skin=0.3)
+    ref.set_rebuild_every(10)
+    p0, v0, ep0, ek0, _ = ref.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 40)
+    ctx = A.Context(m, "fp64", skin=0.3)
+    ctx.set_rebuild_every(10)
+    ctx.set_capacity(st0["max_neighbors"], st0["max_angular"])
+    p1, v1, ep1, ek1, _ = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 40)
+    st = ctx.stats()
+    dp = float(np.abs((p1 - p0 + s.box / 2) % s.box - s.box / 2).max())
+    dv = float(np.abs(v1 - v0).max() / np.abs(v0).max())
+    print(f"capacity retry md (cell bins): retries={st['n_capacity_retries']} rows {st0['max_neighbors']}->"
+          f"{st['row_capacity']} ang {st0['max_angular']}->{st['ang_capacity']} dpos={dp:.3e} dvel={dv:.3e}")
+    assert st["n_capacity_retries"] >= 1
+    assert dp < 1e-9 and dv < 1e-9
+    assert abs(ep1 + ek1 - ep0 - ek0) < 1e-10 * abs(ep0 + ek0)
+
+
 def test_md_resume_is_bitwise(A):
     """100 steps == 50 steps + (positions, velocities) handed back + 50 steps."""
     m = I.load_model("water64")
