@@ -371,7 +371,9 @@ __global__ __launch_bounds__(256) void k_reverse(NbrParams p) {
 // on its first use of the entry and stores the result back.
 constexpr int kMaskWords = kCellAtomsMax / 32;
 
-__global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
+// (at most 80 scalar registers: measured, a version at 84-86 no longer fit two
+// 1024-thread blocks on a CU and a third of the blocks started a round late)
+__global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))) void k_rows_cell(NbrParams p) {
   if (p.binned) {
     // every step: clear this cell's count in the half the integrator fills next
     if (threadIdx.x == 0) p.bin_count[(size_t)(1 - p.bin_sel) * p.n_cells + blockIdx.x] = 0;
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
   }
   extern __shared__ __align__(16) unsigned char smem[];
   const int tp = p.tp;
-  double* s_pos = reinterpret_cast<double*>(smem);                          // [tp][3]
+  double* s_pos = reinterpret_cast<double*>(smem);                          // [3][tp] (x, y, z planes: unit-stride lanes)
   uint32_t* s_key = reinterpret_cast<uint32_t*>(s_pos + 3 * (size_t)tp);      // [tp] atom | stencil cell << kImgBits
   uint32_t* s_mask = s_key + tp;                                              // [tp][2][kMaskWords]
   uint32_t* s_rad = s_mask + (size_t)tp * 2 * kMaskWords;                     // [waves][cap]
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
         // skin-test reference (other blocks may read either value: wrapping
         // is idempotent)
         if (p.binned && p.pbc[a]) x[a] = wrap_coord(x[a], b.L[a]);
-        s_pos[3 * t + a] = x[a];
+        s_pos[(size_t)a * tp + t] = x[a];
       }
       if (p.binned && k == 13) {
         for (int a = 0; a < 3; ++a) {
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
   uint32_t* rad_t = s_rad + (size_t)wv * p.cap;
   for (int ai = wv; ai < ncen; ai += kRowWaves) {
     const int i = (int)(s_key[c0 + ai] & kAtomMask);
-    const double xi0 = s_pos[3 * (c0 + ai)], xi1 = s_pos[3 * (c0 + ai) + 1], xi2 = s_pos[3 * (c0 + ai) + 2];
+    const double xi0 = s_pos[c0 + ai], xi1 = s_pos[tp + c0 + ai], xi2 = s_pos[2 * tp + c0 + ai];
     uint32_t* row = p.nbr + (size_t)i * p.cap;
     int* slot = p.rev + (size_t)i * p.cap;  // (candidate slot, stencil cell) of each entry, then (rank, cell)
     int cnt_a = 0, cnt_r = 0;
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_rows_cell(NbrParams p) {
       const uint32_t key = s_key[tt];
       k_cell = (int)(key >> kImgBits);
       const int q = (int)(key & kAtomMask);
-      const double qx = s_pos[3 * tt], qy = s_pos[3 * tt + 1], qz = s_pos[3 * tt + 2];
+      const double qx = s_pos[tt], qy = s_pos[tp + tt], qz = s_pos[2 * tp + tt];
       const double sx = s_shift[k_cell][0], sy = s_shift[k_cell][1], sz = s_shift[k_cell][2];
       // displacement from the lower-index atom (image shifts counted from
       // it), so that an entry and its reverse agree bit for bit on r^2
