@@ -90,7 +90,14 @@ __device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const doub
 // the force pass stored the gradient of every contributing entry at the slot
 // of its reverse entry, so this gather reads within one row: the slots of q's
 // own contributing entries, listed by the forward pass.
+//
+// The kernel is a chain of dependent memory accesses, so everything it reads
+// is requested before anything is written: the atom's state (lanes 0..2 of
+// its group hold component 0..2), the first kPre listed slots of every lane
+// (in bounds whatever the count, a row has cap slots) and the box.  The
+// count then only masks.
 constexpr int kGatherLanes = 16;  // lanes per atom in the force gather
+constexpr int kGatherPre = 8;     // listed slots per lane requested up front
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int* nrad, const uint16_t* ridx,
@@ -101,12 +108,47 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
   constexpr int LPA = kGatherLanes;
   const int g = threadIdx.x / LPA, l = threadIdx.x % LPA;
   const int i = blockIdx.x * (blockDim.x / LPA) + g;
+  const bool act = i < n;
+  const int ic = act ? i : 0;
+  const bool drift = next.pos != nullptr && vel != nullptr;
+  const bool binning = drift && next.bin_count != nullptr;
+
+  // ---- loads (addresses chosen without branches: a missing array reads a
+  // harmless stand-in whose value is not used)
+  const int a = l < 3 ? l : 0;
+  const size_t k3 = 3 * (size_t)ic + a;
+  const double* vel_in = vel ? vel : Fself;
+  const double* pos_in = drift ? next.pos : Fself;
+  const double* ref_in = drift ? next.pos_ref : Fself;
+  const int* flag_in = drift ? next.rebuild_flag : nrad;
+  const int* sp_in = vel ? species + ic : nrad + ic;
+  const double fself = Fself[k3];
+  const double v_old = vel_in[k3];
+  const double x_old = pos_in[k3];
+  const double x_ref = ref_in[k3];
+  const int flag0 = *flag_in;
+  const int sv = *sp_in;
+  const int code = nrad[ic];
+  const uint16_t* ri = ridx + (size_t)ic * cap;
+  int ep[kGatherPre];
+#pragma unroll
+  for (int m = 0; m < kGatherPre; ++m) ep[m] = (int)ri[min(l + m * LPA, max(cap - 1, 0))];
+  BoxInfo bx{};
+  if (binning) bx = *next.box;
+  const double im = *(vel ? inv_mass_k + sv : Fself + k3);
+  const int nk = act ? (code & 0xffff) : 0;
+  const R* row = pg + (size_t)ic * cap * 3;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  const int nk = i < n ? (nrad[i] & 0xffff) : 0;
-  const R* row = pg + (size_t)(i < n ? i : 0) * cap * 3;
-  const uint16_t* ri = ridx + (size_t)(i < n ? i : 0) * cap;
-#pragma unroll 4
-  for (int k = l; k < nk; k += LPA) {
+#pragma unroll
+  for (int m = 0; m < kGatherPre; ++m) {
+    const bool use = l + m * LPA < nk;
+    const int e = use ? ep[m] : 0;
+    const R px = row[3 * e], py = row[3 * e + 1], pz = row[3 * e + 2];
+    sx += use ? (double)px : 0.0;
+    sy += use ? (double)py : 0.0;
+    sz += use ? (double)pz : 0.0;
+  }
+  for (int k = l + kGatherPre * LPA; k < nk; k += LPA) {
     const int e = ri[k];
     sx += (double)row[3 * e];
     sy += (double)row[3 * e + 1];
@@ -118,47 +160,51 @@ __global__ __launch_bounds__(256) void k_force_gather(int n, int cap, const int*
     sy += __shfl_xor(sy, o, LPA);
     sz += __shfl_xor(sz, o, LPA);
   }
+
+  // ---- stores
   if (next.pos && blockIdx.x == 0 && threadIdx.x == 0) {
     *next.clear_flag = 0;
     if (next.force_rebuild) *next.rebuild_flag = 1;
   }
-  double xn[3] = {0.0, 0.0, 0.0};
-  if (i < n && l == 0) {
-    const double f[3] = {Fself[3 * (size_t)i] - sx, Fself[3 * (size_t)i + 1] - sy,
-                         Fself[3 * (size_t)i + 2] - sz};
-    double d2 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      const size_t k = 3 * (size_t)i + a;
-      F[k] = f[a];
-      if (vel) {
-        const double c = half_dt * inv_mass_k[species[i]];
-        double v = vel[k] + c * f[a];        // closing half kick of this step
-        if (next.pos) {
-          v = v + c * f[a];                  // opening half kick of the next step
-          const double x = next.pos[k] + next.dt * v;
-          next.pos[k] = x;
-          xn[a] = x;
-          const double dd = x - next.pos_ref[k];
-          d2 += dd * dd;
-        }
-        vel[k] = v;
+  const double f = fself - (a == 0 ? sx : a == 1 ? sy : sz);
+  double xn = 0.0, dd = 0.0;
+  if (act && l < 3) {
+    F[k3] = f;
+    if (vel) {
+      const double c = half_dt * im;
+      double v = v_old + c * f;    // closing half kick of this step
+      if (drift) {
+        v = v + c * f;             // opening half kick of the next step
+        xn = x_old + next.dt * v;
+        next.pos[k3] = xn;
+        dd = xn - x_ref;
       }
+      vel[k3] = v;
     }
-    if (next.pos && !(d2 <= next.half_skin2) && *next.rebuild_flag == 0) *next.rebuild_flag = 1;
   }
-  if (next.pos && vel && next.bin_count) {
-    // the block's 16 atoms are binned by its first wavefront, so atoms of one
-    // cell share one atomic across the block
-    __shared__ int s_cell[256 / LPA], s_atom[256 / LPA];
-    if (l == 0) {
-      s_cell[g] = i < n ? cell_of(*next.box, next.pbc, xn) : -1;
-      s_atom[g] = i;
+  if (drift) {
+    const double dd1 = __shfl(dd, 1, LPA), dd2 = __shfl(dd, 2, LPA);
+    const double xn1 = __shfl(xn, 1, LPA), xn2 = __shfl(xn, 2, LPA);
+    if (act && l == 0) {
+      double d2 = dd * dd;
+      d2 += dd1 * dd1;
+      d2 += dd2 * dd2;
+      if (!(d2 <= next.half_skin2) && flag0 == 0) *next.rebuild_flag = 1;
     }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int t = threadIdx.x;
-      const bool mine = t < 256 / LPA && s_cell[t] >= 0;
-      bin_wave_cells(next, mine, mine ? s_atom[t] : 0, mine ? s_cell[t] : -1);
+    if (binning) {
+      // the block's 16 atoms are binned by its first wavefront, so atoms of
+      // one cell share one atomic across the block
+      __shared__ int s_cell[256 / LPA];
+      if (l == 0) {
+        const double x3[3] = {xn, xn1, xn2};
+        s_cell[g] = act ? cell_of(bx, next.pbc, x3) : -1;
+      }
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        const bool mine = t < 256 / LPA && s_cell[t] >= 0;
+        bin_wave_cells(next, mine, blockIdx.x * (blockDim.x / LPA) + t, mine ? s_cell[t] : -1);
+      }
     }
   }
 }
