@@ -46,13 +46,13 @@ __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
 template <typename R, int NR, int NA>
 __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int apb = blockDim.x >> 6;
-  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // one wavefront per block and atom; the launch covers exactly the n atoms,
+  // so every load below is unconditional (loads under a branch are issued
+  // one after another, each waiting for the last)
+  const int i = blockIdx.x;
   const int l = threadIdx.x & 63;
-  const int i = blockIdx.x * apb + g;
-  const bool active = i < p.n;
   const int ca = p.cap_ang;
-  R* ux = reinterpret_cast<R*>(smem) + (size_t)g * ca * 10;
+  R* ux = reinterpret_cast<R*>(smem);
   R* uy = ux + ca;
   R* uz = uy + ca;
   R* fs = uz + ca;
@@ -62,41 +62,35 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   R* gx = ri + ca;
   R* gy = gx + ca;
   R* gz = gy + ca;
-  int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)apb * ca * 10) + (size_t)g * ca;
+  int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)ca * 10);
 
-  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
-  const double xi0 = active ? p.pos[3 * (size_t)i] : 0.0;
-  const double xi1 = active ? p.pos[3 * (size_t)i + 1] : 0.0;
-  const double xi2 = active ? p.pos[3 * (size_t)i + 2] : 0.0;
-  const uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
-  const int nn = active ? p.nnb[i] : 0;
-  const int na = active ? p.nang[i] : 0;
+  const BoxInfo b = p.boxes[p.seg[i]];
+  const double xi0 = p.pos[3 * (size_t)i];
+  const double xi1 = p.pos[3 * (size_t)i + 1];
+  const double xi2 = p.pos[3 * (size_t)i + 2];
+  const uint32_t* row = p.nbr + (size_t)i * p.cap;
+  const int na = p.nang[i];
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
   const R inv_rr2 = R(2.0 / p.rr), pi_2rr = R(0.5 * kPi / p.rr), pi_2ra = R(0.5 * kPi / p.ra);
-  const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)(active ? i : 0) * p.ldG;
+  const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)i * p.ldG;
   constexpr int T1 = NR + 1, T2 = NR + NA + 2;
+  // the weighted channel's coefficients (read at the typed ones and unused
+  // when the descriptor has no weighted channel)
+  const R* gW = gG + (p.weighted ? T2 : 0);
 
-  // compact the entries within R_a
+  // compact the entries within R_a (lanes past the end reread the last one)
   int nv = 0;
   for (int base = 0; base < na; base += 64) {
     const int e = base + l;
-    bool valid = false;
-    R vx = 0, vy = 0, vz = 0, vf = 0, vfp = 0, vw = 0, vri = 0;
-    if (e < na) {
-      double d0, d1, d2;
-      const int q = entry_disp(p, b, xi0, xi1, xi2, row[e], d0, d1, d2);
-      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      if (r2 < ra2) {
-        valid = true;
-        R r;
-        len_inv<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2), &r, &vri);
-        vx = R(d0) * vri;
-        vy = R(d1) * vri;
-        vz = R(d2) * vri;
-        cutoff_d<R>(r, pi_2ra, &vf, &vfp);
-        vw = R(p.tw[p.species[q]]);
-      }
-    }
+    const NbrLoad nl = load_nbr(p, row[min(e, na - 1)]);
+    double d0, d1, d2;
+    nbr_disp(nl, b, xi0, xi1, xi2, d0, d1, d2);
+    const bool valid = e < na && d0 * d0 + d1 * d1 + d2 * d2 < ra2;
+    R r, vri, vf, vfp;
+    len_inv<R>(R(d0) * R(d0) + R(d1) * R(d1) + R(d2) * R(d2), &r, &vri);
+    const R vx = R(d0) * vri, vy = R(d1) * vri, vz = R(d2) * vri;
+    cutoff_d<R>(r, pi_2ra, &vf, &vfp);
+    const R vw = R(nl.w);
     const uint64_t m = __ballot(valid);
     const int at_ = nv + __popcll(m & ((1ull << l) - 1ull));
     if (valid) {
@@ -119,8 +113,9 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
     R ga[NA + 1], gw[NA + 1];
 #pragma unroll
     for (int a = 0; a <= NA; ++a) {
-      ga[a] = active ? gG[T1 + a] : R(0);
-      gw[a] = (active && p.weighted) ? gG[T2 + T1 + a] : R(0);
+      const R v = gW[T1 + a];
+      ga[a] = gG[T1 + a];
+      gw[a] = p.weighted ? v : R(0);
     }
     if (nv <= 64) {
       // Unordered pairs by rotation: the lane owning entry e takes at step t
@@ -226,11 +221,12 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   R grt[NR + 1], grw[NR + 1];
 #pragma unroll
   for (int a = 0; a <= NR; ++a) {
-    grt[a] = active ? gG[a] : R(0);
-    grw[a] = (active && p.weighted) ? gG[T2 + a] : R(0);
+    const R v = gW[a];
+    grt[a] = gG[a];
+    grw[a] = p.weighted ? v : R(0);
   }
   R* pg = reinterpret_cast<R*>(p.pg);
-  int* rev = p.rev + (size_t)(active ? i : 0) * p.cap;
+  int* rev = p.rev + (size_t)i * p.cap;
   const int n_slots = p.n * p.cap;
   double sx = 0.0, sy = 0.0, sz = 0.0;
   // The reverse slot of entry e: on first use after a per-cell row build rev
@@ -257,11 +253,11 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   // the end repeats the last entry (an empty list reads the atom itself,
   // always in bounds).  Their pg is stored at the reverse entry's slot, where
   // the force gather of the neighbour reads it.
-  const uint16_t* ridx = p.ridx + (size_t)(active ? i : 0) * p.cap;
-  const int nr_code = active ? p.nrad[i] : 0;
+  const uint16_t* ridx = p.ridx + (size_t)i * p.cap;
+  const int nr_code = p.nrad[i];
   const int nkeep = nr_code & 0xffff;
   const int nk = nkeep + (nr_code >> 16);
-  const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
+  const uint32_t self_word = (uint32_t)i | (13u << kImgBits);
   // (three dependent loads per entry: its row position, its row word, the
   // neighbour's position; each is issued one iteration before it is needed)
   auto entry = [&](int k) {
@@ -324,7 +320,7 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   sx = group_sum<64>(sx);
   sy = group_sum<64>(sy);
   sz = group_sum<64>(sz);
-  if (active && l == 0) {
+  if (l == 0) {
     p.Fself[3 * (size_t)i] = sx;
     p.Fself[3 * (size_t)i + 1] = sy;
     p.Fself[3 * (size_t)i + 2] = sz;
