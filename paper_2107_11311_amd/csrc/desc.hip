@@ -250,21 +250,21 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   // The entries the forward pass listed (the contributing ones from the
   // front of ridx, then the margin ones from its back: nk in all), one per
   // lane per iteration with the next one's position loaded ahead; a slot past
-  // the end repeats the last entry (an empty list reads the atom itself,
-  // always in bounds).  Their pg is stored at the reverse entry's slot, where
-  // the force gather of the neighbour reads it.
+  // the end repeats the last entry (an empty list reads row slot 0; the
+  // clamps keep whatever it holds inside the arrays, and it is not used).
+  // Their pg is stored at the reverse entry's slot, where the force gather of
+  // the neighbour reads it.
   const uint16_t* ridx = p.ridx + (size_t)i * p.cap;
   const int nr_code = p.nrad[i];
   const int nkeep = nr_code & 0xffff;
   const int nk = nkeep + (nr_code >> 16);
-  const uint32_t self_word = (uint32_t)i | (13u << kImgBits);
   // (three dependent loads per entry: its row position, its row word, the
   // neighbour's position; each is issued one iteration before it is needed)
   auto entry = [&](int k) {
     const int kk = k < nk ? k : nk - 1;
-    return nk > 0 ? (int)ridx[kk < nkeep ? kk : p.cap - 1 - (kk - nkeep)] : 0;
+    return min((int)ridx[kk < 0 ? 0 : kk < nkeep ? kk : p.cap - 1 - (kk - nkeep)], p.cap - 1);
   };
-  auto word = [&](int e) { return nk > 0 ? row[e] : self_word; };
+  auto word = [&](int e) { return row[e]; };
   int ea = entry(l), eb = entry(l + 64), ec = entry(l + 128);
   NbrLoad nx = load_nbr(p, word(ea));
   uint32_t wb = word(eb);

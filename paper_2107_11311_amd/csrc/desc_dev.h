@@ -184,7 +184,9 @@ struct NbrLoad {
 
 __device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t word) {
   NbrLoad n;
-  const int q = (int)(word & kAtomMask);
+  // clamped, so that a slot read past the end of a row (whose value is not
+  // used) stays inside the arrays
+  const int q = min((int)(word & kAtomMask), p.n - 1);
   n.code = (int)(word >> kImgBits);
   n.x = p.pos[3 * (size_t)q];
   n.y = p.pos[3 * (size_t)q + 1];
@@ -247,13 +249,17 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
 #pragma unroll
   for (int a = 0; a <= NA; ++a) at[a] = aw[a] = R(0);
 
-  const BoxInfo b = p.boxes[active ? p.seg[i] : 0];
-  const double xi0 = active ? p.pos[3 * (size_t)i] : 0.0;
-  const double xi1 = active ? p.pos[3 * (size_t)i + 1] : 0.0;
-  const double xi2 = active ? p.pos[3 * (size_t)i + 2] : 0.0;
-  const uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
-  const int nn = active ? p.nnb[i] : 0;
-  const int na = active ? p.nang[i] : 0;
+  // an inactive group reads atom 0 and uses none of it (unconditional loads
+  // are issued together; loads under a branch one after another)
+  const int ic = active ? i : 0;
+  const BoxInfo b = p.boxes[p.seg[ic]];
+  const double xi0 = p.pos[3 * (size_t)ic];
+  const double xi1 = p.pos[3 * (size_t)ic + 1];
+  const double xi2 = p.pos[3 * (size_t)ic + 2];
+  const uint32_t* row = p.nbr + (size_t)ic * p.cap;
+  const int nn_ld = p.nnb[ic], na_ld = p.nang[ic];
+  const int nn = active ? nn_ld : 0;
+  const int na = active ? na_ld : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
   const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
   const R two_ra = R(2.0 / p.ra);
@@ -261,15 +267,14 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
   // radial terms, Eq. 3.  Two entries per lane per iteration give two
   // independent recurrence chains; entries beyond R_r (skin) or past the end
   // of the row are computed with weight 0 instead of branching.
-  // slots past the end of the row repeat its last entry (an empty row reads the
-  // atom itself, always in bounds) and are given weight 0
-  const uint32_t self_word = (uint32_t)(active ? i : 0) | (13u << kImgBits);
-  auto word = [&](int e) { return nn > 0 ? row[e < nn ? e : nn - 1] : self_word; };
+  // slots past the end of the row repeat its last entry (an empty row reads
+  // slot 0, whatever it holds) and are given weight 0
+  auto word = [&](int e) { return row[e < nn ? e : max(nn - 1, 0)]; };
   NbrLoad na_ = load_nbr(p, word(l)), nb_ = load_nbr(p, word(l + LPA));
   uint32_t wa1 = word(l + 2 * LPA), wb1 = word(l + 3 * LPA);
   // for the force pass and the gather: the contributing entries from the
   // front of ridx, the margin entries from the back (see DescParams)
-  uint16_t* ridx = p.ridx + (size_t)(active ? i : 0) * p.cap;
+  uint16_t* ridx = p.ridx + (size_t)ic * p.cap;
   const double rr2m = rr2 * (1.0 + 1e-9);
   int n_keep = 0, n_marg = 0;
   for (int e = l; e < nn; e += 2 * LPA) {
