@@ -117,7 +117,7 @@ struct DescParams {
   int cap, cap_ang;
   int ang_hint;          // expected largest angular shell within R_a (tuning only)
   double rr, ra;
-  double tw[kMaxSpecies];
+  const double* wq;      // [n] type weight of each atom's species (Sec. II B)
   int weighted;          // n_species > 1
   int ldG;               // row stride of G / dE/dG
   void* G;               // [n x ldG] (float or double)

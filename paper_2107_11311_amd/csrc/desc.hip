@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
       sincos_cut<R>(r, inv_rr2, &sn, &cs);
       const R fc = R(0.5) * (cs + R(1));
       const R fcp = R(-0.5) * pi_rr * sn;
-      const R w = R(p.tw[p.species[q]]);
+      const R w = R(p.wq[q]);
       R t0 = R(1), t1 = x, u0 = R(1), u1 = R(2) * x;
       rt[0] += fcp * proj;
       rw[0] += w * fcp * proj;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
         sincos_cut<R>(r, two_ra, &sn, &cs);
         vf = R(0.5) * (cs + R(1));
         vfd = R(-0.5) * pi_ra * sn * vpa;
-        vw = R(p.tw[p.species[q]]);
+        vw = R(p.wq[q]);
       }
     }
     const uint64_t m = group_ballot<LPA>(valid);

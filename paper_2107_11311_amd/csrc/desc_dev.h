@@ -191,7 +191,7 @@ __device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t word) {
   n.x = p.pos[3 * (size_t)q];
   n.y = p.pos[3 * (size_t)q + 1];
   n.z = p.pos[3 * (size_t)q + 2];
-  n.w = p.tw[p.species[q]];
+  n.w = p.wq[q];
   return n;
 }
 
@@ -361,7 +361,7 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
         R sn, cs;
         sincos_cut<R>(r, two_ra, &sn, &cs);
         vf = R(0.5) * (cs + R(1));
-        vw = R(p.tw[p.species[q]]);
+        vw = R(p.wq[q]);
       }
     }
     const uint64_t m = group_ballot<LPA>(valid);

@@ -83,7 +83,7 @@ struct aenet_ctx {
   int ang_mean = 0;  // expected mean number of neighbours within R_a (densest structure)
   bool nbr_valid = false;
 
-  DevMem d_perm, d_species, d_seg, d_segoff, d_segcount, d_boxes;
+  DevMem d_perm, d_species, d_wq, d_seg, d_segoff, d_segcount, d_boxes;
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
       d_tmp, d_red, d_scal, d_flags, d_mass, d_invmk;
   DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_segs, d_nnb, d_nang, d_rev;
@@ -329,21 +329,25 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
       return zkey[a] < zkey[b];
     });
     std::vector<int> sp_int(n), seg_int(n);
+    std::vector<double> wq(n);
     for (int64_t p = 0; p < n; ++p) {
       sp_int[p] = species[c->perm[p]];
       seg_int[p] = seg_orig[c->perm[p]];
+      wq[p] = c->tw[sp_int[p]];
     }
     std::vector<int64_t> segcount(n_struct);
     for (int s = 0; s < n_struct; ++s) segcount[s] = offsets[s + 1] - offsets[s];
     const size_t nb = (size_t)std::max<int64_t>(n, 1);
     TRY(ensure(c, c->d_perm, nb * 4));
     TRY(ensure(c, c->d_species, nb * 4));
+    TRY(ensure(c, c->d_wq, nb * 8));
     TRY(ensure(c, c->d_seg, nb * 4));
     TRY(ensure(c, c->d_segoff, (n_struct + 1) * 8));
     TRY(ensure(c, c->d_segcount, n_struct * 8));
     if (n > 0) {
       HIP_TRY(c, hipMemcpy(c->d_perm.p, c->perm.data(), n * 4, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(c->d_species.p, sp_int.data(), n * 4, hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(c->d_wq.p, wq.data(), n * 8, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(c->d_seg.p, seg_int.data(), n * 4, hipMemcpyHostToDevice));
     }
     HIP_TRY(c, hipMemcpy(c->d_segoff.p, offsets, (n_struct + 1) * 8, hipMemcpyHostToDevice));
@@ -489,7 +493,7 @@ DescParams desc_params(aenet_ctx* c) {
   p.ang_hint = c->ang_mean;
   p.rr = c->rr;
   p.ra = c->ra;
-  for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];
+  p.wq = c->d_wq.as<double>();
   p.weighted = c->S > 1;
   p.ldG = c->ldG;
   p.G = c->d_G.p;
