@@ -118,6 +118,8 @@ struct DescParams {
   int ang_hint;          // expected largest angular shell within R_a (tuning only)
   double rr, ra;
   const double* wq;      // [n] type weight of each atom's species (Sec. II B)
+  double tw[kMaxSpecies];  // type weight per species
+  int n_species;
   int weighted;          // n_species > 1
   int ldG;               // row stride of G / dE/dG
   void* G;               // [n x ldG] (float or double)

@@ -34,6 +34,13 @@ __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
 }
 
 // ------------------------------------------------------------------ backward
+// LDS of the force pass (elements of R): ten arrays of cap_ang entries, the
+// compaction index (cap_ang ints), then the per-species series coefficients
+template <typename R>
+__host__ __device__ constexpr size_t bwd_coef_offset(int ca) {
+  return (size_t)ca * 10 + ((size_t)ca * sizeof(int) + sizeof(R) - 1) / sizeof(R);
+}
+
 // dE_i / d d_e for every entry e of atom i, stored at the slot of the reverse
 // entry (pg[rev(i, e)]) for the force gather; Fself[i] = sum_e dE_i / d d_e.
 // One wavefront per atom (the atom index is uniform over the wave):
@@ -63,6 +70,8 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   R* gy = gx + ca;
   R* gz = gy + ca;
   int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)ca * 10);
+  // radial series coefficients of each species s (NR + 1 per species)
+  R* s_c = reinterpret_cast<R*>(smem) + bwd_coef_offset<R>(ca);
 
   const BoxInfo b = p.boxes[p.seg[i]];
   const double xi0 = p.pos[3 * (size_t)i];
@@ -217,14 +226,17 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   }
   __syncthreads();
 
-  // radial terms, plus the angular part of each entry, written per entry
-  R grt[NR + 1], grw[NR + 1];
-#pragma unroll
-  for (int a = 0; a <= NR; ++a) {
-    const R v = gW[a];
-    grt[a] = gG[a];
-    grw[a] = p.weighted ? v : R(0);
+  // radial terms, plus the angular part of each entry, written per entry.
+  // The coefficients of the series are combined per species into
+  // c_a(s) = dE/dG_t,a + tw_s dE/dG_w,a in LDS (read by every lane for its
+  // neighbour's species; kept in registers they would crowd out the scalar
+  // registers the loop needs).
+  for (int t = l; t < p.n_species * (NR + 1); t += 64) {
+    const int sp = t / (NR + 1), a = t - sp * (NR + 1);
+    const R w = p.weighted ? R(p.tw[sp]) : R(0);
+    s_c[t] = gG[a] + w * gW[a];
   }
+  __syncthreads();
   R* pg = reinterpret_cast<R*>(p.pg);
   int* rev = p.rev + (size_t)i * p.cap;
   const int n_slots = p.n * p.cap;
@@ -279,7 +291,7 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
     const bool he = k < nk;
     double d0, d1, d2;
     nbr_disp(nx, b, xi0, xi1, xi2, d0, d1, d2);
-    const R wq = R(nx.w);
+    const R* cq = s_c + nx.sp * (NR + 1);
     nx = n1;
     // angular entries beyond R_r (R_a + skin > R_r) have no radial term
     const R mq = (he && d0 * d0 + d1 * d1 + d2 * d2 < rr2) ? R(1) : R(0);
@@ -289,9 +301,9 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
     const R x = r * inv_rr2 - R(1);
     R fc, fcp;
     cutoff_d<R>(r, pi_2rr, &fc, &fcp);
-    // dE/dr = S'(x) (2/R_r) f_c + S(x) f_c' with S = sum_a (grt_a + w grw_a) T_a
+    // dE/dr = S'(x) (2/R_r) f_c + S(x) f_c' with S = sum_a c_a(s) T_a
     R S, dS;
-    cheb_series_d<R, NR>(grt, grw, wq, x, &S, &dS);
+    cheb_series_tab<R, NR>(cq, x, &S, &dS);
     const R sc = mq * (dS * inv_rr2 * fc + S * fcp) * ir;
     R px = sc * dx, py = sc * dy, pz = sc * dz;
     if (he && e < na) {
@@ -541,7 +553,7 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
 // schedule with the finest grain: measured ~2 % faster than four per block)
 template <typename R, int NR, int NA>
 void launch_bwd(const DescParams& p, hipStream_t s) {
-  const size_t per_atom = (size_t)p.cap_ang * (lds_words(BWD) * sizeof(R) + sizeof(int));
+  const size_t per_atom = (bwd_coef_offset<R>(p.cap_ang) + (size_t)p.n_species * (NR + 1)) * sizeof(R);
   hipLaunchKernelGGL((k_desc_bwd<R, NR, NA>), dim3(p.n), dim3(64), per_atom, s, p);
 }
 

@@ -178,7 +178,7 @@ __device__ inline int entry_disp(const DescParams& p, const BoxInfo& b, double x
 // iteration ahead of its use so the gather latency hides behind the
 // arithmetic of the current iteration).
 struct NbrLoad {
-  int code;
+  int code, sp;       // image code; species of the neighbour atom
   double x, y, z, w;  // position and species weight of the neighbour atom
 };
 
@@ -192,6 +192,7 @@ __device__ inline NbrLoad load_nbr(const DescParams& p, uint32_t word) {
   n.y = p.pos[3 * (size_t)q + 1];
   n.z = p.pos[3 * (size_t)q + 2];
   n.w = p.wq[q];
+  n.sp = p.species[q];
   return n;
 }
 
@@ -212,10 +213,17 @@ __device__ inline void nbr_disp(const NbrLoad& n, const BoxInfo& b, double xi0, 
 template <typename R, int N>
 __device__ inline void cheb_series_d(const R (&g)[N + 1], const R (&h)[N + 1], R w, R x, R* S,
                                      R* dS) {
+  static_assert(N >= 2, "series of order >= 2");
   const R x2 = x + x;
-  R b1 = R(0), b2 = R(0), d1 = R(0), d2 = R(0);
+  // the steps a = N and N - 1 written out: b_N = c_N, b'_N = 0,
+  // b_{N-1} = 2x c_N + c_{N-1}, b'_{N-1} = 2 c_N (no terms with the zero
+  // starting values left for the hardware to multiply)
+  R b2 = w * h[N] + g[N];
+  R b1 = x2 * b2 + (w * h[N - 1] + g[N - 1]);
+  R d2 = R(0);
+  R d1 = R(2) * b2;
 #pragma unroll
-  for (int a = N; a >= 1; --a) {
+  for (int a = N - 2; a >= 1; --a) {
     // (w h_a - b2) + g_a: each operation reads at most one wave-uniform
     // coefficient, so none has to be copied out of the scalar registers
     const R bk = x2 * b1 + ((w * h[a] - b2) + g[a]);
@@ -226,6 +234,29 @@ __device__ inline void cheb_series_d(const R (&g)[N + 1], const R (&h)[N + 1], R
     d1 = dk;
   }
   *S = x * b1 + ((g[0] + w * h[0]) - b2);
+  *dS = x * d1 + (b1 - d2);
+}
+
+// The same with the coefficients c_0..c_N read from c (LDS): four operations
+// per order.
+template <typename R, int N>
+__device__ inline void cheb_series_tab(const R* c, R x, R* S, R* dS) {
+  static_assert(N >= 2, "series of order >= 2");
+  const R x2 = x + x;
+  R b2 = c[N];
+  R b1 = x2 * b2 + c[N - 1];
+  R d2 = R(0);
+  R d1 = R(2) * b2;
+#pragma unroll
+  for (int a = N - 2; a >= 1; --a) {
+    const R bk = x2 * b1 + (c[a] - b2);
+    const R dk = x2 * d1 + (R(2) * b1 - d2);
+    b2 = b1;
+    b1 = bk;
+    d2 = d1;
+    d1 = dk;
+  }
+  *S = x * b1 + (c[0] - b2);
   *dS = x * d1 + (b1 - d2);
 }
 

@@ -494,6 +494,8 @@ DescParams desc_params(aenet_ctx* c) {
   p.rr = c->rr;
   p.ra = c->ra;
   p.wq = c->d_wq.as<double>();
+  for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];
+  p.n_species = c->S;
   p.weighted = c->S > 1;
   p.ldG = c->ldG;
   p.G = c->d_G.p;
