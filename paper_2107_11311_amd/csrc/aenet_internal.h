@@ -10,6 +10,7 @@
 namespace aenet {
 
 constexpr int kMaxSpecies = 8;
+constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxLayers = 4;  // weight layers
 constexpr int kMaxWidth = 64;
 constexpr int kPad = 32;       // every network width is padded to a multiple of this
@@ -117,6 +118,8 @@ struct DescParams {
   int cap, cap_ang;
   int ang_hint;          // expected largest angular shell within R_a (tuning only)
   double rr, ra;
+  // 2/R, pi/R and pi/(2R) of both cutoffs (computed once on the host)
+  double two_rr, two_ra, pi_rr, pi_ra, pi_2rr, pi_2ra;
   const double* wq;      // [n] type weight of each atom's species (Sec. II B)
   double tw[kMaxSpecies];  // type weight per species
   int n_species;

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   const uint32_t* row = p.nbr + (size_t)i * p.cap;
   const int na = p.nang[i];
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
-  const R inv_rr2 = R(2.0 / p.rr), pi_2rr = R(0.5 * kPi / p.rr), pi_2ra = R(0.5 * kPi / p.ra);
+  const R inv_rr2 = R(p.two_rr), pi_2rr = R(p.pi_2rr), pi_2ra = R(p.pi_2ra);
   const R* gG = reinterpret_cast<const R*>(p.gG) + (size_t)i * p.ldG;
   constexpr int T1 = NR + 1, T2 = NR + NA + 2;
   // the weighted channel's coefficients (read at the typed ones and unused
@@ -378,8 +378,8 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
   const int nn = active ? p.nnb[i] : 0;
   const int na = active ? p.nang[i] : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
-  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
-  const R two_ra = R(2.0 / p.ra);
+  const R inv_rr2 = R(p.two_rr), pi_rr = R(p.pi_rr), pi_ra = R(p.pi_ra);
+  const R two_ra = R(p.two_ra);
 
   for (int e = l; e < nn; e += LPA) {
     double d0, d1, d2;

@@ -98,7 +98,6 @@ __device__ inline void len_inv<float>(float r2, float* r, float* ir) {
   *r = r2 * y;
 }
 
-constexpr double kPi = 3.14159265358979323846;
 
 // Taylor coefficient of t^n in sin t (n odd) or cos t (n even): +-1/n!
 constexpr double taylor_sc(int n) {
@@ -292,8 +291,8 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
   const int nn = active ? nn_ld : 0;
   const int na = active ? na_ld : 0;
   const double rr2 = p.rr * p.rr, ra2 = p.ra * p.ra;
-  const R inv_rr2 = R(2.0 / p.rr), pi_rr = R(kPi / p.rr), pi_ra = R(kPi / p.ra);
-  const R two_ra = R(2.0 / p.ra);
+  const R inv_rr2 = R(p.two_rr), pi_rr = R(p.pi_rr), pi_ra = R(p.pi_ra);
+  const R two_ra = R(p.two_ra);
 
   // radial terms, Eq. 3.  Two entries per lane per iteration give two
   // independent recurrence chains; entries beyond R_r (skin) or past the end

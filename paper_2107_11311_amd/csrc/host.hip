@@ -493,6 +493,12 @@ DescParams desc_params(aenet_ctx* c) {
   p.ang_hint = c->ang_mean;
   p.rr = c->rr;
   p.ra = c->ra;
+  p.two_rr = 2.0 / c->rr;
+  p.two_ra = 2.0 / c->ra;
+  p.pi_rr = kPi / c->rr;
+  p.pi_ra = kPi / c->ra;
+  p.pi_2rr = 0.5 * kPi / c->rr;
+  p.pi_2ra = 0.5 * kPi / c->ra;
   p.wq = c->d_wq.as<double>();
   for (int s = 0; s < kMaxSpecies; ++s) p.tw[s] = c->tw[s];
   p.n_species = c->S;
