@@ -55,10 +55,12 @@ __global__ __launch_bounds__(256, 3) void k_fwd_mlp(DescParams dp, MlpParams mp,
   // the first layer's weights are on their way while the block waits
   Frag<PREC> b0{};
   mlp_prefetch<PREC>(mp, net, 0, threadIdx.x >> 6, threadIdx.x & 63, b0);
+  MlpConsts<PREC> kc;
+  mlp_consts<PREC>(mp, net, threadIdx.x, kc);
   __syncthreads();
   // the network's work buffers reuse the descriptor pass's LDS
   if (dp.prio) __builtin_amdgcn_s_setprio(0);
-  mlp_tile<PREC>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x, b0);
+  mlp_tile<PREC>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x, b0, kc);
 }
 
 template <int PREC, int NR, int NA>

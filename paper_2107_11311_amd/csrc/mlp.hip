@@ -37,6 +37,8 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
   const MlpNet& net = p.net[ti.species];
   Frag<PREC> b0{};
   mlp_prefetch<PREC>(p, net, 0, tid >> 6, tid & 63, b0);
+  MlpConsts<PREC> kc;
+  mlp_consts<PREC>(p, net, tid, kc);
   {
     const T* G = reinterpret_cast<const T*>(p.G);
     const T* sh = reinterpret_cast<const T*>(net.shift);
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
     }
   }
   __syncthreads();
-  mlp_tile<PREC>(p, ti, lds, lds + act_offset(p, 1), tid, b0);
+  mlp_tile<PREC>(p, ti, lds, lds + act_offset(p, 1), tid, b0, kc);
 }
 
 // ------------------------------------------------------------------ training

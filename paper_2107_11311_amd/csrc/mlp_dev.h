@@ -266,6 +266,35 @@ __device__ inline void mlp_prefetch(const MlpParams& p, const MlpNet& net, int s
                     lane);
 }
 
+// Per-thread constants of a tile's network, loaded with the first B operand
+// (before the tile barrier) so that no layer waits on a global load of its
+// own: the bias of the thread's output column in each hidden layer, the
+// output weights of the columns it reduces for the energy (k = (tid & 15) +
+// 16 m), and the input scaling of its output column in the last backward
+// stage.  Indices are clamped into the padded arrays; values past the true
+// widths are not used.
+template <int PREC>
+struct MlpConsts {
+  typename Mt<PREC>::T bias[kMaxLayers];
+  typename Mt<PREC>::T wl[kMaxWidth / 16];
+  typename Mt<PREC>::T sc;
+};
+template <int PREC>
+__device__ inline void mlp_consts(const MlpParams& p, const MlpNet& net, int tid, MlpConsts<PREC>& c) {
+  typedef typename Mt<PREC>::T T;
+  const int col = (tid >> 6) * 16 + (tid & 15);
+  const int L = p.n_layers;
+  c.bias[0] = T(0);
+#pragma unroll
+  for (int l = 1; l < kMaxLayers; ++l)
+    c.bias[l] = l < L ? reinterpret_cast<const T*>(net.bias[l])[min(col, p.wp[l] - 1)] : T(0);
+  const T* wl = reinterpret_cast<const T*>(net.wlast);
+  const int KL = p.wp[L - 1];
+#pragma unroll
+  for (int m = 0; m < kMaxWidth / 16; ++m) c.wl[m] = wl[min((tid & 15) + 16 * m, KL - 1)];
+  c.sc = reinterpret_cast<const T*>(net.scale)[min(col, p.w[0] - 1)];
+}
+
 // Hidden layers, energy and (if p.gG) input gradient of one 16-atom tile
 // whose normalised input is in X0, by kMlpWaves wavefronts (tid < 64 *
 // kMlpWaves): wavefront w computes the 16-column output block w of every
@@ -274,7 +303,8 @@ __device__ inline void mlp_prefetch(const MlpParams& p, const MlpNet& net, int s
 // issues the loads of the next one before its own products.
 template <int PREC>
 __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename Mt<PREC>::T* X0,
-                                typename Mt<PREC>::T* work, int tid, const Frag<PREC>& b0) {
+                                typename Mt<PREC>::T* work, int tid, const Frag<PREC>& b0,
+                                const MlpConsts<PREC>& kc) {
   typedef typename Mt<PREC>::T T;
   constexpr int NT = 64 * kMlpWaves;
   static_assert(16 * kMlpWaves == kMaxWidth, "one output block per wavefront and layer");
@@ -290,12 +320,13 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
   int s = 0;
 
   // hidden layers
-  for (int l = 1; l < L; ++l, ++s) {
+#pragma unroll
+  for (int l = 1; l < kMaxLayers; ++l) {
+    if (l >= L) break;
     mlp_prefetch<PREC>(p, net, s + 1, wave, lane, nxt);
     const T* Xin = X(l - 1);
     T* Y = X(l);
     const int K = p.wp[l - 1], N = p.wp[l];
-    const T* bias = reinterpret_cast<const T*>(net.bias[l]);
     const int act = p.act[l - 1];
     if (wave < N / 16) {
       auto acc = mfma_frag<PREC>(Xin, K + 1, K, cur, lane);
@@ -303,35 +334,43 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = acc_row<PREC>(lane, i);
-        Y[row * (N + 1) + col] = act_fn<T>(act, T(acc[i]) + bias[col]);
+        Y[row * (N + 1) + col] = act_fn<T>(act, T(acc[i]) + kc.bias[l]);
       }
     }
     cur = nxt;
+    ++s;
     __syncthreads();
   }
 
   // output layer and per-atom energy: 16 lanes per row, each summing every
-  // 16th column, then a 16-lane tree
+  // 16th column, then a 16-lane tree; the same thread starts the
+  // back-propagation to the input at those columns (the output layer is
+  // linear; X_{L-1} was produced by the activation of layer L-1, none if
+  // L == 1)
   const T* XL = X(L - 1);
   const int KL = p.wp[L - 1];
-  const T* wl = reinterpret_cast<const T*>(net.wlast);
   {
     static_assert(NT == 256, "16 rows x 16 lanes");
     const int r = tid >> 4, c0 = tid & 15;
     T e = T(0);
-    for (int k = c0; k < KL; k += 16) e += XL[r * (KL + 1) + k] * wl[k];
+    T x[kMaxWidth / 16];
+#pragma unroll
+    for (int m = 0; m < kMaxWidth / 16; ++m) {
+      const int k = c0 + 16 * m;
+      if (k < KL) {
+        x[m] = XL[r * (KL + 1) + k];
+        e += x[m] * kc.wl[m];
+      }
+    }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) e += __shfl_xor(e, o, 16);
     if (c0 == 0 && r < ti.count) p.E[ti.first + r] = (double)e + net.blast + net.e_offset;
-  }
-  if (!p.gG) return;
-
-  // back-propagation to the input (the output layer is linear; X_{L-1} was
-  // produced by the activation of layer L-1, none if L == 1)
-  for (int idx = tid; idx < 16 * KL; idx += NT) {
-    const int r = idx / KL, c = idx % KL;
-    const T x = XL[r * (KL + 1) + c];
-    D0[r * DLD + c] = L >= 2 ? wl[c] * act_d1<T>(p.act[L - 2], x) : wl[c];
+    if (!p.gG) return;
+#pragma unroll
+    for (int m = 0; m < kMaxWidth / 16; ++m) {
+      const int k = c0 + 16 * m;
+      if (k < KL) D0[r * DLD + k] = L >= 2 ? kc.wl[m] * act_d1<T>(p.act[L - 2], x[m]) : kc.wl[m];
+    }
   }
   __syncthreads();
   T* Dcur = D0;
@@ -360,7 +399,7 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
         if (l >= 2) {
           Dnext[row * DLD + col] = v * act_d1<T>(actp, Xp[row * (N + 1) + col]);
         } else if (row < ti.count && col < p.w[0]) {
-          gout[(size_t)(ti.first + row) * p.ldG + col] = v * sc[col];
+          gout[(size_t)(ti.first + row) * p.ldG + col] = v * kc.sc;
         }
       }
     }
