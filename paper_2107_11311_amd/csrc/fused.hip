@@ -27,7 +27,7 @@ struct DescType<0> {
 
 constexpr int kFusedLanes = 16;  // lanes per atom: 16 atoms = one network tile per block
 
-template <int PREC, int NR, int NA>
+template <int PREC, int NR, int NA, int NL, bool NARROW>
 __global__ __launch_bounds__(256, 3) void k_fwd_mlp(DescParams dp, MlpParams mp, int x0_off) {
   typedef typename Mt<PREC>::T T;
   typedef typename DescType<PREC>::R R;
@@ -52,25 +52,27 @@ __global__ __launch_bounds__(256, 3) void k_fwd_mlp(DescParams dp, MlpParams mp,
   // padding columns, and the rows of a tile shorter than 16 atoms, are zero
   for (int c = l; c < w0; c += LPA)
     if (!active || c >= D) xrow[c] = T(0);
-  // the first layer's weights are on their way while the block waits
-  Frag<PREC> b0{};
-  mlp_prefetch<PREC>(mp, net, 0, threadIdx.x >> 6, threadIdx.x & 63, b0);
-  MlpConsts<PREC> kc;
-  mlp_consts<PREC>(mp, net, threadIdx.x, kc);
-  __syncthreads();
-  // the network's work buffers reuse the descriptor pass's LDS
-  if (dp.prio) __builtin_amdgcn_s_setprio(0);
-  mlp_tile<PREC>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x, b0, kc);
+  // the network phase (its first loads are issued before its barrier); its
+  // work buffers reuse the descriptor pass's LDS
+  mlp_tile_n<PREC, NL, mlp_mkh<PREC, NARROW>()>(mp, ti, X0, reinterpret_cast<T*>(smem), threadIdx.x, dp.prio);
 }
 
 template <int PREC, int NR, int NA>
 void launch_fused(const DescParams& dp, const MlpParams& mp, int n_tiles, size_t lds, int x0_off,
                   hipStream_t s) {
   DescParams q = dp;
-  q.prio = fits_one_round(reinterpret_cast<const void*>(&k_fwd_mlp<PREC, NR, NA>), 16 * kFusedLanes, lds,
-                          n_tiles);
-  hipLaunchKernelGGL((k_fwd_mlp<PREC, NR, NA>), dim3(n_tiles), dim3(16 * kFusedLanes), lds, s, q, mp,
-                     x0_off);
+  // the network's depth and hidden width select the kernel (see mlp_tile_n)
+  const bool narrow = mlp_narrow(mp);
+  auto go = [&](auto kernel) {
+    q.prio = fits_one_round(reinterpret_cast<const void*>(kernel), 16 * kFusedLanes, lds, n_tiles);
+    hipLaunchKernelGGL(kernel, dim3(n_tiles), dim3(16 * kFusedLanes), lds, s, q, mp, x0_off);
+  };
+  switch (mp.n_layers) {  // 1..kMaxLayers, checked when the model is set up
+    case 1: go(k_fwd_mlp<PREC, NR, NA, 1, true>); break;
+    case 2: narrow ? go(k_fwd_mlp<PREC, NR, NA, 2, true>) : go(k_fwd_mlp<PREC, NR, NA, 2, false>); break;
+    case 3: narrow ? go(k_fwd_mlp<PREC, NR, NA, 3, true>) : go(k_fwd_mlp<PREC, NR, NA, 3, false>); break;
+    default: narrow ? go(k_fwd_mlp<PREC, NR, NA, 4, true>) : go(k_fwd_mlp<PREC, NR, NA, 4, false>); break;
+  }
 }
 
 template <int PREC>

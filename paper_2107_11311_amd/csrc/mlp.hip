@@ -18,6 +18,8 @@
 //   phi = eps * E - (dE/dX_0 . u*scale)
 // (double back-propagation), accumulating dphi/dW and dphi/db of the tile
 // into an LDS copy of the species' parameters with MFMA outer products.
+#include <type_traits>
+
 #include "mlp_dev.h"
 
 namespace aenet {
@@ -25,8 +27,9 @@ namespace aenet {
 namespace {
 
 // Forward and input-gradient pass of one 16-atom tile per block: the tile's
-// descriptors are loaded and normalised into LDS, then mlp_tile.
-template <int PREC>
+// descriptors are loaded and normalised into LDS, then mlp_tile (which holds
+// the barrier).
+template <int PREC, int NL, bool NARROW>
 __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
   typedef typename Mt<PREC>::T T;
   constexpr int NT = 64 * kMlpWaves;  // threads per tile
@@ -35,10 +38,6 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
   const int tid = threadIdx.x;
   const TileInfo ti = tile_info(p, blockIdx.x);
   const MlpNet& net = p.net[ti.species];
-  Frag<PREC> b0{};
-  mlp_prefetch<PREC>(p, net, 0, tid >> 6, tid & 63, b0);
-  MlpConsts<PREC> kc;
-  mlp_consts<PREC>(p, net, tid, kc);
   {
     const T* G = reinterpret_cast<const T*>(p.G);
     const T* sh = reinterpret_cast<const T*>(net.shift);
@@ -60,8 +59,7 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp(MlpParams p) {
       if (idx < 16 * w0) lds[r * (w0 + 1) + c] = (r < ti.count && c < D) ? (v[it] - sh[c]) * sc[c] : T(0);
     }
   }
-  __syncthreads();
-  mlp_tile<PREC>(p, ti, lds, lds + act_offset(p, 1), tid, b0, kc);
+  mlp_tile_n<PREC, NL, mlp_mkh<PREC, NARROW>()>(p, ti, lds, lds + act_offset(p, 1), tid, 0);
 }
 
 // ------------------------------------------------------------------ training
@@ -304,12 +302,24 @@ void launch_mlp(int prec, const MlpParams& p, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return;
   const size_t lds = mlp_lds_bytes(prec, p);
   const dim3 block(64 * kMlpWaves);
+  const bool narrow = mlp_narrow(p);
+  auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, dim3(n_tiles), block, lds, s, p); };
+  // the network's depth and hidden width select the kernel (see mlp_tile_n)
+  auto by_shape = [&](auto prec_tag) {
+    constexpr int P = decltype(prec_tag)::value;
+    switch (p.n_layers) {  // 1..kMaxLayers, checked when the model is set up
+      case 1: go(k_mlp<P, 1, true>); break;
+      case 2: narrow ? go(k_mlp<P, 2, true>) : go(k_mlp<P, 2, false>); break;
+      case 3: narrow ? go(k_mlp<P, 3, true>) : go(k_mlp<P, 3, false>); break;
+      default: narrow ? go(k_mlp<P, 4, true>) : go(k_mlp<P, 4, false>); break;
+    }
+  };
   if (prec == 0)
-    hipLaunchKernelGGL(k_mlp<0>, dim3(n_tiles), block, lds, s, p);
+    by_shape(std::integral_constant<int, 0>());
   else if (prec == 1)
-    hipLaunchKernelGGL(k_mlp<1>, dim3(n_tiles), block, lds, s, p);
+    by_shape(std::integral_constant<int, 1>());
   else
-    hipLaunchKernelGGL(k_mlp<2>, dim3(n_tiles), block, lds, s, p);
+    by_shape(std::integral_constant<int, 2>());
 }
 
 void launch_mlp_train(int prec, const MlpParams& p, int n_blocks, hipStream_t s) {

@@ -51,38 +51,42 @@ __device__ inline int acc_row(int lane, int i) {
 // k-steps of one packed element (FP64/FP32) or eight BF16 values per lane.
 // BF16 also holds an optional second operand: the low parts of a layer kept
 // as a BF16 pair (has_lo, wave-uniform).
-template <int PREC>
+// MK: k-steps the fragment can hold (the full kMaxWidth by default).
+template <int PREC, int MK = kMaxWidth / Mt<PREC>::KS>
 struct Frag {
-  typename Mt<PREC>::B b[kMaxWidth / Mt<PREC>::KS][Mt<PREC>::BV];
-  typename Mt<PREC>::B lo[PREC == 2 ? kMaxWidth / 32 : 1][PREC == 2 ? 8 : 1];
+  static constexpr int maxks = MK;
+  typename Mt<PREC>::B b[MK][Mt<PREC>::BV];
+  typename Mt<PREC>::B lo[PREC == 2 ? MK : 1][PREC == 2 ? 8 : 1];
   bool has_lo;
 };
 
 // issue the loads of output block nb's B operand (K/KS k-steps), and of its
 // low parts if Blo is not NULL (BF16 only)
-template <int PREC>
-__device__ inline void load_frag(Frag<PREC>& f, const typename Mt<PREC>::B* Bp, const typename Mt<PREC>::B* Blo,
+template <int PREC, int MK>
+__device__ __forceinline__ void load_frag(Frag<PREC, MK>& f, const typename Mt<PREC>::B* Bp, const typename Mt<PREC>::B* Blo,
                                  int nb, int K, int lane) {
   typedef Mt<PREC> M;
-  constexpr int MAXKS = kMaxWidth / M::KS;
+  constexpr int MAXKS = MK;
   const int ksteps = K / M::KS;
   f.has_lo = PREC == 2 && Blo != nullptr;
+  // every k-step slot is loaded, those past the layer's width with a copy of
+  // its last k-step (unused): loads under a branch would make the wait for
+  // this fragment, one stage later, also wait for the next stage's loads
+  const typename Mt<PREC>::B* Bl = f.has_lo ? Blo : Bp;
 #pragma unroll
   for (int ks = 0; ks < MAXKS; ++ks) {
-    if (ks < ksteps) {
-      if constexpr (PREC == 2) {
-        const size_t o = (((size_t)nb * ksteps + ks) * 64 + lane) * 8;
-        const v8bf v = *reinterpret_cast<const v8bf*>(Bp + o);
+    const int kc = min(ks, ksteps - 1);
+    if constexpr (PREC == 2) {
+      const size_t o = (((size_t)nb * ksteps + kc) * 64 + lane) * 8;
+      const v8bf v = *reinterpret_cast<const v8bf*>(Bp + o);
+      const v8bf w = *reinterpret_cast<const v8bf*>(Bl + o);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) f.b[ks][t] = v[t];
-        if (f.has_lo) {
-          const v8bf w = *reinterpret_cast<const v8bf*>(Blo + o);
-#pragma unroll
-          for (int t = 0; t < 8; ++t) f.lo[ks][t] = w[t];
-        }
-      } else {
-        f.b[ks][0] = Bp[((size_t)nb * ksteps + ks) * 64 + lane];
+      for (int t = 0; t < 8; ++t) {
+        f.b[ks][t] = v[t];
+        f.lo[ks][t] = w[t];
       }
+    } else {
+      f.b[ks][0] = Bp[((size_t)nb * ksteps + kc) * 64 + lane];
     }
   }
 }
@@ -90,20 +94,19 @@ __device__ inline void load_frag(Frag<PREC>& f, const typename Mt<PREC>::B* Bp, 
 // one 16x16 output block: sum over K of A[16 x K] (LDS, row-major, row stride
 // ld) times the B operand in f.  All A operands are loaded before the MFMA
 // chain so their latencies overlap.
-template <int PREC>
-__device__ inline typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A, int ld, int K,
-                                                    const Frag<PREC>& f, int lane) {
+template <int PREC, int MK>
+__device__ __forceinline__ typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A, int ld, int K,
+                                                    const Frag<PREC, MK>& f, int lane) {
   typedef Mt<PREC> M;
   typename M::Acc acc = {0, 0, 0, 0};
   const int ksteps = K / M::KS;
   const int r = lane & 15, kq = lane >> 4;
   if constexpr (PREC == 0 || PREC == 1) {
     typedef typename M::T T;
-    constexpr int MAXKS = kMaxWidth / 4;
+    constexpr int MAXKS = MK;
     T a[MAXKS];
 #pragma unroll
-    for (int ks = 0; ks < MAXKS; ++ks)
-      if (ks < ksteps) a[ks] = A[r * ld + ks * 4 + kq];
+    for (int ks = 0; ks < MAXKS; ++ks) a[ks] = A[r * ld + min(ks, ksteps - 1) * 4 + kq];
     // two independent accumulation chains (even / odd k-steps) halve the
     // dependent MFMA latency
     typename M::Acc acc1 = {0, 0, 0, 0};
@@ -129,20 +132,18 @@ __device__ inline typename Mt<PREC>::Acc mfma_frag(const typename Mt<PREC>::T* A
     // products per k-step on the BF16 MFMA, FP32 accumulation; a layer held
     // as a weight pair adds the product of the activations' hi part with the
     // weights' lo part
-    constexpr int MAXKS = kMaxWidth / 32;
+    constexpr int MAXKS = MK;
     v8bf ah[MAXKS], al[MAXKS], bb[MAXKS], bl[MAXKS];
 #pragma unroll
     for (int ks = 0; ks < MAXKS; ++ks) {
-      if (ks < ksteps) {
-        const float* ap = A + r * ld + ks * 32 + 8 * kq;
+      const float* ap = A + r * ld + min(ks, ksteps - 1) * 32 + 8 * kq;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const __bf16 hi = (__bf16)ap[t];
-          ah[ks][t] = hi;
-          al[ks][t] = (__bf16)(ap[t] - (float)hi);
-          bb[ks][t] = f.b[ks][t];
-          bl[ks][t] = f.lo[ks][t];
-        }
+      for (int t = 0; t < 8; ++t) {
+        const __bf16 hi = (__bf16)ap[t];
+        ah[ks][t] = hi;
+        al[ks][t] = (__bf16)(ap[t] - (float)hi);
+        bb[ks][t] = f.b[ks][t];
+        bl[ks][t] = f.lo[ks][t];
       }
     }
     typename M::Acc acc1 = {0, 0, 0, 0};
@@ -208,7 +209,7 @@ struct TileInfo {
   int species, first, count;
 };
 
-__device__ inline TileInfo tile_info(const MlpParams& p, int tile) {
+__device__ __forceinline__ TileInfo tile_info(const MlpParams& p, int tile) {
   TileInfo t{0, 0, 0};
   int s = 0;
   while (s + 1 < p.n_species && tile >= p.tile_off[s + 1]) ++s;
@@ -220,7 +221,7 @@ __device__ inline TileInfo tile_info(const MlpParams& p, int tile) {
 
 // element offset of the activations of layer l when X_0..X_{L-1} are stored
 // one after the other with row strides wp[l] + 1
-__host__ __device__ inline size_t act_offset(const MlpParams& p, int l) {
+__host__ __device__ __forceinline__ size_t act_offset(const MlpParams& p, int l) {
   size_t o = 0;
   for (int k = 0; k < l; ++k) o += 16 * (size_t)(p.wp[k] + 1);
   return o;
@@ -245,19 +246,19 @@ struct MlpStage {
   const void* Blo;  // low parts of a BF16 weight pair, or NULL
   int K, N;
 };
-__device__ inline MlpStage mlp_stage(const MlpParams& p, const MlpNet& net, int s) {
+__device__ __forceinline__ MlpStage mlp_stage(const MlpParams& p, const MlpNet& net, int s) {
   const int H = p.n_layers - 1;
   if (s < H) return MlpStage{net.wf[s + 1], s == 0 ? net.wf_lo : nullptr, p.wp[s], p.wp[s + 1]};
   const int l = H - (s - H);
   return MlpStage{net.wb[l], l == 1 ? net.wb_lo : nullptr, p.wp[l], p.wp[l - 1]};
 }
-__device__ inline int mlp_n_stages(const MlpParams& p) { return (p.n_layers - 1) * (p.gG ? 2 : 1); }
+__device__ __forceinline__ int mlp_n_stages(const MlpParams& p) { return (p.n_layers - 1) * (p.gG ? 2 : 1); }
 
 // Issue wavefront `wave`'s B-operand loads of stage s (it owns the 16-column
 // block nb = wave; a layer is at most kMaxWidth = 16 * kMlpWaves wide).
-template <int PREC>
-__device__ inline void mlp_prefetch(const MlpParams& p, const MlpNet& net, int s, int wave, int lane,
-                                    Frag<PREC>& f) {
+template <int PREC, int MK>
+__device__ __forceinline__ void mlp_prefetch(const MlpParams& p, const MlpNet& net, int s, int wave, int lane,
+                                    Frag<PREC, MK>& f) {
   if (s >= mlp_n_stages(p)) return;
   const MlpStage st = mlp_stage(p, net, s);
   typedef typename Mt<PREC>::B Bt;
@@ -280,7 +281,7 @@ struct MlpConsts {
   typename Mt<PREC>::T sc;
 };
 template <int PREC>
-__device__ inline void mlp_consts(const MlpParams& p, const MlpNet& net, int tid, MlpConsts<PREC>& c) {
+__device__ __forceinline__ void mlp_consts(const MlpParams& p, const MlpNet& net, int tid, MlpConsts<PREC>& c) {
   typedef typename Mt<PREC>::T T;
   const int col = (tid >> 6) * 16 + (tid & 15);
   const int L = p.n_layers;
@@ -295,60 +296,178 @@ __device__ inline void mlp_consts(const MlpParams& p, const MlpNet& net, int tid
   c.sc = reinterpret_cast<const T*>(net.scale)[min(col, p.w[0] - 1)];
 }
 
+// The network phase of a tile.  Stage 0 (the input layer) has its own
+// fragment b0; the B operands of stages 1, 2, ... rotate through three
+// fragments ring[(s - 1) mod 3].  Stages 0 and 1, and the per-thread
+// constants, are loaded before the block barrier that starts the phase, and
+// stage s + 2 while stage s multiplies, so that no stage waits for loads
+// issued in the stage before.  Only stage 0 multiplies by the input width;
+// the others by a hidden width, so the ring holds MKH k-steps (half the
+// registers when every hidden layer is at most 32 wide).  NL = p.n_layers
+// (weight layers) is a template parameter and every stage a template
+// instance, so every fragment is a fixed register set.
+//
 // Hidden layers, energy and (if p.gG) input gradient of one 16-atom tile
 // whose normalised input is in X0, by kMlpWaves wavefronts (tid < 64 *
 // kMlpWaves): wavefront w computes the 16-column output block w of every
-// layer, with a block barrier between layers.  `b0` holds the wavefront's
-// B operand of the first stage (mlp_prefetch(p, net, 0, ...)); each stage
-// issues the loads of the next one before its own products.
-template <int PREC>
-__device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename Mt<PREC>::T* X0,
-                                typename Mt<PREC>::T* work, int tid, const Frag<PREC>& b0,
-                                const MlpConsts<PREC>& kc) {
-  typedef typename Mt<PREC>::T T;
-  constexpr int NT = 64 * kMlpWaves;
-  static_assert(16 * kMlpWaves == kMaxWidth, "one output block per wavefront and layer");
-  const int lane = tid & 63, wave = tid >> 6;
-  const MlpNet& net = p.net[ti.species];
-  const int L = p.n_layers;
-  constexpr int DLD = kMaxWidth + 1;  // row stride of the delta buffers
-  const size_t base1 = act_offset(p, 1);
-  auto X = [&](int l) { return l == 0 ? X0 : work + (act_offset(p, l) - base1); };
-  T* D0 = work + (act_offset(p, L) - base1);
-  T* D1 = D0 + 16 * DLD;
-  Frag<PREC> cur = b0, nxt{};
-  int s = 0;
+// layer, with a block barrier between layers.
+// loads of stage S of a network of NL layers into its fragment (the stages
+// as in mlp_stage; none past the last stage)
+template <int PREC, int NL, int S, typename F>
+__device__ __forceinline__ void mt_load_into(const MlpParams& p, const MlpNet& net, int wave, int lane, F& f) {
+  constexpr int H = NL - 1;
+  typedef typename Mt<PREC>::B Bt;
+  if constexpr (S < 2 * H) {
+    if (S >= H && !p.gG) return;
+    const void* Bp;
+    const void* Blo;
+    int K, N;
+    if constexpr (S < H) {
+      Bp = net.wf[S + 1];
+      Blo = S == 0 ? net.wf_lo : nullptr;
+      K = p.wp[S];
+      N = p.wp[S + 1];
+    } else {
+      constexpr int l = H - (S - H);
+      Bp = net.wb[l];
+      Blo = l == 1 ? net.wb_lo : nullptr;
+      K = p.wp[l];
+      N = p.wp[l - 1];
+    }
+    if (wave < N / 16)
+      load_frag<PREC>(f, reinterpret_cast<const Bt*>(Bp), reinterpret_cast<const Bt*>(Blo), wave, K, lane);
+  }
+}
+template <int PREC, int NL, int MKH, int S>
+__device__ __forceinline__ void mt_load(const MlpParams& p, const MlpNet& net, int wave, int lane,
+                                        Frag<PREC>& b0, Frag<PREC, MKH> (&ring)[3]) {
+  if constexpr (S == 0)
+    mt_load_into<PREC, NL, 0>(p, net, wave, lane, b0);
+  else
+    mt_load_into<PREC, NL, S>(p, net, wave, lane, ring[(S - 1) % 3]);
+}
+template <int PREC, int MKH, int S>
+__device__ __forceinline__ typename Mt<PREC>::Acc mt_product(const typename Mt<PREC>::T* A, int ld, int K,
+                                                             int lane, const Frag<PREC>& b0,
+                                                             const Frag<PREC, MKH> (&ring)[3]) {
+  if constexpr (S == 0)
+    return mfma_frag<PREC>(A, ld, K, b0, lane);
+  else
+    return mfma_frag<PREC>(A, ld, K, ring[(S - 1) % 3], lane);
+}
 
-  // hidden layers
-#pragma unroll
-  for (int l = 1; l < kMaxLayers; ++l) {
-    if (l >= L) break;
-    mlp_prefetch<PREC>(p, net, s + 1, wave, lane, nxt);
-    const T* Xin = X(l - 1);
-    T* Y = X(l);
+// everything one stage of a tile needs; X[l] = the activations of layer l
+// (X[NL] = the first delta buffer)
+template <int PREC, int NL>
+struct MtState {
+  typename Mt<PREC>::T* X[NL + 1];
+  int tid, lane, wave;
+  typename Mt<PREC>::T* Dcur;
+  typename Mt<PREC>::T* Dnext;
+};
+
+// hidden layer l of NL (stage l - 1)
+template <int PREC, int NL, int MKH, int l>
+__device__ __forceinline__ void mt_forward(const MlpParams& p, const MlpNet& net, MtState<PREC, NL>& st,
+                                           Frag<PREC>& b0, Frag<PREC, MKH> (&ring)[3],
+                                           const MlpConsts<PREC>& kc) {
+  typedef typename Mt<PREC>::T T;
+  if constexpr (l <= NL - 1) {
+    mt_load<PREC, NL, MKH, l + 1>(p, net, st.wave, st.lane, b0, ring);
+    const T* Xin = st.X[l - 1];
+    T* Y = st.X[l];
     const int K = p.wp[l - 1], N = p.wp[l];
     const int act = p.act[l - 1];
-    if (wave < N / 16) {
-      auto acc = mfma_frag<PREC>(Xin, K + 1, K, cur, lane);
-      const int col = wave * 16 + (lane & 15);
+    if (st.wave < N / 16) {
+      const auto acc = mt_product<PREC, MKH, l - 1>(Xin, K + 1, K, st.lane, b0, ring);
+      const int col = st.wave * 16 + (st.lane & 15);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = acc_row<PREC>(lane, i);
+        const int row = acc_row<PREC>(st.lane, i);
         Y[row * (N + 1) + col] = act_fn<T>(act, T(acc[i]) + kc.bias[l]);
       }
     }
-    cur = nxt;
-    ++s;
     __syncthreads();
+    mt_forward<PREC, NL, MKH, l + 1>(p, net, st, b0, ring, kc);
   }
+}
+
+// back-propagation through layer l of NL (stage 2 (NL - 1) - l)
+template <int PREC, int NL, int MKH, int l>
+__device__ __forceinline__ void mt_backward(const MlpParams& p, const TileInfo& ti, const MlpNet& net,
+                                            MtState<PREC, NL>& st, Frag<PREC>& b0,
+                                            Frag<PREC, MKH> (&ring)[3], const MlpConsts<PREC>& kc) {
+  typedef typename Mt<PREC>::T T;
+  constexpr int DLD = kMaxWidth + 1;
+  if constexpr (l >= 1) {
+    constexpr int S = 2 * (NL - 1) - l;
+    mt_load<PREC, NL, MKH, S + 2>(p, net, st.wave, st.lane, b0, ring);
+    const int K = p.wp[l], N = p.wp[l - 1];
+    const T* Xp = st.X[l - 1];
+    const int actp = l >= 2 ? p.act[l - 2] : 0;
+    T* gout = reinterpret_cast<T*>(p.gG);
+    if (st.wave < N / 16) {
+      const auto acc = mt_product<PREC, MKH, S>(st.Dcur, DLD, K, st.lane, b0, ring);
+      const int col = st.wave * 16 + (st.lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = acc_row<PREC>(st.lane, i);
+        const T v = T(acc[i]);
+        if (l >= 2) {
+          st.Dnext[row * DLD + col] = v * act_d1<T>(actp, Xp[row * (N + 1) + col]);
+        } else if (row < ti.count && col < p.w[0]) {
+          gout[(size_t)(ti.first + row) * p.ldG + col] = v * kc.sc;
+        }
+      }
+    }
+    __syncthreads();
+    T* t = st.Dcur;
+    st.Dcur = st.Dnext;
+    st.Dnext = t;
+    mt_backward<PREC, NL, MKH, l - 1>(p, ti, net, st, b0, ring, kc);
+  }
+}
+
+template <int PREC, int NL, int MKH>
+__device__ __forceinline__ void mlp_tile_n(const MlpParams& p, const TileInfo& ti, typename Mt<PREC>::T* X0,
+                                           typename Mt<PREC>::T* work, int tid, int prio) {
+  typedef typename Mt<PREC>::T T;
+  constexpr int NT = 64 * kMlpWaves;
+  constexpr int L = NL, H = NL - 1;
+  constexpr int DLD = kMaxWidth + 1;  // row stride of the delta buffers
+  static_assert(16 * kMlpWaves == kMaxWidth, "one output block per wavefront and layer");
+  const MlpNet& net = p.net[ti.species];
+  MtState<PREC, NL> st;
+  st.tid = tid;
+  st.lane = tid & 63;
+  st.wave = tid >> 6;
+  st.X[0] = X0;
+  {
+    T* x = work;
+#pragma unroll
+    for (int l = 1; l <= NL; ++l) {
+      st.X[l] = x;
+      x += 16 * (size_t)(p.wp[l] + 1);
+    }
+  }
+  Frag<PREC> b0;
+  Frag<PREC, MKH> ring[3];
+  MlpConsts<PREC> kc;
+  mt_load<PREC, NL, MKH, 0>(p, net, st.wave, st.lane, b0, ring);
+  mt_load<PREC, NL, MKH, 1>(p, net, st.wave, st.lane, b0, ring);
+  mlp_consts<PREC>(p, net, tid, kc);
+  __syncthreads();  // the tile's input is in X0
+  if (prio) __builtin_amdgcn_s_setprio(0);
+  mt_forward<PREC, NL, MKH, 1>(p, net, st, b0, ring, kc);
 
   // output layer and per-atom energy: 16 lanes per row, each summing every
   // 16th column, then a 16-lane tree; the same thread starts the
   // back-propagation to the input at those columns (the output layer is
   // linear; X_{L-1} was produced by the activation of layer L-1, none if
   // L == 1)
-  const T* XL = X(L - 1);
+  const T* XL = st.X[L - 1];
   const int KL = p.wp[L - 1];
+  T* D0 = st.X[L];
   {
     static_assert(NT == 256, "16 rows x 16 lanes");
     const int r = tid >> 4, c0 = tid & 15;
@@ -373,42 +492,30 @@ __device__ inline void mlp_tile(const MlpParams& p, const TileInfo& ti, typename
     }
   }
   __syncthreads();
-  T* Dcur = D0;
-  T* Dnext = D1;
-  T* gout = reinterpret_cast<T*>(p.gG);
-  const T* sc = reinterpret_cast<const T*>(net.scale);
-  if (L == 1) {
+  st.Dcur = D0;
+  st.Dnext = D0 + 16 * DLD;
+  if constexpr (H == 0) {
+    T* gout = reinterpret_cast<T*>(p.gG);
+    const T* sc = reinterpret_cast<const T*>(net.scale);
     for (int idx = tid; idx < 16 * p.wp[0]; idx += NT) {
       const int r = idx / p.wp[0], c = idx % p.wp[0];
-      if (r < ti.count && c < p.w[0]) gout[(size_t)(ti.first + r) * p.ldG + c] = Dcur[r * DLD + c] * sc[c];
+      if (r < ti.count && c < p.w[0]) gout[(size_t)(ti.first + r) * p.ldG + c] = st.Dcur[r * DLD + c] * sc[c];
     }
-    return;
+  } else {
+    mt_backward<PREC, NL, MKH, H>(p, ti, net, st, b0, ring, kc);
   }
-  for (int l = L - 1; l >= 1; --l, ++s) {
-    mlp_prefetch<PREC>(p, net, s + 1, wave, lane, nxt);
-    const int K = p.wp[l], N = p.wp[l - 1];
-    const T* Xp = X(l - 1);
-    const int actp = l >= 2 ? p.act[l - 2] : 0;
-    if (wave < N / 16) {
-      auto acc = mfma_frag<PREC>(Dcur, DLD, K, cur, lane);
-      const int col = wave * 16 + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = acc_row<PREC>(lane, i);
-        const T v = T(acc[i]);
-        if (l >= 2) {
-          Dnext[row * DLD + col] = v * act_d1<T>(actp, Xp[row * (N + 1) + col]);
-        } else if (row < ti.count && col < p.w[0]) {
-          gout[(size_t)(ti.first + row) * p.ldG + col] = v * kc.sc;
-        }
-      }
-    }
-    cur = nxt;
-    __syncthreads();
-    T* t = Dcur;
-    Dcur = Dnext;
-    Dnext = t;
-  }
+}
+
+// k-steps of the ring fragments of mlp_tile_n: half the full width when every
+// hidden layer of the network is at most 32 wide (NARROW, decided on the host)
+template <int PREC, bool NARROW>
+constexpr int mlp_mkh() {
+  return (NARROW ? kMaxWidth / 2 : kMaxWidth) / Mt<PREC>::KS;
+}
+inline bool mlp_narrow(const MlpParams& p) {
+  for (int l = 1; l < p.n_layers; ++l)
+    if (p.wp[l] > kMaxWidth / 2) return false;
+  return true;
 }
 
 }  // namespace

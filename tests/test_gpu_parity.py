@@ -181,6 +181,28 @@ def test_fused_forward_network_is_bitwise_the_two_kernels(A, precision):
         assert np.array_equal(Ea1, Ea0) and np.array_equal(F1, F0), name
 
 
+@pytest.mark.parametrize("hidden", [(), (9,), (9, 7, 5), (40, 7), (9, 40, 33)])
+def test_network_shapes(A, orc, hidden):
+    """Every network depth (1..4 weight layers) and hidden widths on both
+    sides of 32 (the network tile keeps narrower operand fragments when all
+    hidden layers are at most 32 wide) against the oracle, through the fused
+    kernel and through the separate network kernel, whose results agree
+    bitwise."""
+    m = small_model(nr=5, na=3, rr=4.5, ra=3.5, hidden=hidden)
+    s = I.make_system("water64")
+    E0, Ea0, F0 = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    out = []
+    for fused in (True, False):
+        ctx = A.Context(m, "fp64")
+        ctx.set_fused(fused)
+        E, Ea, F = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
+        ctx.close()
+        assert abs(E - E0) / abs(E0) <= 1e-10, (hidden, fused)
+        assert rel_rmse(F, F0) <= 1e-10, (hidden, fused)
+        out.append((E, Ea, F))
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][2], out[1][2]), hidden
+
+
 def test_nonfinite_device_input(A):
     """A NaN in device-resident positions is reported, not computed with."""
     import torch
