@@ -98,7 +98,6 @@ __device__ inline void len_inv<float>(float r2, float* r, float* ir) {
   *r = r2 * y;
 }
 
-
 // Taylor coefficient of t^n in sin t (n odd) or cos t (n even): +-1/n!
 constexpr double taylor_sc(int n) {
   double f = 1.0;

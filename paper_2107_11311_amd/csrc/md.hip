@@ -93,7 +93,7 @@ __device__ inline void bin_wave(const DriftArgs& d, bool mine, int i, const doub
 //
 // The kernel is a chain of dependent memory accesses, so everything it reads
 // is requested before anything is written: the atom's state (lanes 0..2 of
-// its group hold component 0..2), the first kPre listed slots of every lane
+// its group hold component 0..2), the first kGatherPre listed slots of every lane
 // (in bounds whatever the count, a row has cap slots) and the box.  The
 // count then only masks.
 constexpr int kGatherLanes = 16;  // lanes per atom in the force gather
