@@ -66,6 +66,7 @@ def lib():
         L.orc_neighbors.argtypes = [C.c_int, dp, dp, ip, C.c_double, C.c_int, ip, ip, ip]
         L.orc_descriptors.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp]
         L.orc_energy_forces.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp, dp, dp, dp]
+        L.orc_energy_forces_virial.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp, dp, dp, dp, dp]
         L.orc_forces_dense.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, dp]
         L.orc_energy_forces_subset.argtypes = [C.POINTER(_Model), C.c_int, dp, ip, dp, ip, C.c_int, ip,
                                                dp, dp, dp]
@@ -241,6 +242,23 @@ def energy_forces(model, pos, species, box, pbc, want_G=False):
     if want_G:
         return E.value, Ea, F, G
     return E.value, Ea, F
+
+
+def energy_forces_virial(model, pos, species, box, pbc):
+    """(E_total, F [n,3], W [3,3]): the virial W_ab = -dE/d eps_ab under the
+    homogeneous strain r -> (1 + eps) r, by the chain rule over every
+    neighbour entry's gradient (the definition the strain derivative of the
+    energy reduces to for a function of the entries' displacement vectors)."""
+    pos, box, pbc = _geom(pos, box, pbc)
+    sp = _i32(species)
+    pk = _Packed(model)
+    n = pos.shape[0]
+    E = C.c_double()
+    F = np.zeros((n, 3))
+    W = np.zeros((3, 3))
+    _check(lib().orc_energy_forces_virial(pk.ptr, n, _dp(pos), _ip(sp), _dp(box), _ip(pbc), C.byref(E),
+                                          None, _dp(F), None, _dp(W)))
+    return E.value, F, W
 
 
 def energy_forces_subset(model, pos, species, box, pbc, sel):

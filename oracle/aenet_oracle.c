@@ -19,6 +19,9 @@
  *   - angular Chebyshev coefficients c^triple_alpha           Sec. II B, Eq. 6
  *   - training cost / back-propagated gradients               Sec. II C, Eq. 7
  *   - the MD cycle (coordinates -> E, F -> new coordinates)   Sec. III, Fig. 1
+ *   - the virial (stress tensor of the whole system, which    Sec. III
+ *     the earlier LAMMPS interface provides): minus the strain
+ *     derivative of E, by the chain rule over the entries
  *
  * Readings where the paper is silent or loose (each also listed in the design
  * notes of the repository):
@@ -431,9 +434,11 @@ static void ks_add(ksum* k, double x) {
 static double ks_val(const ksum* k) { return k->s + k->c; }
 
 /* Adds -dE_i/dr to forces for atom i, given g = dE_i/dG_i and its entries. */
+/* F += the forces of E_i; if vir != NULL, vir[3a+b] -= (dE_i/dd)_a d_b over
+ * every entry's gradient (the virial W = -dE/d(strain)). */
 static void atom_forces(const orc_model* m, const layout* L, int i, const entry* e, int ne,
                         const int* species, const double* g, double* T, double* dT,
-                        double* F) {
+                        double* F, double* vir) {
   const double Rr = m->radial_cutoff, Ra = m->angular_cutoff;
   for (int p = 0; p < ne; ++p) {
     if (!(e[p].r < Rr)) continue;
@@ -450,6 +455,8 @@ static void atom_forces(const orc_model* m, const layout* L, int i, const entry*
       double v = dEdr * e[p].d[c] / e[p].r; /* dE_i/dd */
       F[3 * i + c] += v;
       F[3 * e[p].j + c] -= v;
+      if (vir)
+        for (int b = 0; b < 3; ++b) vir[3 * c + b] -= v * e[p].d[b];
     }
   }
   for (int p = 0; p < ne; ++p) {
@@ -477,6 +484,8 @@ static void atom_forces(const orc_model* m, const layout* L, int i, const entry*
         F[3 * i + c] += vj + vk;
         F[3 * e[p].j + c] -= vj;
         F[3 * e[q].j + c] -= vk;
+        if (vir)
+          for (int b = 0; b < 3; ++b) vir[3 * c + b] -= vj * e[p].d[b] + vk * e[q].d[b];
       }
     }
   }
@@ -544,6 +553,12 @@ int orc_descriptors(const orc_model* m, int n, const double* pos, const int* spe
 int orc_energy_forces(const orc_model* m, int n, const double* pos, const int* species,
                       const double* box, const int* pbc, double* e_total, double* e_atom,
                       double* forces, double* Gout) {
+  return orc_energy_forces_virial(m, n, pos, species, box, pbc, e_total, e_atom, forces, Gout, NULL);
+}
+
+int orc_energy_forces_virial(const orc_model* m, int n, const double* pos, const int* species,
+                             const double* box, const int* pbc, double* e_total, double* e_atom,
+                             double* forces, double* Gout, double* virial) {
   int st = check_model(m);
   if (st) return st;
   if ((st = check_species(m, n, species))) return st;
@@ -551,6 +566,13 @@ int orc_energy_forces(const orc_model* m, int n, const double* pos, const int* s
   st = work_init(m, n, pos, box, pbc, &w);
   if (st) { work_free(m, &w); return st; }
   layout L = make_layout(m);
+  double* fbuf = NULL;
+  if (virial && !forces) {
+    fbuf = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!fbuf) { work_free(m, &w); return ORC_E_NOMEM; }
+    forces = fbuf;
+  }
+  if (virial) for (int k = 0; k < 9; ++k) virial[k] = 0.0;
   if (forces) for (int k = 0; k < 3 * n; ++k) forces[k] = 0.0;
   ksum E = {0.0, 0.0};
   for (int i = 0; i < n; ++i) {
@@ -564,10 +586,11 @@ int orc_energy_forces(const orc_model* m, int n, const double* pos, const int* s
     ks_add(&E, Ei);
     if (forces) {
       net_backward(net, w.ws.xs, w.ws.b1, w.ws.b2, w.g);
-      atom_forces(m, &L, i, e, ne, species, w.g, w.T, w.dT, forces);
+      atom_forces(m, &L, i, e, ne, species, w.g, w.T, w.dT, forces, virial);
     }
   }
   if (e_total) *e_total = ks_val(&E);
+  free(fbuf);
   work_free(m, &w);
   return ORC_OK;
 }
@@ -680,7 +703,7 @@ int orc_energy_forces_subset(const orc_model* m, int n, const double* pos, const
       const orc_net* net = &m->nets[species[i]];
       double Ei = net_forward(net, G, ws.xs);
       net_backward(net, ws.xs, ws.b1, ws.b2, g);
-      atom_forces(m, &L, i, ei, ni, species, g, T, dT, F);
+      atom_forces(m, &L, i, ei, ni, species, g, T, dT, F, NULL);
       if (i == mi) {
         if (e_sel) e_sel[q] = Ei;
         if (g_sel) memcpy(g_sel + (size_t)q * L.D, G, sizeof(double) * (size_t)L.D);

@@ -81,6 +81,15 @@ int orc_energy_forces(const orc_model* m, int n, const double* pos, const int* s
                       const double* box, const int* pbc, double* e_total, double* e_atom,
                       double* forces, double* G);
 
+/* The same and the virial W [3 x 3] (row-major, eV): W_ab = -dE/d eps_ab for
+ * the homogeneous strain r -> (1 + eps) r of positions and box, i.e.
+ * W_ab = -sum_i sum_e (dE_i/dd_e)_a (d_e)_b over every neighbour entry e of
+ * every atom i (d_e = r_j + image shift - r_i); the pressure of the
+ * configuration is (N k T + tr W / 3) / V.  virial may be NULL. */
+int orc_energy_forces_virial(const orc_model* m, int n, const double* pos, const int* species,
+                             const double* box, const int* pbc, double* e_total, double* e_atom,
+                             double* forces, double* G, double* virial);
+
 /* E_m, F_m (and G_m if g_sel != NULL) of the n_sel atoms listed in sel only,
  * for structures too large for a full evaluation; e_sel [n_sel], f_sel
  * [n_sel x 3], g_sel [n_sel x D]. */

@@ -399,3 +399,55 @@ def test_subset_evaluation_equals_full(orc, water_small):
     E, Ea, F = orc.energy_forces(m2, s2.pos, s2.species, s2.box, s2.pbc)
     Es, Fs, _ = orc.energy_forces_subset(m2, s2.pos, s2.species, s2.box, s2.pbc, np.arange(len(s2.pos)))
     np.testing.assert_allclose(Fs, F, rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------------------------- virial
+def _strained_energy(orc, m, pos, sp, box, pbc, eps):
+    """E of the configuration under the homogeneous strain r -> (1 + eps) r
+    (positions, and the box lengths of an orthorhombic box for diagonal eps)."""
+    T = np.eye(3) + eps
+    return orc.energy_forces(m, pos @ T.T, sp, box * np.diag(T), pbc)[0]
+
+
+def test_virial_is_minus_strain_derivative_open_cluster(orc):
+    """W_ab = -dE/d eps_ab for every component (central differences under
+    shear and stretch of an open cluster), W = sum_i F_i r_i^T (the classical
+    form, exact for a non-periodic system), and W is symmetric (rotational
+    invariance of E)."""
+    m = normalised(tiny_model(S=2, nr=5, rr=4.5, na=3, ra=3.5, hidden=(6, 5)), 31)
+    pos = I.rsa(24, 7.0, 1.4, 9) + 40.0
+    sp = (np.arange(24) % 2).astype(np.int32)
+    E, F, W = orc.energy_forces_virial(m, pos, sp, BIG, OPEN)
+    h = 1e-5
+    Wfd = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = h
+            Wfd[a, b] = -(_strained_energy(orc, m, pos, sp, BIG, OPEN, e)
+                          - _strained_energy(orc, m, pos, sp, BIG, OPEN, -e)) / (2 * h)
+    scale = np.abs(W).max()
+    assert scale > 1e-3
+    np.testing.assert_allclose(W, Wfd, atol=1e-7 * max(scale, 1.0))
+    np.testing.assert_allclose(W, F.T @ pos, atol=1e-10 * max(scale, 1.0))
+    np.testing.assert_allclose(W, W.T, atol=1e-10 * max(scale, 1.0))
+
+
+def test_virial_periodic_stretch(orc):
+    """In a periodic box the diagonal of W is minus the derivative of E under
+    stretching one axis (box length and coordinates together), the off-diagonal
+    part is symmetric, and forces alone do not give W (images)."""
+    m = normalised(tiny_model(S=2, nr=5, rr=4.0, na=3, ra=3.0, hidden=(6,)), 33)
+    s = I.make_system("water64")
+    E, F, W = orc.energy_forces_virial(m, s.pos, s.species, s.box, s.pbc)
+    h = 1e-6
+    scale = max(np.abs(W).max(), 1.0)
+    for a in range(3):
+        e = np.zeros((3, 3))
+        e[a, a] = h
+        wfd = -(_strained_energy(orc, m, s.pos, s.species, s.box, s.pbc, e)
+                - _strained_energy(orc, m, s.pos, s.species, s.box, s.pbc, -e)) / (2 * h)
+        assert abs(W[a, a] - wfd) <= 1e-6 * scale, (a, W[a, a], wfd)
+    np.testing.assert_allclose(W, W.T, atol=1e-10 * scale)
+    E2, _, _ = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
+    assert E == E2
