@@ -7,14 +7,17 @@ back-propagation and gather, integration) over the water4096 workload:
 4096 H2O (12,288 atoms, rigid-geometry molecules placed at random) at 1.0 g/cm^3, radial order 16 within
 6.5 A, angular order 8 within 4.0 A (D = 52), 52-25-25-1 tanh networks,
 dt = 0.25 fs, skin 0.5 A.  Inputs are seeded and synthetic (the paper's
-trained water potential is not available): Maxwell-Boltzmann velocities at
-300 K, then an untimed equilibration under the model with the velocities
-rescaled to 300 K every 20 steps, after which the NVE run is timed.
+trained water potential is not available).  The timed NVE run starts from
+Maxwell-Boltzmann velocities at 300 K (the specified start); an extra FP64
+pass starts from a state equilibrated under the model (velocities rescaled to
+300 K every 20 steps, untimed) and is reported beside it.
 
 Prints one JSON line: atom-steps/s of the FP64 path (value), the FP32 and BF16
-network modes beside it, force RMSE against the FP64 oracle on the final
-positions, the roofline position of the dominant kernel (timed with HIP events
-on the launch stream) and the oracle's own throughput on the host.
+network modes and the equilibrated start beside it, force RMSE against the
+FP64 oracle on the final positions, the roofline position of the dominant
+kernel (timed with HIP events on the launch stream), the oracle's own
+throughput on the host, and the virial entry point's cost and its error
+against the oracle.
 """
 import argparse
 import hashlib
@@ -284,6 +287,26 @@ def run_student(args):
     print(json.dumps(line))
 
 
+def virial_timing(A, model, sysm, reps=30):
+    """The virial entry point (energy, forces and the virial tensor of the
+    configuration, host buffers in and out) against the plain energy+force
+    entry point on the same positions: ms per call of each and the tensor."""
+    ctx = A.Context(model, "fp64")
+    args = (sysm.pos, sysm.species, sysm.box, sysm.pbc)
+    for _ in range(3):
+        ctx.energy_forces(*args)
+        ctx.energy_forces_virial(*args)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.energy_forces(*args)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        _, _, W = ctx.energy_forces_virial(*args)
+    t2 = time.perf_counter()
+    ctx.close()
+    return dict(ms_per_call=1e3 * (t2 - t1) / reps, ms_per_call_forces_only=1e3 * (t1 - t0) / reps, W=W)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +378,7 @@ def main():
                                             profile=False)
     main_mode = "fp64" if "fp64" in res else modes[0]
     r = res[main_mode]
+    vir = virial_timing(A, model, sysm) if "fp64" in modes else None
 
     # roofline of the dominant kernel of the FP64 path
     roofline = None
@@ -410,6 +434,16 @@ def main():
     else:
         for m in res:
             modes_out[m] = dict(atom_steps_per_s=res[m]["atom_steps_per_s"], ms_per_step=res[m]["ms_per_step"])
+    virial = None
+    if vir is not None:
+        virial = dict(ms_per_call=vir["ms_per_call"], ms_per_call_forces_only=vir["ms_per_call_forces_only"],
+                      W_eV=vir["W"].tolist(),
+                      note="aenet_energy_forces_virial vs aenet_energy_forces, host buffers in and out, "
+                           "water4096 initial positions, FP64")
+        if not args.no_cpu_baseline:
+            import oracle
+            _, _, W0 = oracle.energy_forces_virial(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
+            virial["max_rel_err_vs_oracle"] = float(np.abs(vir["W"] - W0).max() / np.abs(W0).max())
 
     line = {
         "metric": "atom-steps/s (energy+forces) on 1 MI355X; force RMSE vs FP64 oracle",
@@ -432,6 +466,7 @@ def main():
         "modes": modes_out,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "virial": virial,
     }
     print(json.dumps(line))
 

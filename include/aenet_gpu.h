@@ -142,6 +142,20 @@ aenet_status aenet_energy_forces(aenet_ctx* ctx, int64_t n, const double* pos,
                                  const uint8_t pbc[3], double* e_total, double* e_atom,
                                  double* forces);
 
+/* The same (host buffers) and the virial of the configuration, the stress
+ * tensor of the whole system that the paper's earlier LAMMPS interface
+ * provides (Sec. III): virial[3a+b] = W_ab = -dE/d eps_ab under the
+ * homogeneous strain r -> (1 + eps) r of positions and box, formed as
+ * -sum_i sum_e (dE_i/dd_e)_a (d_e)_b over every neighbour entry e of every
+ * atom i (d_e = r_j + image shift - r_i), in eV; the pressure is
+ * (N k T + (W_xx + W_yy + W_zz) / 3) / V.  Summed in a fixed order
+ * (deterministic).  virial (9 doubles, row-major) must not be NULL; forces
+ * may be NULL. */
+aenet_status aenet_energy_forces_virial(aenet_ctx* ctx, int64_t n, const double* pos,
+                                        const int32_t* species, const double box[3],
+                                        const uint8_t pbc[3], double* e_total, double* forces,
+                                        double virial[9]);
+
 /* Same with device pointers (pos, e_total[1], e_atom, forces) and a stream. */
 aenet_status aenet_energy_forces_dev(aenet_ctx* ctx, int64_t n, const double* pos,
                                      const int32_t* species, const double box[3],

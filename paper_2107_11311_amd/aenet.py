@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "AENET_OK", -1: "AENET_E_INVALID", -2: "AENET_E_SPECIES", -3:
 # every entry point declared in include/aenet_gpu.h
 EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor_dim", "aenet_n_params",
            "aenet_get_params", "aenet_set_params", "aenet_supported_orders", "aenet_energy_forces",
-           "aenet_energy_forces_dev", "aenet_energy_forces_batch_dev", "aenet_descriptors",
+           "aenet_energy_forces_virial", "aenet_energy_forces_dev", "aenet_energy_forces_batch_dev", "aenet_descriptors",
            "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_get_stats",
            "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_profiling", "aenet_get_kernel_times"]
 KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate", "fwd_network"]
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     L.aenet_set_params.argtypes = [ctxp, _dp]
     L.aenet_supported_orders.argtypes = [_ip, C.c_int]
     L.aenet_energy_forces.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp, _dp, _dp]
+    L.aenet_energy_forces_virial.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp, _dp, _dp]
     L.aenet_energy_forces_dev.argtypes = [ctxp, C.c_int64, _vp, _ip, _dp, _u8p, _vp, _vp, _vp, _vp]
     L.aenet_energy_forces_batch_dev.argtypes = [ctxp, C.c_int, _i64p, _vp, _ip, _dp, _u8p, _vp, _vp,
                                                 _vp, _vp]
@@ -268,6 +269,19 @@ class Context:
         self._check(self._lib.aenet_energy_forces(self._h, n, _ptr(pos), _ptr(sp, _ip), _ptr(box),
                                                   _ptr(pbc, _u8p), C.byref(e), _ptr(ea), _ptr(F)))
         return e.value, ea, F
+
+    def energy_forces_virial(self, pos, species, box, pbc=(1, 1, 1)):
+        """aenet_energy_forces_virial: (E_total, F [n,3], W [3,3]) from host arrays."""
+        pos = _f64(pos).reshape(-1, 3)
+        sp = _i32(species)
+        box, pbc = _box(box, pbc)
+        n = pos.shape[0]
+        e = C.c_double()
+        F = np.zeros((n, 3))
+        W = np.zeros((3, 3))
+        self._check(self._lib.aenet_energy_forces_virial(self._h, n, _ptr(pos), _ptr(sp, _ip), _ptr(box),
+                                                         _ptr(pbc, _u8p), C.byref(e), _ptr(F), _ptr(W)))
+        return e.value, F, W
 
     def descriptors(self, pos, species, box, pbc=(1, 1, 1)):
         pos = _f64(pos).reshape(-1, 3)

@@ -145,6 +145,8 @@ struct DescParams {
   void* pg;              // [n*cap*3] dE_i/dd_e, stored at the slot of the
                          // reverse entry: pg[rev(i,e)] (see the force gather)
   double* Fself;         // [n*3]  sum_e dE_i/dd_e
+  double* vir;           // [9][n] per-atom virial -sum_e (dE_i/dd_e)_a (d_e)_b
+                         // (component 3a+b at vir[(3a+b) n + i]); NULL: none
   const double* adj;     // [n*3] JVP direction (loss adjoint of the forces)
   void* U;               // [n x ldG] JVP output
   int* flags;

@@ -50,7 +50,9 @@ __host__ __device__ constexpr size_t bwd_coef_offset(int ca) {
 //     registers of the lane that owns k, so no atomics are needed;
 //   radial terms, one entry per lane per iteration, adding the angular
 //     gradient of the entry and writing pg.
-template <typename R, int NR, int NA>
+// VIR: also the atom's virial -sum_e (dE_i/dd_e) d_e^T (a separate
+// instance, so that the force pass of MD keeps its registers).
+template <typename R, int NR, int NA, bool VIR>
 __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   // one wavefront per block and atom; the launch covers exactly the n atoms,
@@ -241,6 +243,7 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   int* rev = p.rev + (size_t)i * p.cap;
   const int n_slots = p.n * p.cap;
   double sx = 0.0, sy = 0.0, sz = 0.0;
+  double w9[VIR ? 9 : 1] = {};
   // The reverse slot of entry e: on first use after a per-cell row build rev
   // holds (rank, stencil cell k) and the reverse entry (q -> i) is the rank-th
   // entry of the segment of stencil cell 26 - k in q's row part; resolved once
@@ -324,6 +327,13 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
       sx += (double)px;
       sy += (double)py;
       sz += (double)pz;
+      if constexpr (VIR) {
+        const double g3[3] = {(double)px, (double)py, (double)pz}, d3[3] = {d0, d1, d2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) w9[3 * a + c] -= g3[a] * d3[c];
+      }
     }
   }
   // The other entries (the skin shell) store nothing: no gather reads their
@@ -332,6 +342,13 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   sx = group_sum<64>(sx);
   sy = group_sum<64>(sy);
   sz = group_sum<64>(sz);
+  if constexpr (VIR) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double v = group_sum<64>(w9[k]);
+      if (l == 0) p.vir[(size_t)k * p.n + i] = v;
+    }
+  }
   if (l == 0) {
     p.Fself[3 * (size_t)i] = sx;
     p.Fself[3 * (size_t)i + 1] = sy;
@@ -554,7 +571,10 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
 template <typename R, int NR, int NA>
 void launch_bwd(const DescParams& p, hipStream_t s) {
   const size_t per_atom = (bwd_coef_offset<R>(p.cap_ang) + (size_t)p.n_species * (NR + 1)) * sizeof(R);
-  hipLaunchKernelGGL((k_desc_bwd<R, NR, NA>), dim3(p.n), dim3(64), per_atom, s, p);
+  if (p.vir)
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true>), dim3(p.n), dim3(64), per_atom, s, p);
+  else
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false>), dim3(p.n), dim3(64), per_atom, s, p);
 }
 
 template <typename R, int NR, int NA>

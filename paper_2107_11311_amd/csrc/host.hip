@@ -89,6 +89,8 @@ struct aenet_ctx {
   DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_segs, d_nnb, d_nang, d_rev;
   DevMem d_bin_count, d_bin_atoms;  // MD: cell bins filled by the integrator
   DevMem d_ridx, d_nrad;            // contributing entries, from the forward pass
+  DevMem d_vir;                     // [9][n] per-atom virial, then its 9 sums
+  bool want_vir = false;            // the next force pass also forms the virial
   DevMem d_build;  // [2] ints: decision of the current build, block counter
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
@@ -512,6 +514,7 @@ DescParams desc_params(aenet_ctx* c) {
   p.nrad = c->d_nrad.as<int>();
   p.pg = c->d_pg.p;
   p.Fself = c->d_Fself.as<double>();
+  p.vir = c->want_vir ? c->d_vir.as<double>() : nullptr;
   p.adj = c->d_adj.as<double>();
   p.U = c->d_U.p;
   p.flags = c->d_flags.as<int>();
@@ -706,22 +709,31 @@ aenet_status check_ctx(aenet_ctx* c) {
 }
 
 // energies/forces of a batch whose positions are on the device in caller order
+// virial (device, 9 doubles, or NULL): the virial of the whole batch
 aenet_status ef_core(aenet_ctx* c, int n_struct, const int64_t* offsets, const double* pos,
                      const int32_t* species, const double* boxes, const uint8_t* pbc,
                      double* e_struct, double* e_total, double* e_atom, double* forces,
-                     hipStream_t s) {
+                     hipStream_t s, double* virial = nullptr) {
   TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos));
   const int n = (int)c->n;
   if (n == 0) {
     if (e_total) HIP_TRY(c, hipMemsetAsync(e_total, 0, 8, s));
     if (e_struct) HIP_TRY(c, hipMemsetAsync(e_struct, 0, 8 * (size_t)n_struct, s));
+    if (virial) HIP_TRY(c, hipMemsetAsync(virial, 0, 9 * 8, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     return AENET_OK;
   }
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
   launch_gather_in(n, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
   TRY(build_checked(c, s));
-  TRY(compute(c, s, forces != nullptr, nullptr, 0.0));
+  if (virial) TRY(ensure(c, c->d_vir, (size_t)9 * n * 8));
+  c->want_vir = virial != nullptr;
+  const aenet_status st = compute(c, s, forces != nullptr || virial != nullptr, nullptr, 0.0);
+  c->want_vir = false;
+  TRY(st);
+  if (virial)
+    for (int k = 0; k < 9; ++k)
+      launch_sum(n, c->d_vir.as<double>() + (size_t)k * n, c->d_red.as<double>(), virial + k, s);
   launch_scatter_out(n, c->d_perm.as<int>(), c->d_F.as<double>(), forces, c->d_E.as<double>(),
                      c->d_Eorig.as<double>(), s);
   if (e_atom) HIP_TRY(c, hipMemcpyAsync(e_atom, c->d_Eorig.p, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
@@ -944,10 +956,10 @@ aenet_status aenet_energy_forces_batch_dev(aenet_ctx* c, int n_struct, const int
                  pick_stream(c, stream));
 }
 
-aenet_status aenet_energy_forces(aenet_ctx* c, int64_t n, const double* pos,
-                                 const int32_t* species, const double box[3],
-                                 const uint8_t pbc[3], double* e_total, double* e_atom,
-                                 double* forces) {
+namespace {
+aenet_status ef_host(aenet_ctx* c, int64_t n, const double* pos, const int32_t* species,
+                     const double box[3], const uint8_t pbc[3], double* e_total, double* e_atom,
+                     double* forces, double* virial) {
   TRY(check_ctx(c));
   if (n < 0 || !box || (n > 0 && !pos)) return fail(c, AENET_E_INVALID, "bad arguments");
   for (int64_t k = 0; k < 3 * n; ++k)
@@ -955,21 +967,39 @@ aenet_status aenet_energy_forces(aenet_ctx* c, int64_t n, const double* pos,
   const size_t nb = (size_t)std::max<int64_t>(n, 1);
   TRY(ensure(c, c->h_pos, nb * 24));
   TRY(ensure(c, c->h_F, nb * 24));
-  TRY(ensure(c, c->h_E, (nb + 1) * 8));
+  TRY(ensure(c, c->h_E, (nb + 1 + 9) * 8));
   hipStream_t s = c->stream;
   if (n > 0) HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
   const int64_t off[2] = {0, n};
   double* dE = c->h_E.as<double>();
   TRY(ef_core(c, 1, off, c->h_pos.as<double>(), species, box, pbc, nullptr, dE + nb,
-              e_atom ? dE : nullptr, forces ? c->h_F.as<double>() : nullptr, s));
+              e_atom ? dE : nullptr, forces ? c->h_F.as<double>() : nullptr, s,
+              virial ? dE + nb + 1 : nullptr));
   double et = 0.0;
   HIP_TRY(c, hipMemcpyAsync(&et, dE + nb, 8, hipMemcpyDeviceToHost, s));
+  if (virial) HIP_TRY(c, hipMemcpyAsync(virial, dE + nb + 1, 9 * 8, hipMemcpyDeviceToHost, s));
   if (e_atom && n > 0) HIP_TRY(c, hipMemcpyAsync(e_atom, dE, n * 8, hipMemcpyDeviceToHost, s));
   if (forces && n > 0) HIP_TRY(c, hipMemcpyAsync(forces, c->h_F.p, n * 24, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if (!std::isfinite(et)) return fail(c, AENET_E_NONFINITE, "non-finite energy");
   if (e_total) *e_total = et;
   return AENET_OK;
+}
+}  // namespace
+
+aenet_status aenet_energy_forces(aenet_ctx* c, int64_t n, const double* pos,
+                                 const int32_t* species, const double box[3],
+                                 const uint8_t pbc[3], double* e_total, double* e_atom,
+                                 double* forces) {
+  return ef_host(c, n, pos, species, box, pbc, e_total, e_atom, forces, nullptr);
+}
+
+aenet_status aenet_energy_forces_virial(aenet_ctx* c, int64_t n, const double* pos,
+                                        const int32_t* species, const double box[3],
+                                        const uint8_t pbc[3], double* e_total, double* forces,
+                                        double virial[9]) {
+  if (c && !virial) return fail(c, AENET_E_INVALID, "virial is NULL");
+  return ef_host(c, n, pos, species, box, pbc, e_total, nullptr, forces, virial);
 }
 
 aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const int32_t* species,

@@ -203,6 +203,35 @@ def test_network_shapes(A, orc, hidden):
     assert out[0][0] == out[1][0] and np.array_equal(out[0][2], out[1][2]), hidden
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_virial_matches_oracle(A, orc, precision):
+    """The virial (-dE/d strain, summed over every entry's gradient) of a
+    periodic water box, a three-species open cluster and a small box with
+    many images against the oracle; energy and forces unchanged by asking
+    for it."""
+    g = np.random.default_rng(5)
+    pos = I.rsa(60, 14.0, 1.6, 77) + 30.0
+    sp = g.integers(0, 3, size=60).astype(np.int32)
+    s3 = I.System(pos, sp, np.array([80.0, 80.0, 80.0]), np.zeros(3, dtype=np.uint8))
+    m3 = small_model(S=3, nr=4, na=2, rr=5.0, ra=4.0, tw=(1.0, 2.0, 3.0))
+    cases = [("water64", I.load_model("water64"), I.make_system("water64")), ("cluster3", m3, s3),
+             ("water20", None, I.water_box(20, 920))]
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for name, m, s in cases:
+        if m is None:  # a box smaller than twice the cutoff: entries through many images
+            m = small_model(nr=6, na=2, rr=min(6.5, s.box[0] * 0.99), ra=4.0)
+        E0, F0, W0 = orc.energy_forces_virial(m, s.pos, s.species, s.box, s.pbc)
+        ctx = A.Context(m, precision)
+        E, F, W = ctx.energy_forces_virial(s.pos, s.species, s.box, s.pbc)
+        E1, _, F1 = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
+        ctx.close()
+        scale = np.abs(W0).max()
+        print(f"{name} {precision}: |W| {scale:.3e} max dW {np.abs(W - W0).max():.3e}")
+        assert np.abs(W - W0).max() <= tol * scale, name
+        assert E == E1 and np.array_equal(F, F1), name
+        assert abs(E - E0) <= tol * abs(E0), name
+
+
 def test_nonfinite_device_input(A):
     """A NaN in device-resident positions is reported, not computed with."""
     import torch
