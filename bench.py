@@ -319,6 +319,7 @@ def main():
     ap.add_argument("--cpu-sample-calls", type=int, default=5,
                     help="oracle energy+force calls on the full box for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-virial", action="store_true", help="skip the virial entry point's timing")
     ap.add_argument("--student", action="store_true", help="run the distilled-student pipeline instead")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes 20 times (the reference "
@@ -378,7 +379,7 @@ def main():
                                             profile=False)
     main_mode = "fp64" if "fp64" in res else modes[0]
     r = res[main_mode]
-    vir = virial_timing(A, model, sysm) if "fp64" in modes else None
+    vir = virial_timing(A, model, sysm) if "fp64" in modes and not args.no_virial else None
 
     # roofline of the dominant kernel of the FP64 path
     roofline = None

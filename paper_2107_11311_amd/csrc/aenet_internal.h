@@ -254,6 +254,9 @@ void launch_vv_drift(int n, double* vel, const double* F, const double* inv_mass
 // deterministic sums: out[0] = sum x ; partials has >= reduce_blocks(n) doubles
 int reduce_blocks(int64_t n);
 void launch_sum(int64_t n, const double* x, double* partials, double* out, hipStream_t s);
+// rows independent sums of x [rows][n] into out[rows]; partials has >= rows *
+// reduce_blocks(n) doubles; each row summed as launch_sum sums it
+void launch_sum_rows(int rows, int64_t n, const double* x, double* partials, double* out, hipStream_t s);
 void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
                     hipStream_t s);
 void launch_segment_sum(int n_seg, const int64_t* seg_off, const double* x, double* out,

@@ -726,14 +726,15 @@ aenet_status ef_core(aenet_ctx* c, int n_struct, const int64_t* offsets, const d
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
   launch_gather_in(n, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
   TRY(build_checked(c, s));
-  if (virial) TRY(ensure(c, c->d_vir, (size_t)9 * n * 8));
+  if (virial) {
+    TRY(ensure(c, c->d_vir, (size_t)9 * n * 8));
+    TRY(ensure(c, c->d_red, (size_t)(9 * reduce_blocks(n) + 1) * 8));
+  }
   c->want_vir = virial != nullptr;
   const aenet_status st = compute(c, s, forces != nullptr || virial != nullptr, nullptr, 0.0);
   c->want_vir = false;
   TRY(st);
-  if (virial)
-    for (int k = 0; k < 9; ++k)
-      launch_sum(n, c->d_vir.as<double>() + (size_t)k * n, c->d_red.as<double>(), virial + k, s);
+  if (virial) launch_sum_rows(9, n, c->d_vir.as<double>(), c->d_red.as<double>(), virial, s);
   launch_scatter_out(n, c->d_perm.as<int>(), c->d_F.as<double>(), forces, c->d_E.as<double>(),
                      c->d_Eorig.as<double>(), s);
   if (e_atom) HIP_TRY(c, hipMemcpyAsync(e_atom, c->d_Eorig.p, (size_t)n * 8, hipMemcpyDeviceToDevice, s));

@@ -239,8 +239,11 @@ __global__ void k_vv_drift(int n, double* vel, const double* F, const double* in
 
 constexpr int kRedChunk = 2048;  // elements per partial sum (fixed: results depend only on n)
 
+// row blockIdx.y of x ([rows][n]) into part[blockIdx.y * gridDim.x + blockIdx.x]
 __global__ __launch_bounds__(256) void k_partial_sum(int64_t n, const double* x, double* part) {
   __shared__ double s[256];
+  x += (size_t)blockIdx.y * n;
+  part += (size_t)blockIdx.y * gridDim.x;
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
   double acc = 0.0;
   for (int k = threadIdx.x; k < kRedChunk; k += 256) {
@@ -256,8 +259,11 @@ __global__ __launch_bounds__(256) void k_partial_sum(int64_t n, const double* x,
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// row blockIdx.x of part ([rows][m]) into out[blockIdx.x]
 __global__ __launch_bounds__(1024) void k_final_sum(int m, const double* part, double* out) {
   __shared__ double s[1024];
+  part += (size_t)blockIdx.x * m;
+  out += blockIdx.x;
   double acc = 0.0;
   for (int k = threadIdx.x; k < m; k += 1024) acc += part[k];
   s[threadIdx.x] = acc;
@@ -374,9 +380,13 @@ void launch_vv_drift(int n, double* vel, const double* F, const double* inv_mass
 int reduce_blocks(int64_t n) { return (int)((n + kRedChunk - 1) / kRedChunk); }
 
 void launch_sum(int64_t n, const double* x, double* partials, double* out, hipStream_t s) {
+  launch_sum_rows(1, n, x, partials, out, s);
+}
+
+void launch_sum_rows(int rows, int64_t n, const double* x, double* partials, double* out, hipStream_t s) {
   const int m = reduce_blocks(n);
-  if (m > 0) hipLaunchKernelGGL(k_partial_sum, dim3(m), dim3(256), 0, s, n, x, partials);
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(1024), 0, s, m, partials, out);
+  if (m > 0) hipLaunchKernelGGL(k_partial_sum, dim3(m, rows), dim3(256), 0, s, n, x, partials);
+  hipLaunchKernelGGL(k_final_sum, dim3(rows), dim3(1024), 0, s, m, partials, out);
 }
 
 void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
