@@ -193,3 +193,24 @@ def test_loss_grad_full_batch_is_mean_of_structures(A, orc, torch_dev):
                                fr[a:b], 1.0)
         assert abs(Lk - L0) <= 1e-10 * abs(L0)
         assert float(np.abs(gk - g0).max()) <= 1e-9 * float(np.abs(g0).max())
+
+
+# ---------------------------------------------------------------- L-BFGS training (Sec. II C)
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_lbfgs_fit(A, orc, torch_dev, small_batch, lam):
+    """Full-batch L-BFGS on the library's cost (energy only, the objective of
+    Eq. 7, and energy+force): its first evaluation is the oracle's cost, and
+    the optimiser lowers it by an order of magnitude within 40 iterations."""
+    from paper_2107_11311_amd import train
+    m, boxes, offs, pos, sp, bx, er, fr = small_batch
+    ctx = A.Context(m, "fp64")
+    L0, _ = orc.loss_grad(m, offs, pos, sp, bx, (1, 1, 1), er, fr, lam)
+    r = train.fit_lbfgs(ctx, offs, pos, sp, bx, (1, 1, 1), er, fr if lam > 0 else None, lambda_f=lam,
+                        maxiter=40)
+    print(f"lambda_f={lam}: loss {r.loss0:.4e} -> {r.loss:.4e} in {r.iterations} iterations, "
+          f"{r.evaluations} evaluations, {1e3 * r.seconds / max(r.evaluations, 1):.2f} ms each; "
+          f"|grad| {r.grad_norm0:.3e} -> {r.grad_norm:.3e}")
+    assert abs(r.loss0 - L0) <= 1e-10 * abs(L0)
+    assert r.loss <= 0.1 * r.loss0
+    assert np.array_equal(ctx.get_params(), r.params)
+    ctx.close()
