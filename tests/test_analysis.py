@@ -1,0 +1,50 @@
+"""Diffusion analysis (Eqs. 8 and 9): a random walk of known diffusion
+coefficient, wrapped into a periodic box, recovered through unwrapping and
+the MSD slope; the finite-size correction and the 1/L extrapolation against
+closed forms."""
+import numpy as np
+
+from paper_2107_11311_amd import analysis as AN
+
+
+def test_random_walk_recovers_diffusion_coefficient():
+    rng = np.random.default_rng(4)
+    D, dt, T, N = 0.23, 0.05, 400, 500          # A^2/ps, ps, frames, walkers
+    steps = rng.normal(scale=np.sqrt(2 * D * dt), size=(T - 1, N, 3))
+    x0 = rng.uniform(0, 20.0, size=(N, 3))
+    traj = np.concatenate([x0[None], x0 + np.cumsum(steps, axis=0)])
+    box = np.array([20.0, 20.0, 20.0])
+    wrapped = traj - box * np.floor(traj / box)
+    un = AN.unwrap(wrapped, box)
+    np.testing.assert_allclose(un, traj, atol=1e-9)
+    m = AN.msd(un, max_lag=100)
+    assert m[0] == 0.0
+    d = AN.diffusion_coefficient(m, dt)
+    assert abs(d - D) / D < 0.05, d
+    # an open axis is not unwrapped
+    un2 = AN.unwrap(traj, box, pbc=(1, 1, 0))
+    np.testing.assert_allclose(un2, traj, atol=1e-9)
+
+
+def test_msd_of_ballistic_motion():
+    """Uniform motion r = r0 + v t: MSD(k) = |v|^2 (k dt)^2 exactly."""
+    v = np.array([0.3, -0.2, 0.1])
+    t = np.arange(50) * 0.1
+    traj = np.zeros((50, 3, 3)) + t[:, None, None] * v
+    m = AN.msd(traj)
+    np.testing.assert_allclose(m, (v @ v) * (np.arange(50) * 0.1) ** 2, rtol=1e-12, atol=1e-15)
+
+
+def test_finite_size_correction_closed_form():
+    # water near 300 K: eta = 0.89 mPa s, L = 30 A
+    d_inf = AN.finite_size_correction(0.20, 30.0, 300.0, 0.89e-3)
+    corr = 2.837297 * 1.380649e-23 * 300.0 / (6 * np.pi * 0.89e-3 * 30e-10)  # m^2/s
+    assert abs(d_inf - (0.20 + corr * 1e8)) < 1e-12
+    assert 0.02 < corr * 1e8 < 0.03
+
+
+def test_extrapolation_to_infinite_size():
+    L = np.array([12.4, 15.6, 19.7, 24.8, 31.3])
+    d = 0.25 - 0.9 / L
+    d_inf, slope = AN.extrapolate_infinite(L, d)
+    assert abs(d_inf - 0.25) < 1e-12 and abs(slope + 0.9) < 1e-10
