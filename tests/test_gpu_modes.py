@@ -214,3 +214,39 @@ def test_lbfgs_fit(A, orc, torch_dev, small_batch, lam):
     assert r.loss <= 0.1 * r.loss0
     assert np.array_equal(ctx.get_params(), r.params)
     ctx.close()
+
+
+# ---------------------------------------------------------------- NVT (weak coupling)
+def test_nvt_berendsen_matches_oracle_chunks(A, orc, torch_dev):
+    """Velocity-Verlet chunks on the GPU with a Berendsen velocity scale after
+    each chunk against the oracle's velocity Verlet under the same coupling:
+    the temperatures seen, the scale factors and the final state agree, and
+    every scale factor pulls toward the target."""
+    from paper_2107_11311_amd import thermostat as TH
+    torch, dev = torch_dev
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    v0 = I.maxwell_boltzmann(m.masses[s.species], 900.0, 21)
+    dt, chunk, n_chunks, T0, tau = 5e-4, 5, 4, 300.0, 0.01
+    ctx = A.Context(m, "fp64", skin=0.5)
+    pos = torch.from_numpy(s.pos.copy()).to(dev)
+    vel = torch.from_numpy(v0.copy()).to(dev)
+    tr = TH.nvt_berendsen(ctx, pos, vel, s.species, s.box, s.pbc, dt, n_chunks, chunk, T0, tau)
+    ctx.close()
+    p, v = s.pos.copy(), v0.copy()
+    n = len(p)
+    for k in range(n_chunks):
+        p, v, ep, ek, _ = orc.md_vv(m, p, v, s.species, m.masses, s.box, s.pbc, dt, chunk)
+        t_now = 2.0 * ek / (3 * n * TH.KB_EV)
+        lam = TH.berendsen_lambda(t_now, T0, chunk * dt, tau)
+        v = v * lam
+        assert abs(tr.temperatures[k] - t_now) <= 1e-9 * t_now, k
+        assert abs(tr.lambdas[k] - lam) <= 1e-9, k
+    L = np.asarray(s.box)
+    dp = pos.cpu().numpy() - p
+    dp -= L * np.round(dp / L)
+    assert np.abs(dp).max() <= 1e-8
+    np.testing.assert_allclose(vel.cpu().numpy(), v, atol=1e-8 * np.abs(v).max())
+    # every coupling step pulls toward the target (the random-weight network
+    # itself keeps heating the box, so T need not fall)
+    assert all((t > T0) == (lam < 1.0) for t, lam in zip(tr.temperatures, tr.lambdas))
