@@ -117,7 +117,7 @@ def equilibrate(A, model, sysm, vel0, dt, steps, T, chunk=20):
     F = torch.zeros(n, 3, dtype=torch.float64, device=dev)
     for _ in range(max(1, steps // chunk)):
         ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, chunk, ep, ek, F)
-        t_now = 2.0 * ek.item() / (3 * n * KB_EV)
+        t_now = 2.0 * ek.item() / ((3 * n - 3) * KB_EV)
         vel.mul_(float(np.sqrt(T / t_now)))
     out = pos.cpu().numpy(), vel.cpu().numpy()
     ctx.close()
@@ -151,7 +151,7 @@ def run_mode(A, model, sysm, vel0, precision, steps, warmup, dt, profile):
     e1 = (ep + ek).item()
     out = dict(atom_steps_per_s=n * steps / wall, ms_per_step=1e3 * wall / steps,
                gpu_ms_per_step=gpu_ms / steps, e_total_start=e0, e_total_end=e1,
-               t_end=2.0 * ek.item() / (3 * n * KB_EV), rebuilds=ctx.stats()["n_rebuilds"] - rb0)
+               t_end=2.0 * ek.item() / ((3 * n - 3) * KB_EV), rebuilds=ctx.stats()["n_rebuilds"] - rb0)
     if profile:
         # timing pass: the same steps again, every kernel bracketed by HIP events
         ctx.set_profiling(True)

@@ -5,8 +5,10 @@ by lambda = sqrt(1 + (chunk dt / tau) (T0 / T - 1)) with T the kinetic
 temperature at the end of the chunk (Berendsen coupling applied per chunk,
 so the device loop runs undisturbed between couplings).
 
-T = 2 E_kin / (3 N k_B) with N the number of atoms (no constraints are
-removed).  Positions and velocities are torch tensors on the device, updated
+T = 2 E_kin / ((3 N - 3) k_B): the centre-of-mass momentum is zero at the
+start (Maxwell-Boltzmann initialisation) and stays zero (forces sum to zero,
+and the scaling keeps it), so 3 of the 3N degrees of freedom carry no kinetic
+energy.  Positions and velocities are torch tensors on the device, updated
 in place; the caller's atom order.
 """
 from dataclasses import dataclass, field
@@ -15,6 +17,11 @@ from typing import List
 import numpy as np
 
 KB_EV = 8.617333262e-5  # Boltzmann constant, eV/K
+
+
+def kinetic_temperature(e_kin: float, n_atoms: int) -> float:
+    """T (K) of n_atoms with zero total momentum and kinetic energy e_kin (eV)."""
+    return 2.0 * e_kin / (max(3 * n_atoms - 3, 1) * KB_EV)
 
 
 def berendsen_lambda(t_now: float, t_target: float, dt_chunk: float, tau: float) -> float:
@@ -38,7 +45,7 @@ def nvt_berendsen(ctx, pos, vel, species, box, pbc, dt_ps: float, n_chunks: int,
     tr = NvtTrace()
     for _ in range(n_chunks):
         ctx.md_step_dev(pos, vel, species, box, pbc, dt_ps, chunk, ep, ek)
-        t_now = 2.0 * ek.item() / (3 * n * KB_EV)
+        t_now = kinetic_temperature(ek.item(), n)
         lam = berendsen_lambda(t_now, t_target, chunk * dt_ps, tau_ps)
         vel.mul_(lam)
         tr.temperatures.append(t_now)

@@ -237,8 +237,11 @@ def test_nvt_berendsen_matches_oracle_chunks(A, orc, torch_dev):
     n = len(p)
     for k in range(n_chunks):
         p, v, ep, ek, _ = orc.md_vv(m, p, v, s.species, m.masses, s.box, s.pbc, dt, chunk)
-        t_now = 2.0 * ek / (3 * n * TH.KB_EV)
-        lam = TH.berendsen_lambda(t_now, T0, chunk * dt, tau)
+        # T with 3N - 3 degrees of freedom (zero total momentum) and the
+        # weak-coupling scale sqrt(1 + (t/tau)(T0/T - 1)) of Berendsen et al.
+        # (1984) over the chunk's time t, written out here
+        t_now = 2.0 * ek / ((3 * n - 3) * 8.617333262e-5)
+        lam = np.sqrt(1.0 + (chunk * dt / tau) * (T0 / t_now - 1.0))
         v = v * lam
         assert abs(tr.temperatures[k] - t_now) <= 1e-9 * t_now, k
         assert abs(tr.lambdas[k] - lam) <= 1e-9, k

@@ -451,3 +451,106 @@ def test_virial_periodic_stretch(orc):
     np.testing.assert_allclose(W, W.T, atol=1e-10 * scale)
     E2, _, _ = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc)
     assert E == E2
+
+
+# ---------------------------------------------------------------- pins of units and network values
+# CODATA: elementary charge (exact since 2019) and the atomic mass constant
+# (CODATA 2018).  1 eV/amu in A^2/ps^2 = e/u * (1e10 A/m)^2 * (1e-12 s/ps)^2.
+E_CHARGE_C = 1.602176634e-19
+AMU_KG = 1.66053906660e-27
+KAPPA_CODATA = E_CHARGE_C / AMU_KG * 1e20 * 1e-24
+
+
+def _dimer_energy_and_force(model, sp, d):
+    """Closed form for two atoms with a one-layer (linear) network and no
+    angular neighbours: E_i = sum_a k_i[a] T_a(2r/R - 1) f_c(r) + b_i with
+    k_i = W_i[typed radial] + w_{t_j} W_i[weighted radial] (Eqs. 1-5).
+    Returns E_total and the force on atom 1 (atom 0 gets its negative);
+    d = r_1 - r_0.  Uses numpy's Chebyshev routines and the cosine."""
+    R = model.radial_cutoff
+    nr = model.radial_order
+    typed = nr + 1 + model.angular_order + 1
+    r = float(np.linalg.norm(d))
+    x = 2.0 * r / R - 1.0
+    fc = 0.5 * (np.cos(np.pi * r / R) + 1.0)
+    dfc = -0.5 * np.pi / R * np.sin(np.pi * r / R)
+    E, dEdr = 0.0, 0.0
+    for i, j in ((0, 1), (1, 0)):
+        W = model.nets[sp[i]].W[0][0]
+        k = W[:nr + 1] + model.type_weight[sp[j]] * W[typed:typed + nr + 1]
+        E += npcheb.chebval(x, k) * fc + model.nets[sp[i]].b[0][0]
+        dEdr += npcheb.chebval(x, npcheb.chebder(k)) * (2.0 / R) * fc + npcheb.chebval(x, k) * dfc
+    return E, -dEdr * d / r
+
+
+def test_velocity_verlet_closed_form_units(orc):
+    """One and three velocity-Verlet steps of a dimer whose forces are known in
+    closed form: r1 = r0 + v0 dt + dt^2 kappa F0 / (2m), v1 = v0 + dt kappa
+    (F0 + F1) / (2m), E_kin = m v^2 / (2 kappa), with kappa (eV/amu in
+    A^2/ps^2) computed here from the CODATA charge and mass unit, and two
+    species of different mass (masses indexed by species)."""
+    assert abs(KAPPA_CODATA - 9648.533) < 1e-3
+    g = np.random.default_rng(8)
+    nr, na = 6, 2
+    typed = nr + 1 + na + 1
+    nets = [I.NetSpec([g.normal(size=(1, 2 * typed))], [g.normal(size=1)], [I.ACT_LINEAR]) for _ in range(2)]
+    m = I.ModelSpec(2, np.array([-1.0, 1.0]), np.array([1.5, 7.0]), nr, 5.0, na, 3.0, nets)
+    sp = np.array([0, 1])
+    mass = m.masses[sp]
+    pos0 = np.array([[20.0, 20.0, 20.0], [22.3, 20.4, 19.1]])
+    vel0 = np.array([[3.0, -1.0, 0.5], [-0.4, 2.0, 1.0]])
+    dt = 2e-3
+
+    def closed_form_step(p, v):
+        _, f1 = _dimer_energy_and_force(m, sp, p[1] - p[0])
+        F = np.array([-f1, f1])
+        vh = v + 0.5 * dt * KAPPA_CODATA * F / mass[:, None]
+        p2 = p + dt * vh
+        E2, f2 = _dimer_energy_and_force(m, sp, p2[1] - p2[0])
+        F2 = np.array([-f2, f2])
+        return p2, vh + 0.5 * dt * KAPPA_CODATA * F2 / mass[:, None], E2, F2
+
+    p, v = pos0.copy(), vel0.copy()
+    for steps in (1, 3):
+        p, v = pos0.copy(), vel0.copy()
+        for _ in range(steps):
+            p, v, E, F = closed_form_step(p, v)
+        ekin = 0.5 * np.sum(mass[:, None] * v * v) / KAPPA_CODATA
+        po, vo, ep, ek, Fo = orc.md_vv(m, pos0, vel0, sp, m.masses, BIG, OPEN, dt, steps)
+        assert np.abs(p - pos0).max() > 1e-3           # the atoms moved
+        assert np.abs(F).max() > 1e-2                  # under a real force
+        np.testing.assert_allclose(po, p, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(vo, v, rtol=0, atol=1e-10 * np.abs(v).max())
+        np.testing.assert_allclose(Fo, F, rtol=0, atol=1e-11 * np.abs(F).max())
+        assert abs(ek - ekin) <= 1e-12 * ekin
+        assert abs(ep - E) <= 1e-12 * max(1.0, abs(E))
+
+
+def test_tanh_network_closed_form_value(orc):
+    """A two-hidden-layer tanh network whose biases are chosen so that the
+    hidden units take prescribed values (b = atanh(h) - W x): the energy is
+    then w3 . h2 + b3 + e_offset exactly, and the input gradient follows from
+    tanh' = 1 - h^2 with the prescribed h (Eq. 1 with tanh hidden layers and a
+    linear output).  A misplaced or missing activation, a transposed weight
+    matrix or a dropped input normalisation changes E."""
+    D = 3
+    G = np.array([0.7, -1.2, 2.5])
+    shift = np.array([0.2, -0.5, 1.0])
+    scale = np.array([2.0, 0.5, 0.25])
+    x0 = (G - shift) * scale                          # (1.0, -0.35, 0.375)
+    W1 = np.array([[0.3, -1.1, 0.8], [1.7, 0.4, -0.6]])
+    h1 = np.array([0.5, -0.25])
+    W2 = np.array([[0.9, -0.3], [-1.4, 2.2]])
+    h2 = np.array([0.6, -0.8])
+    W3 = np.array([[2.0, 3.0]])
+    b1 = np.arctanh(h1) - W1 @ x0
+    b2 = np.arctanh(h2) - W2 @ h1
+    b3 = np.array([0.125])
+    net = I.NetSpec([W1, W2, W3], [b1, b2, b3], [I.ACT_TANH, I.ACT_TANH, I.ACT_LINEAR], shift, scale, -0.5)
+    E, grad = orc.net_eval(net, G)
+    assert abs(E - (2.0 * 0.6 + 3.0 * (-0.8) + 0.125 - 0.5)) <= 1e-14
+    # dE/dG by hand: delta2 = w3 (1 - h2^2) = (2 * 0.64, 3 * 0.36)
+    d2 = np.array([2.0 * 0.64, 3.0 * 0.36])
+    d1 = (W2.T @ d2) * np.array([0.75, 0.9375])
+    np.testing.assert_allclose(grad, (W1.T @ d1) * scale, rtol=0, atol=1e-13)
+    assert D == G.size
