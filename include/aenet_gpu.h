@@ -182,9 +182,15 @@ aenet_status aenet_descriptors(aenet_ctx* ctx, int64_t n, const double* pos,
  * rebuilt when an atom moved more than skin/2 since the last build, and every
  * rebuild_every steps); F = F(r); v += dt/2 F/m.  pos and vel are read at
  * entry and overwritten at exit (positions wrapped into the box on periodic
- * axes); forces at the input positions are computed first.  e_pot/e_kin (may
- * be NULL) receive the final potential and kinetic energy (eV); forces (may be
- * NULL) the final forces.  State lives on the device for the whole call. */
+ * axes).  The forces at the input positions are computed first, unless the
+ * positions are bitwise those this context wrote at the end of its previous
+ * md_step call, with the same species and box and no other call on the
+ * context since that could change them (energy/force, descriptor or training
+ * calls, new parameters or capacities): then the forces and neighbour list of
+ * that call's end are taken over (the velocities are always read, so a
+ * thermostat may rescale them between calls).  e_pot/e_kin (may be NULL)
+ * receive the final potential and kinetic energy (eV); forces (may be NULL)
+ * the final forces.  State lives on the device for the whole call. */
 aenet_status aenet_md_step(aenet_ctx* ctx, int64_t n, double* pos, double* vel,
                            const int32_t* species, const double box[3], const uint8_t pbc[3],
                            double dt_ps, int n_steps, double* e_pot, double* e_kin,

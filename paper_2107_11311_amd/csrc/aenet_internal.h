@@ -223,6 +223,14 @@ void launch_scatter_out(int n, const int* perm, const double* src3, double* dst3
                         const double* src1, double* dst1, hipStream_t s);
 void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
                              const BoxInfo* boxes, const int pbc[3], double* dst, hipStream_t s);
+// *differ |= 1 unless every caller-order position src[perm[p]] equals, bitwise,
+// the wrapped internal position pos[p] (what launch_wrap_scatter_out writes)
+void launch_same_wrapped(int n, const int* perm, const double* pos, const int* seg,
+                         const BoxInfo* boxes, const int pbc[3], const double* src, int* differ,
+                         hipStream_t s);
+// a2 = a, b2 = b, c2 = c (m doubles each), one launch
+void launch_copy3(int64_t m, const double* a, double* a2, const double* b, double* b2,
+                  const double* c, double* c2, hipStream_t s);
 // F_q = Fself_q - sum_{f < nnb[q]} pg[q, f] (pg holds at slot (q, f) the
 // gradient of the entry whose reverse is (q, f)); prec of pg: 0 double,
 // 1 float.  If vel != NULL also v += c*F/m.

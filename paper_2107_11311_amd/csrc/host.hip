@@ -82,6 +82,13 @@ struct aenet_ctx {
   bool fused = true;
   int ang_mean = 0;  // expected mean number of neighbours within R_a (densest structure)
   bool nbr_valid = false;
+  // the cell counters and the build's block counter are zero (what a build
+  // expects; every successful call leaves them so)
+  bool counters_clean = false;
+  // the device holds the end state of the last md_step call: internal
+  // positions, forces at them, the neighbour rows and their reference
+  // positions; anything else that uses the buffers clears it
+  bool md_state = false;
 
   DevMem d_perm, d_species, d_wq, d_seg, d_segoff, d_segcount, d_boxes;
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
@@ -241,7 +248,7 @@ aenet_status pack_networks(aenet_ctx* c) {
 
 // ------------------------------------------------------------------ geometry
 aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const int32_t* species,
-                     const double* boxes, const uint8_t* pbc, const double* pos_dev) {
+                     const double* boxes, const uint8_t* pbc, const double* pos_dev, hipStream_t st) {
   if (n_struct < 1 || !offsets || offsets[0] != 0) return fail(c, AENET_E_INVALID, "bad structure offsets");
   for (int s = 0; s < n_struct; ++s)
     if (offsets[s + 1] < offsets[s]) return fail(c, AENET_E_INVALID, "structure offsets must not decrease");
@@ -281,7 +288,13 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
                      std::equal(offsets, offsets + n_struct + 1, c->offsets_cache.begin()) &&
                      c->species_cache.size() == (size_t)n &&
                      (n == 0 || std::memcmp(species, c->species_cache.data(), n * sizeof(int32_t)) == 0));
-  hipStream_t st = c->stream;
+  // same cell grids as the last call
+  bool box_same = same && c->boxes.size() == (size_t)n_struct && c->d_boxes.p != nullptr;
+  for (int a = 0; a < 3 && box_same; ++a) box_same = c->pbc[a] == pb[a];
+  for (int s = 0; s < n_struct && box_same; ++s)
+    for (int a = 0; a < 3; ++a)
+      box_same = box_same && bx[s].L[a] == c->boxes[s].L[a] && bx[s].nc[a] == c->boxes[s].nc[a];
+  if (!box_same) c->md_state = false;
   if (!same) {
     c->n = n;
     c->n_struct = n_struct;
@@ -360,9 +373,11 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
   for (int a = 0; a < 3; ++a) c->pbc[a] = pb[a];
   c->boxes = bx;
   c->n_cells = (int)cells;
-  TRY(ensure(c, c->d_boxes, n_struct * sizeof(BoxInfo)));
-  HIP_TRY(c, hipMemcpyAsync(c->d_boxes.p, bx.data(), n_struct * sizeof(BoxInfo), hipMemcpyHostToDevice, st));
-  HIP_TRY(c, hipStreamSynchronize(st));
+  if (!box_same) {
+    TRY(ensure(c, c->d_boxes, n_struct * sizeof(BoxInfo)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_boxes.p, c->boxes.data(), n_struct * sizeof(BoxInfo), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+  }
   // per-atom buffers
   const size_t nb = (size_t)std::max<int64_t>(n, 1);
   const size_t el = real_size(c);
@@ -388,16 +403,19 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
   TRY(ensure(c, c->d_nang, nb * 4));
   TRY(ensure(c, c->d_segs, nb * kSegWords * 2));
   TRY(ensure(c, c->d_build, 2 * 4));
-  // the binning kernel expects zero cell counters and block counter (each
-  // build leaves them so for the next one)
-  HIP_TRY(c, hipMemsetAsync(c->d_cell_count.p, 0, (size_t)std::max(cells, (int64_t)1) * 4, st));
-  HIP_TRY(c, hipMemsetAsync(c->d_cell_fill.p, 0, (size_t)std::max(cells, (int64_t)1) * 4, st));
-  HIP_TRY(c, hipMemsetAsync(c->d_build.p, 0, 2 * 4, st));
-  // empty rows until a build writes them (a cell the per-cell row kernel
-  // cannot hold leaves its atoms' rows unwritten until the retry)
-  HIP_TRY(c, hipMemsetAsync(c->d_nnb.p, 0, nb * 4, st));
-  HIP_TRY(c, hipMemsetAsync(c->d_nang.p, 0, nb * 4, st));
-  HIP_TRY(c, hipStreamSynchronize(st));  // before work on the caller's stream
+  if (!box_same || !c->counters_clean) {
+    // the binning kernel expects zero cell counters and block counter (each
+    // build leaves them so for the next one)
+    HIP_TRY(c, hipMemsetAsync(c->d_cell_count.p, 0, (size_t)std::max(cells, (int64_t)1) * 4, st));
+    HIP_TRY(c, hipMemsetAsync(c->d_cell_fill.p, 0, (size_t)std::max(cells, (int64_t)1) * 4, st));
+    HIP_TRY(c, hipMemsetAsync(c->d_build.p, 0, 2 * 4, st));
+    // empty rows until a build writes them (a cell the per-cell row kernel
+    // cannot hold leaves its atoms' rows unwritten until the retry)
+    HIP_TRY(c, hipMemsetAsync(c->d_nnb.p, 0, nb * 4, st));
+    HIP_TRY(c, hipMemsetAsync(c->d_nang.p, 0, nb * 4, st));
+  }
+  // cleared again by a successful end of the call
+  c->counters_clean = false;
   // initial row capacities from the density of the densest structure
   if (c->cap == 0) {
     double est = 0.0, est_a = 0.0;
@@ -714,7 +732,8 @@ aenet_status ef_core(aenet_ctx* c, int n_struct, const int64_t* offsets, const d
                      const int32_t* species, const double* boxes, const uint8_t* pbc,
                      double* e_struct, double* e_total, double* e_atom, double* forces,
                      hipStream_t s, double* virial = nullptr) {
-  TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos));
+  c->md_state = false;
+  TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos, s));
   const int n = (int)c->n;
   if (n == 0) {
     if (e_total) HIP_TRY(c, hipMemsetAsync(e_total, 0, 8, s));
@@ -745,6 +764,7 @@ aenet_status ef_core(aenet_ctx* c, int n_struct, const int64_t* offsets, const d
   int hf[8];
   TRY(read_flags(c, s, hf));
   TRY(flag_status(c, hf[0]));
+  c->counters_clean = true;
   return AENET_OK;
 }
 
@@ -930,6 +950,7 @@ aenet_status aenet_set_params(aenet_ctx* c, const double* params) {
   for (size_t k = 0; k < c->params.size(); ++k)
     if (!std::isfinite(params[k])) return fail(c, AENET_E_NONFINITE, "non-finite parameter");
   std::memcpy(c->params.data(), params, c->params.size() * 8);
+  c->md_state = false;  // the forces kept from the last MD call belong to the old parameters
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return pack_networks(c);
 }
@@ -1014,7 +1035,8 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
     HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, n * 24, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipStreamSynchronize(s));
   }
-  TRY(prepare(c, 1, off, species, box, pbc, n > 0 ? c->h_pos.as<double>() : nullptr));
+  c->md_state = false;
+  TRY(prepare(c, 1, off, species, box, pbc, n > 0 ? c->h_pos.as<double>() : nullptr, s));
   if (n == 0) return AENET_OK;
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
   launch_gather_in((int)n, c->d_perm.as<int>(), c->h_pos.as<double>(), c->d_pos.as<double>(),
@@ -1027,6 +1049,7 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
   std::vector<unsigned char> buf((size_t)n * c->ldG * el);
   HIP_TRY(c, hipMemcpyAsync(buf.data(), c->d_G.p, buf.size(), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  c->counters_clean = true;
   for (int64_t p = 0; p < n; ++p) {
     double* dst = G + (size_t)c->perm[p] * c->D;
     for (int k = 0; k < c->D; ++k)
@@ -1042,45 +1065,84 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   if (!c->have_mass) return fail(c, AENET_E_INVALID, "molecular dynamics needs mass_amu in the model");
   if (!(dt > 0) || n_steps < 0) return fail(c, AENET_E_INVALID, "dt must be > 0 and n_steps >= 0");
   const int64_t off[2] = {0, n};
-  TRY(prepare(c, 1, off, species, box, pbc, pos));
+  // prepare() clears md_state when the species pattern or the box changed
+  TRY(prepare(c, 1, off, species, box, pbc, pos, s));
+  bool resume = c->md_state;
+  c->md_state = false;
   const int N = (int)n;
   if (N == 0) {
     if (e_pot) HIP_TRY(c, hipMemsetAsync(e_pot, 0, 8, s));
     if (e_kin) HIP_TRY(c, hipMemsetAsync(e_kin, 0, 8, s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    c->counters_clean = true;
     return AENET_OK;
   }
   TRY(ensure(c, c->d_save_pos, (size_t)N * 24));
   TRY(ensure(c, c->d_save_vel, (size_t)N * 24));
   TRY(ensure(c, c->d_save_F, (size_t)N * 24));
+  int* flags = c->d_flags.as<int>();
+  // flags: [0] status bits, [1..2] largest rows, [3..4] rebuild decisions by
+  // step parity, [5..6] per-cell kernel needs, [8] device-triggered builds,
+  // [9] positions differ from the kept state
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 16 * sizeof(int), s));
-  launch_gather_in(N, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), c->d_flags.as<int>(), s);
-  launch_gather_in(N, c->d_perm.as<int>(), vel, c->d_vel.as<double>(), c->d_flags.as<int>(), s);
-  TRY(build_checked(c, s));
-  TRY(compute(c, s, true, nullptr, 0.0));
+  launch_gather_in(N, c->d_perm.as<int>(), vel, c->d_vel.as<double>(), flags, s);
+  if (resume) {
+    // positions the caller hands back unchanged (bitwise what the last call
+    // wrote) continue from the kept device state: its forces, rows and list
+    // reference stay valid, so neither a build nor a force evaluation is
+    // needed before the first step
+    launch_same_wrapped(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
+                        c->d_boxes.as<BoxInfo>(), c->pbc, pos, flags + 9, s);
+    int hf[10];
+    HIP_TRY(c, hipMemcpyAsync(hf, c->d_flags.p, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (hf[0] & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
+    resume = hf[9] == 0;
+  }
+  if (!resume) {
+    launch_gather_in(N, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), flags, s);
+    TRY(build_checked(c, s));
+    TRY(compute(c, s, true, nullptr, 0.0));
+  }
   const double half_dt = 0.5 * dt;
   const double hs2 = 0.25 * c->skin * c->skin;
   const int K = std::max(1, c->rebuild_every);
-  int* flags = c->d_flags.as<int>();
+  const int64_t nc = std::max<int64_t>(c->n_cells, 1);
+  int dev_builds = 0;
+  // outputs of the call, enqueued behind the last chunk so that its flag
+  // read is the call's only wait
+  auto outputs = [&]() {
+    double* scal = c->d_scal.as<double>();
+    launch_sum(N, c->d_E.as<double>(), c->d_red.as<double>(), e_pot ? e_pot : scal, s);
+    launch_kinetic(N, c->d_vel.as<double>(), c->d_mass.as<double>(), c->d_species.as<int>(),
+                   c->d_tmp.as<double>(), s);
+    launch_sum(N, c->d_tmp.as<double>(), c->d_red.as<double>(), e_kin ? e_kin : scal + 1, s);
+    launch_wrap_scatter_out(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
+                            c->d_boxes.as<BoxInfo>(), c->pbc, pos, s);
+    launch_scatter_out(N, c->d_perm.as<int>(), c->d_vel.as<double>(), vel, nullptr, nullptr, s);
+    if (forces) launch_scatter_out(N, c->d_perm.as<int>(), c->d_F.as<double>(), forces, nullptr, nullptr, s);
+  };
   int t = 0;  // steps done
-  while (t < n_steps) {
+  bool bins_clean = false;
+  do {
     const int len = std::min(K - (t % K), n_steps - t);
+    const bool last = t + len >= n_steps;
     // checkpoint for a capacity retry
-    launch_copy_f64(3 * (int64_t)N, c->d_pos.as<double>(), c->d_save_pos.as<double>(), s);
-    launch_copy_f64(3 * (int64_t)N, c->d_vel.as<double>(), c->d_save_vel.as<double>(), s);
-    launch_copy_f64(3 * (int64_t)N, c->d_F.as<double>(), c->d_save_F.as<double>(), s);
-    HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+    if (len > 0)
+      launch_copy3(3 * (int64_t)N, c->d_pos.as<double>(), c->d_save_pos.as<double>(), c->d_vel.as<double>(),
+                   c->d_save_vel.as<double>(), c->d_F.as<double>(), c->d_save_F.as<double>(), s);
     bool force_first = false;
     for (int attempt = 0;; ++attempt) {
       // With the per-cell row kernel the integrator bins the atoms for the
       // next build as it moves them (two halves of counts by step parity:
-      // the build of step t reads half t & 1 and clears the other).
+      // the build of step t reads half t & 1 and clears the other, so after
+      // the first chunk of a call the half the next drift fills is clear).
       const bool binned = c->tp > 0;
-      const int64_t nc = std::max<int64_t>(c->n_cells, 1);
-      if (binned) {
+      if (binned && len > 0) {
         TRY(ensure(c, c->d_bin_count, (size_t)2 * nc * sizeof(int)));
         TRY(ensure(c, c->d_bin_atoms, (size_t)nc * kCellAtomsMax * sizeof(int)));
-        HIP_TRY(c, hipMemsetAsync(c->d_bin_count.p, 0, (size_t)2 * nc * sizeof(int), s));
+        if (!bins_clean) HIP_TRY(c, hipMemsetAsync(c->d_bin_count.p, 0, (size_t)2 * nc * sizeof(int), s));
+        bins_clean = true;
       }
       // the opening half kick and drift of a step are fused into the force
       // gather of the step before it, except for the first step of a chunk
@@ -1126,42 +1188,31 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
           TRY(compute(c, s, true, c->d_vel.as<double>(), half_dt));
         }
       }
-      int hf[8];
-      TRY(read_flags(c, s, hf));
+      if (last) outputs();
+      HIP_TRY(c, hipGetLastError());
+      int hf[10];
+      HIP_TRY(c, hipMemcpyAsync(hf, c->d_flags.p, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipStreamSynchronize(s));
       if (!(hf[0] & kFlagOverflow)) {
         TRY(flag_status(c, hf[0]));
+        dev_builds = hf[8];
         break;
       }
       // truncated rows make the rest of the chunk meaningless, whatever else
       // it flagged: grow the rows and redo the chunk from its checkpoint
       if (attempt >= 3) return fail(c, AENET_E_DEVICE, "neighbour capacity retries exhausted");
       TRY(grow_caps(c, hf));
-      launch_copy_f64(3 * (int64_t)N, c->d_save_pos.as<double>(), c->d_pos.as<double>(), s);
-      launch_copy_f64(3 * (int64_t)N, c->d_save_vel.as<double>(), c->d_vel.as<double>(), s);
-      launch_copy_f64(3 * (int64_t)N, c->d_save_F.as<double>(), c->d_F.as<double>(), s);
+      launch_copy3(3 * (int64_t)N, c->d_save_pos.as<double>(), c->d_pos.as<double>(), c->d_save_vel.as<double>(),
+                   c->d_vel.as<double>(), c->d_save_F.as<double>(), c->d_F.as<double>(), s);
       HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 8 * sizeof(int), s));
+      bins_clean = false;
       force_first = true;
     }
     t += len;
-  }
-  // outputs
-  {
-    int dev_builds = 0;
-    HIP_TRY(c, hipMemcpyAsync(&dev_builds, c->d_flags.as<int>() + 8, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    c->stats.n_rebuilds += dev_builds;
-  }
-  double* scal = c->d_scal.as<double>();
-  launch_sum(N, c->d_E.as<double>(), c->d_red.as<double>(), e_pot ? e_pot : scal, s);
-  launch_kinetic(N, c->d_vel.as<double>(), c->d_mass.as<double>(), c->d_species.as<int>(),
-                 c->d_tmp.as<double>(), s);
-  launch_sum(N, c->d_tmp.as<double>(), c->d_red.as<double>(), e_kin ? e_kin : scal + 1, s);
-  launch_wrap_scatter_out(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
-                          c->d_boxes.as<BoxInfo>(), c->pbc, pos, s);
-  launch_scatter_out(N, c->d_perm.as<int>(), c->d_vel.as<double>(), vel, nullptr, nullptr, s);
-  if (forces) launch_scatter_out(N, c->d_perm.as<int>(), c->d_F.as<double>(), forces, nullptr, nullptr, s);
-  HIP_TRY(c, hipGetLastError());
-  HIP_TRY(c, hipStreamSynchronize(s));
+  } while (t < n_steps);
+  c->stats.n_rebuilds += dev_builds;
+  c->counters_clean = true;
+  c->md_state = true;
   return AENET_OK;
 }
 
@@ -1221,7 +1272,8 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   if (n_struct < 1 || !offsets || !boxes || !e_ref || !f_ref || !loss || !grad || !(lambda_f >= 0))
     return fail(c, AENET_E_INVALID, "bad arguments");
   hipStream_t s = pick_stream(c, stream);
-  TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos));
+  c->md_state = false;
+  TRY(prepare(c, n_struct, offsets, species, boxes, pbc, pos, s));
   const int n = (int)c->n;
   if (n == 0) return fail(c, AENET_E_INVALID, "empty batch");
   for (int b = 0; b < n_struct; ++b)
@@ -1271,6 +1323,7 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   int hf[8];
   TRY(read_flags(c, s, hf));
   TRY(flag_status(c, hf[0]));
+  c->counters_clean = true;
   return AENET_OK;
 }
 
@@ -1307,6 +1360,7 @@ aenet_status aenet_set_capacity(aenet_ctx* c, int row_capacity, int ang_capacity
   }
   c->cap = 0;  // applied at the next call's set-up
   c->nbr_valid = false;
+  c->md_state = false;
   return AENET_OK;
 }
 

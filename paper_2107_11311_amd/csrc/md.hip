@@ -50,13 +50,37 @@ __global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, co
   const size_t o = (size_t)perm[p];
   for (int a = 0; a < 3; ++a) {
     double x = pos[3 * (size_t)p + a];
-    if (pb[a]) {
-      x = x - b.L[a] * floor(x / b.L[a]);
-      if (x >= b.L[a]) x -= b.L[a];
-      if (x < 0.0) x = 0.0;
-    }
+    if (pb[a]) x = wrap_coord(x, b.L[a]);
     dst[3 * o + a] = x;
   }
+}
+
+// raises *differ if any caller-order position in src is not bitwise what
+// k_wrap_scatter_out writes for the internal positions pos
+__global__ void k_same_wrapped(int n, const int* perm, const double* pos, const int* seg,
+                               const BoxInfo* boxes, int px, int py, int pz, const double* src,
+                               int* differ) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const BoxInfo b = boxes[seg[p]];
+  const int pb[3] = {px, py, pz};
+  const size_t o = (size_t)perm[p];
+  bool same = true;
+  for (int a = 0; a < 3; ++a) {
+    double x = pos[3 * (size_t)p + a];
+    if (pb[a]) x = wrap_coord(x, b.L[a]);
+    same = same && (src[3 * o + a] == x);
+  }
+  if (!same) atomicOr(differ, 1);
+}
+
+__global__ void k_copy3(int64_t m, const double* a, double* a2, const double* b, double* b2,
+                        const double* c, double* c2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  a2[k] = a[k];
+  b2[k] = b[k];
+  c2[k] = c[k];
 }
 
 // Put the atoms of the wavefront's lanes with `mine` set (atom i at position
@@ -355,6 +379,20 @@ void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const in
   if (n > 0)
     hipLaunchKernelGGL(k_wrap_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, pos, seg,
                        boxes, pbc[0], pbc[1], pbc[2], dst);
+}
+
+void launch_same_wrapped(int n, const int* perm, const double* pos, const int* seg,
+                         const BoxInfo* boxes, const int pbc[3], const double* src, int* differ,
+                         hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_same_wrapped, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, pos, seg, boxes,
+                       pbc[0], pbc[1], pbc[2], src, differ);
+}
+
+void launch_copy3(int64_t m, const double* a, double* a2, const double* b, double* b2,
+                  const double* c, double* c2, hipStream_t s) {
+  if (m > 0)
+    hipLaunchKernelGGL(k_copy3, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, a, a2, b, b2, c, c2);
 }
 
 void launch_force_gather(int prec, int n, int cap, const int* nrad, const uint16_t* ridx, const void* pg,

@@ -45,9 +45,13 @@ def check_ef(A, orc, model, s, precision="fp64", skin=0.0, tol_e=1e-10, tol_f=1e
     de = abs(E - E0) / abs(E0)
     df = rel_rmse(F, F0)
     dea = float(np.abs(Ea - Ea0).max() / np.abs(Ea0).max())
-    print(f"{precision}: rel dE={de:.3e} rel F rmse={df:.3e} rel dE_atom={dea:.3e}")
+    # element-wise: the largest error of any force component against the
+    # largest force component (a single wrong component cannot hide in a norm)
+    dmax = float(np.abs(F - F0).max() / np.abs(F0).max())
+    print(f"{precision}: rel dE={de:.3e} rel F rmse={df:.3e} max|dF|/max|F|={dmax:.3e} rel dE_atom={dea:.3e}")
     assert de <= tol_e, f"energy rel err {de:.3e}"
     assert df <= tol_f, f"force rel rmse {df:.3e}"
+    assert dmax <= (1.0 if precision == "fp64" else 10.0) * tol_f, f"force max rel err {dmax:.3e}"
     assert dea <= 10 * tol_e, f"atom energy rel err {dea:.3e}"
     ctx.close()
     return E, F
@@ -413,3 +417,47 @@ def test_nve_energy_error_scales_dt2(A):
     d2 = max_dev(2.5e-4, 80, 4)
     print(f"nve: max |dE| {d1:.3e} (dt 0.5 fs) {d2:.3e} (dt 0.25 fs) ratio {d1 / d2:.2f}")
     assert 2.5 < d1 / d2 < 5.5
+
+
+def test_md_continuation_detects_changed_state(A):
+    """A call that continues from the state the last call left (positions
+    handed back unchanged) reuses its forces and list; a call whose positions
+    were changed by the caller, or that follows new parameters, starts over
+    and gives what a fresh context gives from the same inputs."""
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 6)
+    dt = 5e-4
+
+    def fresh(model, p, vv, steps):
+        c = A.Context(model, "fp64", skin=0.3)
+        out = c.md_step(p, vv, s.species, s.box, s.pbc, dt, steps)
+        c.close()
+        return out
+
+    ctx = A.Context(m, "fp64", skin=0.3)
+    p1, v1, _, _, _ = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, dt, 7)
+    # velocities rescaled (a thermostat): positions unchanged, state continues
+    p2, v2, e2, k2, F2 = ctx.md_step(p1, 0.9 * v1, s.species, s.box, s.pbc, dt, 6)
+    q2, w2, f2, l2, G2 = fresh(m, p1, 0.9 * v1, 6)
+    assert np.abs(p2 - q2).max() <= 1e-10 and np.abs(v2 - w2).max() <= 1e-8 * np.abs(w2).max()
+    assert abs(e2 - f2) <= 1e-10 * abs(f2)
+    # one atom moved by the caller: the forces of the new positions are used
+    p3 = p2.copy()
+    p3[5] += np.array([0.05, -0.03, 0.02])
+    r3, u3, e3, _, F3 = ctx.md_step(p3, v2, s.species, s.box, s.pbc, dt, 4)
+    q3, w3, f3, _, G3 = fresh(m, p3, v2, 4)
+    assert np.abs(r3 - q3).max() <= 1e-10 and abs(e3 - f3) <= 1e-10 * abs(f3)
+    np.testing.assert_allclose(F3, G3, rtol=0, atol=1e-10 * np.abs(G3).max())
+    # new parameters: the kept forces belong to the old network
+    m2 = m.with_params(1.1 * m.flat_params())
+    ctx.set_params(m2.flat_params())
+    r4, u4, e4, _, F4 = ctx.md_step(r3, u3, s.species, s.box, s.pbc, dt, 3)
+    q4, w4, f4, _, G4 = fresh(m2, r3, u3, 3)
+    assert np.abs(r4 - q4).max() <= 1e-10 and abs(e4 - f4) <= 1e-10 * abs(f4)
+    np.testing.assert_allclose(F4, G4, rtol=0, atol=1e-10 * np.abs(G4).max())
+    # zero steps on an unchanged state returns it as it is
+    r5, u5, e5, _, F5 = ctx.md_step(r4, u4, s.species, s.box, s.pbc, dt, 0)
+    assert np.array_equal(r5, r4) and np.array_equal(u5, u4) and e5 == e4
+    np.testing.assert_array_equal(F5, F4)
+    ctx.close()
