@@ -172,6 +172,29 @@ aenet_status aenet_energy_forces_batch_dev(aenet_ctx* ctx, int n_struct, const i
                                            double* e_struct, double* e_atom, double* forces,
                                            void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as aenet_energy_forces_dev (device pointers pos, e_total[1], e_atom,
+ * forces, and a stream), computed by the same kernels, with every temporary
+ * buffer (atom order, neighbour rows, per-entry gradients, descriptor
+ * gradients, sums) carved from one fixed device array of
+ * AENET_NOALLOC_WORKSPACE_BYTES per GPU instead of allocated.  The array is
+ * reserved when the library is loaded onto a GPU and kept until the process
+ * ends; the call itself allocates no device memory (the model's buffers were
+ * allocated by aenet_setup).  A structure whose buffers do not fit returns
+ * AENET_E_INVALID with the workspace size in the message (roughly 10,000 atoms
+ * of water at a 6 A cutoff in FP64).  All contexts on one GPU share the array,
+ * so calls that overlap in time on one GPU (different threads, or streams
+ * not ordered with each other) race: the caller serialises them.  Nothing of
+ * one call's workspace contents is reused by the next (every counter the
+ * kernels need at zero is cleared by the call).  The context's own buffers
+ * are not touched; a following aenet_md_step starts from its inputs. */
+#define AENET_NOALLOC_WORKSPACE_BYTES (64u << 20)
+aenet_status aenet_energy_forces_noalloc(aenet_ctx* ctx, int64_t n, const double* pos,
+                                         const int32_t* species, const double box[3],
+                                         const uint8_t pbc[3], double* e_total, double* e_atom,
+                                         double* forces, void* stream);
+
 /* Descriptor vectors G [n x D] (layout of aenet_model), host pointers. */
 aenet_status aenet_descriptors(aenet_ctx* ctx, int64_t n, const double* pos,
                                const int32_t* species, const double box[3],

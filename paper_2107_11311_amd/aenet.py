@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "AENET_OK", -1: "AENET_E_INVALID", -2: "AENET_E_SPECIES", -3:
 # every entry point declared in include/aenet_gpu.h
 EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor_dim", "aenet_n_params",
            "aenet_get_params", "aenet_set_params", "aenet_supported_orders", "aenet_energy_forces",
-           "aenet_energy_forces_virial", "aenet_energy_forces_dev", "aenet_energy_forces_batch_dev", "aenet_descriptors",
+           "aenet_energy_forces_virial", "aenet_energy_forces_dev", "aenet_energy_forces_noalloc",
+           "aenet_energy_forces_batch_dev", "aenet_descriptors",
            "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_get_stats",
            "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_profiling", "aenet_get_kernel_times"]
 KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate", "fwd_network"]
@@ -101,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.aenet_energy_forces.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp, _dp, _dp]
     L.aenet_energy_forces_virial.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp, _dp, _dp]
     L.aenet_energy_forces_dev.argtypes = [ctxp, C.c_int64, _vp, _ip, _dp, _u8p, _vp, _vp, _vp, _vp]
+    L.aenet_energy_forces_noalloc.argtypes = [ctxp, C.c_int64, _vp, _ip, _dp, _u8p, _vp, _vp, _vp, _vp]
     L.aenet_energy_forces_batch_dev.argtypes = [ctxp, C.c_int, _i64p, _vp, _ip, _dp, _u8p, _vp, _vp,
                                                 _vp, _vp]
     L.aenet_descriptors.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp]
@@ -313,6 +315,16 @@ class Context:
         self._check(self._lib.aenet_energy_forces_dev(self._h, int(pos.shape[0]), _dev(pos), _ptr(sp, _ip),
                                                       _ptr(box), _ptr(pbc, _u8p), _dev(e_total), _dev(e_atom),
                                                       _dev(forces), _stream(stream)))
+
+    def energy_forces_noalloc(self, pos, species, box, pbc=(1, 1, 1), e_total=None, e_atom=None,
+                              forces=None, stream=None):
+        """aenet_energy_forces_noalloc: as energy_forces_dev, temporaries in the
+        library's fixed per-GPU workspace (no device allocation in the call)."""
+        sp = _i32(species)
+        box, pbc = _box(box, pbc)
+        self._check(self._lib.aenet_energy_forces_noalloc(self._h, int(pos.shape[0]), _dev(pos), _ptr(sp, _ip),
+                                                          _ptr(box), _ptr(pbc, _u8p), _dev(e_total),
+                                                          _dev(e_atom), _dev(forces), _stream(stream)))
 
     def energy_forces_batch_dev(self, offsets, pos, species, boxes, pbc=(1, 1, 1), e_struct=None,
                                 e_atom=None, forces=None, stream=None):

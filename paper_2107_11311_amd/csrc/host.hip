@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,13 @@ struct DevMem {
 };
 
 int pad_to(int x, int m) { return (x + m - 1) / m * m; }
+
+// Bump allocator over a fixed device region (the no-allocation entry point's
+// workspace): buffers are handed out in call order, none is freed.
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t size = 0, used = 0;
+};
 
 }  // namespace
 
@@ -89,6 +97,9 @@ struct aenet_ctx {
   // positions, forces at them, the neighbour rows and their reference
   // positions; anything else that uses the buffers clears it
   bool md_state = false;
+  // non-NULL during a no-allocation call: ensure() carves buffers from this
+  // region instead of allocating
+  Arena* arena = nullptr;
 
   DevMem d_perm, d_species, d_wq, d_seg, d_segoff, d_segcount, d_boxes;
   DevMem d_pos, d_pos_ref, d_vel, d_F, d_Fself, d_E, d_Eorig, d_G, d_gG, d_pg, d_U, d_adj, d_eps,
@@ -134,6 +145,19 @@ aenet_status fail(aenet_ctx* c, aenet_status code, const std::string& msg) {
 aenet_status ensure(aenet_ctx* c, DevMem& m, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (m.bytes >= bytes) return AENET_OK;
+  if (c->arena) {
+    // no-allocation call: a (larger) slice of the workspace; what the buffer
+    // held before is not kept (every buffer is requested before it is filled)
+    const size_t b = (bytes + 255) / 256 * 256;
+    if (c->arena->used + b > c->arena->size)
+      return fail(c, AENET_E_INVALID,
+                  "the no-allocation workspace (" + std::to_string(c->arena->size) +
+                      " bytes) is too small for this structure; use aenet_energy_forces_dev");
+    m.p = c->arena->base + c->arena->used;
+    m.bytes = b;
+    c->arena->used += b;
+    return AENET_OK;
+  }
   if (m.p) {
     (void)hipFree(m.p);
     m.p = nullptr;
@@ -383,7 +407,7 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
   const size_t el = real_size(c);
   TRY(ensure(c, c->d_pos, nb * 24));
   TRY(ensure(c, c->d_pos_ref, nb * 24));
-  TRY(ensure(c, c->d_vel, nb * 24));
+  if (!c->arena) TRY(ensure(c, c->d_vel, nb * 24));  // MD only
   TRY(ensure(c, c->d_F, nb * 24));
   TRY(ensure(c, c->d_Fself, nb * 24));
   TRY(ensure(c, c->d_E, nb * 8));
@@ -719,6 +743,35 @@ void launch_take(int n, const int* idx, const double* src, double* dst, hipStrea
 
 thread_local std::string g_setup_error;
 
+// ------------------------------------------------------------------ no-allocation workspace
+// The device memory of aenet_energy_forces_noalloc: one array per GPU,
+// reserved when the library's code object is loaded onto that GPU and held
+// until the process ends.  Host code never uses the symbol's name as an
+// address: each device's address is looked up once (with that device
+// current) and kept in g_scratch_addr.
+constexpr size_t kScratchBytes = (size_t)AENET_NOALLOC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {nullptr};
+
+// address of this device's workspace (the device must be current); looked up
+// on the first call for the device, NULL if the lookup fails
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[device] = ptr;
+  }
+  return g_scratch_addr[device];
+}
+
 aenet_status check_ctx(aenet_ctx* c) {
   if (!c) return AENET_E_INVALID;
   c->err.clear();
@@ -886,6 +939,12 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
     delete c;
     return AENET_E_DEVICE;
   }
+  // the device's no-allocation workspace (looked up once per device)
+  if (!scratch_address(c->device)) {
+    g_setup_error = "hipGetSymbolAddress of the no-allocation workspace failed";
+    aenet_destroy(c);
+    return AENET_E_DEVICE;
+  }
   if (pack_networks(c) != AENET_OK) {
     g_setup_error = c->err;
     aenet_destroy(c);
@@ -976,6 +1035,67 @@ aenet_status aenet_energy_forces_batch_dev(aenet_ctx* c, int n_struct, const int
   if (n_struct < 1 || !offsets || !boxes) return fail(c, AENET_E_INVALID, "bad arguments");
   return ef_core(c, n_struct, offsets, pos, species, boxes, pbc, e_struct, nullptr, e_atom, forces,
                  pick_stream(c, stream));
+}
+
+aenet_status aenet_energy_forces_noalloc(aenet_ctx* c, int64_t n, const double* pos,
+                                         const int32_t* species, const double box[3],
+                                         const uint8_t pbc[3], double* e_total, double* e_atom,
+                                         double* forces, void* stream) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && !pos)) return fail(c, AENET_E_INVALID, "bad arguments");
+  void* ws = scratch_address(c->device);
+  if (!ws) return fail(c, AENET_E_DEVICE, "no-allocation workspace unavailable on this device");
+  // Every per-call device buffer of the context is swapped for a slice of
+  // the workspace for the duration of the call and restored afterwards; the
+  // context's own buffers (and the model's, allocated at set-up) are not
+  // touched.  The workspace belongs to every context on this device, so
+  // nothing the context remembers about its buffers' contents (atom order,
+  // boxes, neighbour rows, cleared counters, MD state) carries into or out of
+  // this call: set-up runs in full and the context forgets afterwards.
+  DevMem* bufs[] = {&c->d_perm, &c->d_species, &c->d_wq, &c->d_seg, &c->d_segoff, &c->d_segcount,
+                    &c->d_boxes, &c->d_pos, &c->d_pos_ref, &c->d_vel, &c->d_F, &c->d_Fself, &c->d_E,
+                    &c->d_Eorig, &c->d_G, &c->d_gG, &c->d_U, &c->d_adj, &c->d_eps, &c->d_tmp, &c->d_red,
+                    &c->d_scal, &c->d_flags, &c->d_cell_count, &c->d_cell_start, &c->d_cell_fill,
+                    &c->d_cell_atoms, &c->d_atom_cell, &c->d_nbr, &c->d_segs, &c->d_nnb, &c->d_nang,
+                    &c->d_rev, &c->d_ridx, &c->d_nrad, &c->d_vir, &c->d_build};
+  constexpr int nbufs = (int)(sizeof(bufs) / sizeof(bufs[0]));
+  struct Saved {
+    void* p;
+    size_t bytes;
+  } saved[nbufs];
+  auto forget = [&]() {
+    c->n = -1;  // set-up treats the next call's species pattern as new
+    c->species_cache.clear();
+    c->offsets_cache.clear();
+    c->boxes.clear();
+    c->cap = 0;
+    c->nbr_valid = false;
+    c->md_state = false;
+    c->counters_clean = false;
+  };
+  for (int k = 0; k < nbufs; ++k) {
+    saved[k] = {bufs[k]->p, bufs[k]->bytes};
+    bufs[k]->p = nullptr;
+    bufs[k]->bytes = 0;
+  }
+  Arena arena;
+  arena.base = static_cast<unsigned char*>(ws);
+  arena.size = kScratchBytes;
+  const bool prof = c->profiling;
+  c->profiling = false;  // no event creation inside this call
+  c->arena = &arena;
+  forget();
+  const int64_t off[2] = {0, n};
+  const aenet_status st =
+      ef_core(c, 1, off, pos, species, box, pbc, nullptr, e_total, e_atom, forces, pick_stream(c, stream));
+  c->arena = nullptr;
+  c->profiling = prof;
+  forget();
+  for (int k = 0; k < nbufs; ++k) {
+    bufs[k]->p = saved[k].p;
+    bufs[k]->bytes = saved[k].bytes;
+  }
+  return st;
 }
 
 namespace {
