@@ -72,9 +72,9 @@ def lib():
                                                dp, dp, dp]
         L.orc_md_vv.argtypes = [C.POINTER(_Model), C.c_int, dp, dp, ip, dp, dp, ip, C.c_double,
                                 C.c_int, dp, dp, dp]
-        L.orc_loss.argtypes = [C.POINTER(_Model), C.c_int, ip, dp, ip, dp, ip, dp, dp, C.c_double, dp]
+        L.orc_loss.argtypes = [C.POINTER(_Model), C.c_int, ip, dp, ip, dp, ip, dp, dp, C.c_double, C.c_int, dp]
         L.orc_loss_grad.argtypes = [C.POINTER(_Model), C.c_int, ip, dp, ip, dp, ip, dp, dp,
-                                    C.c_double, dp, dp]
+                                    C.c_double, C.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -306,12 +306,15 @@ def _batch_args(offsets, pos, species, boxes, pbc, e_ref, f_ref):
             _i32(np.asarray(pbc, dtype=np.int32).reshape(3)), _f64(e_ref), _f64(f_ref).reshape(-1, 3))
 
 
-def loss(model, offsets, pos, species, boxes, pbc, e_ref, f_ref, lambda_f, params=None):
+LOSS_MEAN_PER_ATOM, LOSS_EQ7 = 0, 1
+
+
+def loss(model, offsets, pos, species, boxes, pbc, e_ref, f_ref, lambda_f, params=None, form=LOSS_MEAN_PER_ATOM):
     off, pos, sp, boxes, pbc, e_ref, f_ref = _batch_args(offsets, pos, species, boxes, pbc, e_ref, f_ref)
     pk = _Packed(model, params)
     out = C.c_double()
     _check(lib().orc_loss(pk.ptr, len(off) - 1, _ip(off), _dp(pos), _ip(sp), _dp(boxes), _ip(pbc),
-                          _dp(e_ref), _dp(f_ref), float(lambda_f), C.byref(out)))
+                          _dp(e_ref), _dp(f_ref), float(lambda_f), int(form), C.byref(out)))
     return out.value
 
 
@@ -320,13 +323,14 @@ def n_params(model) -> int:
                    for W, b in zip(net.W, net.b)))
 
 
-def loss_grad(model, offsets, pos, species, boxes, pbc, e_ref, f_ref, lambda_f, params=None):
+def loss_grad(model, offsets, pos, species, boxes, pbc, e_ref, f_ref, lambda_f, params=None,
+              form=LOSS_MEAN_PER_ATOM):
     off, pos, sp, boxes, pbc, e_ref, f_ref = _batch_args(offsets, pos, species, boxes, pbc, e_ref, f_ref)
     pk = _Packed(model, params)
     out = C.c_double()
     grad = np.zeros(n_params(model))
     _check(lib().orc_loss_grad(pk.ptr, len(off) - 1, _ip(off), _dp(pos), _ip(sp), _dp(boxes),
-                               _ip(pbc), _dp(e_ref), _dp(f_ref), float(lambda_f), C.byref(out),
+                               _ip(pbc), _dp(e_ref), _dp(f_ref), float(lambda_f), int(form), C.byref(out),
                                _dp(grad)))
     return out.value, grad
 

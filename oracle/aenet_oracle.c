@@ -882,9 +882,10 @@ static int check_batch(const orc_model* m, int B, const int* offsets, const int*
 
 int orc_loss(const orc_model* m, int B, const int* offsets, const double* pos,
              const int* species, const double* boxes, const int* pbc, const double* e_ref,
-             const double* f_ref, double lambda_f, double* loss) {
+             const double* f_ref, double lambda_f, int form, double* loss) {
   int st = check_model(m);
   if (st) return st;
+  if (form != 0 && form != 1) return ORC_E_INVALID;
   if ((st = check_batch(m, B, offsets, species))) return st;
   ksum C = {0.0, 0.0};
   for (int s = 0; s < B && st == ORC_OK; ++s) {
@@ -894,14 +895,20 @@ int orc_loss(const orc_model* m, int B, const int* offsets, const double* pos,
     st = orc_energy_forces(m, ns, pos + 3 * (size_t)a0, species + a0, boxes + 3 * s, pbc, &E,
                            NULL, F, NULL);
     if (st == ORC_OK) {
-      double de = (E - e_ref[s]) / ns;
-      ks_add(&C, de * de / B);
       ksum fs = {0.0, 0.0};
       for (int k = 0; k < 3 * ns; ++k) {
         double df = F[k] - f_ref[3 * (size_t)a0 + k];
         ks_add(&fs, df * df);
       }
-      ks_add(&C, lambda_f * ks_val(&fs) / (3.0 * ns) / B);
+      if (form == 0) {
+        double de = (E - e_ref[s]) / ns;
+        ks_add(&C, de * de / B);
+        ks_add(&C, lambda_f * ks_val(&fs) / (3.0 * ns) / B);
+      } else {
+        double de = E - e_ref[s];
+        ks_add(&C, 0.5 * de * de);
+        ks_add(&C, 0.5 * lambda_f * ks_val(&fs));
+      }
     }
     free(F);
   }
@@ -966,10 +973,11 @@ static void net_double_backprop(const orc_net* net, double** xs, const double* u
 
 int orc_loss_grad(const orc_model* m, int B, const int* offsets, const double* pos,
                   const int* species, const double* boxes, const int* pbc,
-                  const double* e_ref, const double* f_ref, double lambda_f, double* loss,
-                  double* grad) {
+                  const double* e_ref, const double* f_ref, double lambda_f, int form,
+                  double* loss, double* grad) {
   int st = check_model(m);
   if (st) return st;
+  if (form != 0 && form != 1) return ORC_E_INVALID;
   if ((st = check_batch(m, B, offsets, species))) return st;
   layout L = make_layout(m);
   size_t poff[64];
@@ -996,17 +1004,25 @@ int orc_loss_grad(const orc_model* m, int B, const int* offsets, const double* p
     double E = 0.0;
     st = orc_energy_forces(m, ns, ps, sp, boxes + 3 * s, pbc, &E, NULL, F, NULL);
     if (st) { free(F); free(adj); break; }
-    /* loss value and its adjoints w.r.t. E_s and F */
-    double de = (E - e_ref[s]) / ns;
-    ks_add(&C, de * de / B);
+    /* loss value and its adjoints w.r.t. E_s (eps) and F (adj) */
     ksum fs = {0.0, 0.0};
     for (int k = 0; k < 3 * ns; ++k) {
       double df = F[k] - f_ref[3 * (size_t)a0 + k];
       ks_add(&fs, df * df);
-      adj[k] = 2.0 * lambda_f * df / (3.0 * ns) / B;
+      adj[k] = form == 0 ? 2.0 * lambda_f * df / (3.0 * ns) / B : lambda_f * df;
     }
-    ks_add(&C, lambda_f * ks_val(&fs) / (3.0 * ns) / B);
-    const double eps = 2.0 * de / ns / B;
+    double eps;
+    if (form == 0) {
+      double de = (E - e_ref[s]) / ns;
+      ks_add(&C, de * de / B);
+      ks_add(&C, lambda_f * ks_val(&fs) / (3.0 * ns) / B);
+      eps = 2.0 * de / ns / B;
+    } else {
+      double de = E - e_ref[s];
+      ks_add(&C, 0.5 * de * de);
+      ks_add(&C, 0.5 * lambda_f * ks_val(&fs));
+      eps = de;
+    }
     /* per atom: u_i = J_i adj, then the double back-propagation */
     work w;
     st = work_init(m, ns, ps, boxes + 3 * s, pbc, &w);

@@ -112,16 +112,21 @@ int orc_md_vv(const orc_model* m, int n, double* pos, double* vel, const int* sp
 
 /* Energy+force loss over a batch of B independent structures.  Structure s owns
  * atoms [offsets[s], offsets[s+1]) of pos/species/F_ref, box boxes[3s..3s+2] and
- * shares pbc.  C = (1/B) sum_s [((E_s-Eref_s)/N_s)^2 + lambda_f/(3 N_s) sum |F-Fref|^2].
+ * shares pbc.  Two forms:
+ *   form 0 (per-atom mean):  C = (1/B) sum_s [((E_s-Eref_s)/N_s)^2
+ *                                             + lambda_f/(3 N_s) sum_{i in s} |F_i-Fref_i|^2]
+ *   form 1 (Eq. 7 as printed, Sec. II C: half the sum of squared energy errors,
+ *           with an optional force term of the same kind):
+ *                            C = 1/2 sum_s (E_s-Eref_s)^2 + lambda_f/2 sum_i |F_i-Fref_i|^2
  * orc_loss_grad also writes dC/dparams (concatenated over species, each in the
  * orc_net params layout) computed analytically by double back-propagation. */
 int orc_loss(const orc_model* m, int n_struct, const int* offsets, const double* pos,
              const int* species, const double* boxes, const int* pbc, const double* e_ref,
-             const double* f_ref, double lambda_f, double* loss);
+             const double* f_ref, double lambda_f, int form, double* loss);
 int orc_loss_grad(const orc_model* m, int n_struct, const int* offsets, const double* pos,
                   const int* species, const double* boxes, const int* pbc,
-                  const double* e_ref, const double* f_ref, double lambda_f, double* loss,
-                  double* grad);
+                  const double* e_ref, const double* f_ref, double lambda_f, int form,
+                  double* loss, double* grad);
 
 #ifdef __cplusplus
 }

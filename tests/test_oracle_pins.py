@@ -345,7 +345,8 @@ def test_maxwell_boltzmann_temperature():
 
 
 # ---------------------------------------------------------------- training loss (Sec. II C)
-def test_loss_gradient_matches_central_differences(orc):
+@pytest.mark.parametrize("form", [0, 1])
+def test_loss_gradient_matches_central_differences(orc, form):
     m = normalised(tiny_model(S=2, nr=5, rr=5.0, na=3, ra=3.5, hidden=(6, 5)), 21)
     ref = normalised(tiny_model(S=2, nr=5, rr=5.0, na=3, ra=3.5, hidden=(6, 5), seed=77), 22)
     boxes = [I.water_box(6, 41), I.water_box(10, 42)]
@@ -360,19 +361,51 @@ def test_loss_gradient_matches_central_differences(orc):
         E, _, F = orc.energy_forces(ref, b.pos, b.species, b.box, b.pbc)
         er.append(E); fr.append(F)
     er = np.array(er); fr = np.vstack(fr)
-    L, grad = orc.loss_grad(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0)
-    assert L == pytest.approx(orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0), rel=1e-14)
+    L, grad = orc.loss_grad(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, form=form)
+    assert L == pytest.approx(orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, form=form), rel=1e-14)
     p0 = orc.all_params(m)
     h = 1e-5
     for k in range(len(p0)):
         if k % 7:
             continue
         pp = p0.copy(); pp[k] += h
-        Lp = orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, params=pp)
+        Lp = orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, params=pp, form=form)
         pp = p0.copy(); pp[k] -= h
-        Lm = orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, params=pp)
+        Lm = orc.loss(m, offs, pos, sp, bx, [1, 1, 1], er, fr, 1.0, params=pp, form=form)
         fd = (Lp - Lm) / (2 * h)
         assert abs(grad[k] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(grad).max()), (k, grad[k], fd)
+
+
+def test_loss_forms_eq7_and_per_atom_mean(orc):
+    """Eq. 7 as printed is half the sum of squared energy errors over the
+    structures: with lambda_f = 0 the form-1 cost is 1/2 sum_s (E_s - E_ref_s)^2
+    with E_s the oracle's structure energies (pinned separately).  For B
+    structures of one size N the two forms are fixed multiples of each other:
+    energy parts by B N^2 / 2, force parts by 3 N B / 2."""
+    m = normalised(tiny_model(S=2, nr=4, rr=4.0, na=2, ra=3.0, hidden=(6,)), 24)
+    ref = normalised(tiny_model(S=2, nr=4, rr=4.0, na=2, ra=3.0, hidden=(6,), seed=78), 25)
+    boxes = [I.water_box(6, 61 + k) for k in range(3)]          # three structures of 18 atoms
+    offs = [0]
+    for b in boxes:
+        offs.append(offs[-1] + len(b.pos))
+    pos = np.vstack([b.pos for b in boxes]); sp = np.concatenate([b.species for b in boxes])
+    bx = np.vstack([b.box for b in boxes])
+    E, er, fr = [], [], []
+    for b in boxes:
+        E.append(orc.energy_forces(m, b.pos, b.species, b.box, b.pbc)[0])
+        Er, _, Fr = orc.energy_forces(ref, b.pos, b.species, b.box, b.pbc)
+        er.append(Er); fr.append(Fr)
+    E, er, fr = np.array(E), np.array(er), np.vstack(fr)
+    args = (m, offs, pos, sp, bx, [1, 1, 1], er, fr)
+    c1e = orc.loss(*args, 0.0, form=1)
+    assert c1e == pytest.approx(0.5 * np.sum((E - er) ** 2), rel=1e-13)
+    B, N = 3, 18
+    c0e = orc.loss(*args, 0.0, form=0)
+    c0f = orc.loss(*args, 1.0, form=0) - c0e
+    c1f = orc.loss(*args, 1.0, form=1) - c1e
+    assert c1e == pytest.approx(0.5 * B * N * N * c0e, rel=1e-12)
+    assert c1f == pytest.approx(1.5 * N * B * c0f, rel=1e-12)
+    assert c0f > 0 and c0e > 0
 
 
 def test_loss_zero_at_reference(orc):
