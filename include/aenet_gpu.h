@@ -225,17 +225,50 @@ aenet_status aenet_md_step_dev(aenet_ctx* ctx, int64_t n, double* pos, double* v
                                const uint8_t pbc[3], double dt_ps, int n_steps, double* e_pot,
                                double* e_kin, double* forces, void* stream);
 
-/* Energy+force training loss over a batch and its gradient w.r.t. all
- * parameters (training, Sec. II C, extended from the energy-only Eq. 7):
- *   C = (1/B) sum_s [ ((E_s - e_ref_s)/N_s)^2 + lambda_f/(3 N_s) sum_{i in s} |F_i - f_ref_i|^2 ].
+/* Training loss over a batch of B structures and its gradient w.r.t. all
+ * parameters (training, Sec. II C).  Two forms (aenet_set_loss_form):
+ *   AENET_LOSS_MEAN_PER_ATOM (default):
+ *     C = (1/B) sum_s [ ((E_s - e_ref_s)/N_s)^2 + lambda_f/(3 N_s) sum_{i in s} |F_i - f_ref_i|^2 ]
+ *   AENET_LOSS_EQ7 (Eq. 7 as printed, half the sum of squared energy errors,
+ *   with a force term of the same kind when lambda_f > 0):
+ *     C = 1/2 sum_s (E_s - e_ref_s)^2 + lambda_f/2 sum_i |F_i - f_ref_i|^2
  * The gradient is obtained by double back-propagation (a descriptor
  * Jacobian-vector product followed by a reverse pass through the network and
  * its tangent).  Batch layout as aenet_energy_forces_batch_dev; e_ref [B],
- * f_ref [n x 3], loss [1], grad [aenet_n_params] are device pointers. */
+ * f_ref [n x 3], loss [1], grad [aenet_n_params] are device pointers.
+ * FP64 and FP32 contexts only. */
 aenet_status aenet_loss_grad_dev(aenet_ctx* ctx, int n_struct, const int64_t* offsets,
                                  const double* pos, const int32_t* species, const double* boxes,
                                  const uint8_t pbc[3], const double* e_ref, const double* f_ref,
                                  double lambda_f, double* loss, double* grad, void* stream);
+
+/* The same with host pointers (pos [n x 3], e_ref [B], f_ref [n x 3], loss
+ * [1], grad [aenet_n_params]). */
+aenet_status aenet_loss_grad(aenet_ctx* ctx, int n_struct, const int64_t* offsets,
+                             const double* pos, const int32_t* species, const double* boxes,
+                             const uint8_t pbc[3], const double* e_ref, const double* f_ref,
+                             double lambda_f, double* loss, double* grad);
+
+/* Selects the loss form of the following aenet_loss_grad[_dev] calls. */
+typedef enum { AENET_LOSS_MEAN_PER_ATOM = 0, AENET_LOSS_EQ7 = 1 } aenet_loss_form;
+aenet_status aenet_set_loss_form(aenet_ctx* ctx, int form);
+
+/* Replaces the parameters from DEVICE memory (flat layout of aenet_n_params,
+ * float64), repacking the network operands on the device: training loops keep
+ * parameters, gradients and optimiser state on the GPU with no host round
+ * trip.  FP64 and FP32 contexts (AENET_E_INVALID for BF16); AENET_E_NONFINITE
+ * (parameters unchanged) if any value is NaN/Inf.  aenet_get_params returns
+ * the values set here. */
+aenet_status aenet_set_params_dev(aenet_ctx* ctx, const double* params, void* stream);
+
+/* One Adam step (Kingma and Ba, 2015) on n float64 device values:
+ *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
+ *   p -= lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps)
+ * step >= 1 counts the updates so far including this one.  Device pointers,
+ * updated in place; synchronises the stream.  Context-free. */
+aenet_status aenet_adam_step_dev(int64_t n, double* params, const double* grad, double* m, double* v,
+                                 double lr, double beta1, double beta2, double eps, int64_t step,
+                                 void* stream);
 
 /* Tuning / diagnostics. */
 typedef struct {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libaenet_gpu.so")
 AENET_OK, AENET_E_INVALID, AENET_E_SPECIES, AENET_E_BOX = 0, -1, -2, -3
 AENET_E_OVERLAP, AENET_E_NONFINITE, AENET_E_DEVICE, AENET_E_OOM = -4, -5, -6, -7
 AENET_FP64, AENET_FP32, AENET_BF16 = 0, 1, 2
+AENET_LOSS_MEAN_PER_ATOM, AENET_LOSS_EQ7 = 0, 1
 PRECISIONS = {"fp64": AENET_FP64, "fp32": AENET_FP32, "bf16": AENET_BF16}
 STATUS_NAMES = {0: "AENET_OK", -1: "AENET_E_INVALID", -2: "AENET_E_SPECIES", -3: "AENET_E_BOX",
                 -4: "AENET_E_OVERLAP", -5: "AENET_E_NONFINITE", -6: "AENET_E_DEVICE", -7: "AENET_E_OOM"}
@@ -28,7 +29,8 @@ EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor
            "aenet_get_params", "aenet_set_params", "aenet_supported_orders", "aenet_energy_forces",
            "aenet_energy_forces_virial", "aenet_energy_forces_dev", "aenet_energy_forces_noalloc",
            "aenet_energy_forces_batch_dev", "aenet_descriptors",
-           "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_get_stats",
+           "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_loss_grad", "aenet_set_loss_form",
+           "aenet_set_params_dev", "aenet_adam_step_dev", "aenet_get_stats",
            "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_profiling", "aenet_get_kernel_times"]
 KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate", "fwd_network"]
 
@@ -112,6 +114,11 @@ def load(path: str = LIB_PATH):
                                     _vp, _vp, _vp, _vp]
     L.aenet_loss_grad_dev.argtypes = [ctxp, C.c_int, _i64p, _vp, _ip, _dp, _u8p, _vp, _vp, C.c_double,
                                       _vp, _vp, _vp]
+    L.aenet_loss_grad.argtypes = [ctxp, C.c_int, _i64p, _dp, _ip, _dp, _u8p, _dp, _dp, C.c_double, _dp, _dp]
+    L.aenet_set_loss_form.argtypes = [ctxp, C.c_int]
+    L.aenet_set_params_dev.argtypes = [ctxp, _vp, _vp]
+    L.aenet_adam_step_dev.argtypes = [C.c_int64, _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_int64, _vp]
     L.aenet_get_stats.argtypes = [ctxp, C.POINTER(Stats)]
     L.aenet_set_rebuild_every.argtypes = [ctxp, C.c_int]
     L.aenet_set_capacity.argtypes = [ctxp, C.c_int, C.c_int]
@@ -127,6 +134,16 @@ def load(path: str = LIB_PATH):
     if path == LIB_PATH:
         _lib = L
     return L
+
+
+def adam_step_dev(params, grad, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1, stream=None):
+    """aenet_adam_step_dev: one Adam update of float64 device tensors in place."""
+    L = load()
+    n = int(params.numel())
+    code = L.aenet_adam_step_dev(n, _dev(params), _dev(grad), _dev(m), _dev(v), float(lr), float(beta1),
+                                 float(beta2), float(eps), int(step), _stream(stream))
+    if code != AENET_OK:
+        raise AenetError(code, "aenet_adam_step_dev")
 
 
 def supported_orders():
@@ -232,6 +249,15 @@ class Context:
         assert p.size == self.n_params()
         self._check(self._lib.aenet_set_params(self._h, _ptr(p)))
 
+    def set_params_dev(self, p, stream=None) -> None:
+        """aenet_set_params_dev: parameters from a float64 device tensor."""
+        assert p.numel() == self.n_params() and p.is_contiguous()
+        self._check(self._lib.aenet_set_params_dev(self._h, _dev(p), _stream(stream)))
+
+    def set_loss_form(self, form: int) -> None:
+        """AENET_LOSS_MEAN_PER_ATOM (default) or AENET_LOSS_EQ7 for the loss-gradient calls."""
+        self._check(self._lib.aenet_set_loss_form(self._h, int(form)))
+
     def stats(self) -> dict:
         s = Stats()
         self._check(self._lib.aenet_get_stats(self._h, C.byref(s)))
@@ -306,6 +332,22 @@ class Context:
                                             _ptr(box), _ptr(pbc, _u8p), float(dt_ps), int(n_steps),
                                             C.byref(ep), C.byref(ek), _ptr(F)))
         return pos, vel, ep.value, ek.value, F
+
+    def loss_grad(self, offsets, pos, species, boxes, pbc, e_ref, f_ref, lambda_f):
+        """aenet_loss_grad: (loss, grad [n_params]) from host arrays."""
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        pos = _f64(pos).reshape(-1, 3)
+        sp = _i32(species)
+        bx = _f64(boxes).reshape(-1, 3)
+        _, pbc = _box(bx[0], pbc)
+        er = _f64(e_ref)
+        fr = _f64(f_ref).reshape(-1, 3)
+        loss = C.c_double()
+        grad = np.zeros(self.n_params())
+        self._check(self._lib.aenet_loss_grad(self._h, len(off) - 1, _ptr(off, _i64p), _ptr(pos), _ptr(sp, _ip),
+                                              _ptr(bx), _ptr(pbc, _u8p), _ptr(er), _ptr(fr), float(lambda_f),
+                                              C.byref(loss), _ptr(grad)))
+        return loss.value, grad
 
     # -------------------------------------------------------------- device calls (torch tensors)
     def energy_forces_dev(self, pos, species, box, pbc=(1, 1, 1), e_total=None, e_atom=None,

@@ -174,7 +174,7 @@ struct MlpNet {          // device pointers of one species (compute type T = dou
   // operands; these are the packed lo parts (NULL otherwise)
   const void* wf_lo;
   const void* wb_lo;
-  double blast;
+  const double* blast;           // output-layer bias (device, one double)
   double e_offset;
 };
 struct MlpParams {
@@ -275,8 +275,8 @@ void launch_check_finite(int64_t n, const double* x, int* flags, hipStream_t s);
 // training helpers
 void launch_loss_terms(int n, int n_struct, const int* seg, const int* perm, const double* F,
                        const double* f_ref, const double* e_struct, const double* e_ref,
-                       const int64_t* seg_count, double lambda_f, double* adj, double* eps_atom,
-                       double* floss_atom, double* eloss_struct, hipStream_t s);
+                       const int64_t* seg_count, double lambda_f, int form, double* adj,
+                       double* eps_atom, double* floss_atom, double* eloss_struct, hipStream_t s);
 void launch_grad_reduce(int n_blocks, int n_params_pad, const double* part, double* out,
                         hipStream_t s);
 

@@ -67,6 +67,14 @@ struct aenet_ctx {
   aenet_stats stats{};
 
   DevMem netbuf;        // packed network operands
+  DevMem d_blast;       // [kMaxSpecies] output-layer bias per species
+  DevMem d_params;      // [S * nps] the parameters (API layout), device copy
+  DevMem d_packmap;     // [n_pack] netbuf element -> parameter index (FP64/FP32)
+  DevMem d_blastsrc;    // [S] parameter index of each species' output bias
+  int64_t n_pack = 0;
+  int blast_src[kMaxSpecies] = {0};
+  bool params_host_stale = false;  // d_params is newer than params (set on the device)
+  int loss_form = 0;               // AENET_LOSS_*
   MlpParams mlp{};      // pointers into netbuf (species part); geometry filled per call
   DevMem d_pidx;        // API parameter index -> padded index
 
@@ -177,13 +185,18 @@ size_t real_size(const aenet_ctx* c) { return c->prec == 0 ? sizeof(double) : si
 int desc_prec(const aenet_ctx* c) { return c->prec == 0 ? 0 : 1; }
 
 // ------------------------------------------------------------------ network packing
+// The per-precision network operands of every species in one device buffer
+// (netbuf): per hidden layer the forward and backward MFMA B operands and the
+// bias, then the output weights and the input shift and scale; the output
+// bias of each species lives in d_blast.  For FP64/FP32 contexts a map from
+// every netbuf element to the flat parameter it holds (-1: padding, zero;
+// -2: input shift/scale, not a parameter) lets the device repack parameters
+// that are already in device memory (aenet_set_params_dev).
 aenet_status pack_networks(aenet_ctx* c) {
   const int S = c->S, L = c->L;
   const int prec = c->prec;
   const size_t el = real_size(c);
   const size_t bel = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
-  // byte layout: per species, per hidden layer: wf, wb, bias; then wlast, shift, scale
-  std::vector<size_t> off;
   size_t total = 0;
   auto take = [&](size_t bytes) {
     size_t o = total;
@@ -210,49 +223,78 @@ aenet_status pack_networks(aenet_ctx* c) {
     so[s].shift = take((size_t)c->ldG * el);
     so[s].scale = take((size_t)c->ldG * el);
   }
-  std::vector<unsigned char> host(total, 0);
-  auto put = [&](size_t o, int idx, double v) {
-    if (el == 8)
-      reinterpret_cast<double*>(host.data() + o)[idx] = v;
-    else
-      reinterpret_cast<float*>(host.data() + o)[idx] = (float)v;
-  };
-  for (int s = 0; s < S; ++s) {
-    const double* P = c->params.data() + (size_t)s * c->nps;
-    size_t po = 0;
-    for (int l = 1; l <= L; ++l) {
-      const int in = c->w[l - 1], out = c->w[l];
-      const double* W = P + po;
-      const double* b = W + (size_t)out * in;
-      po += (size_t)out * in + out;
-      if (l < L) {
-        const int Kp = c->wp[l - 1], Np = c->wp[l];
-        std::vector<double> Bf((size_t)Kp * Np, 0.0), Bb((size_t)Np * Kp, 0.0);
-        for (int q = 0; q < out; ++q)
-          for (int k = 0; k < in; ++k) {
-            Bf[(size_t)k * Np + q] = W[(size_t)q * in + k];  // forward: B[k][n] = W[n][k]
-            Bb[(size_t)q * Kp + k] = W[(size_t)q * in + k];  // backward: B[k][n] = W[k][n]
+  // Fills the layout from per-species parameter values P(s) (API order);
+  // put(o, idx, v) stores element idx of the section at byte offset o,
+  // packB(B, K, N, o, part) a B operand, blast(s, v) the output bias;
+  // pad is the value of padded B-operand entries.
+  auto fill = [&](auto P, auto put, auto packB, auto blast, double pad, double shift_scale_mark) {
+    for (int s = 0; s < S; ++s) {
+      size_t po = 0;
+      for (int l = 1; l <= L; ++l) {
+        const int in = c->w[l - 1], out = c->w[l];
+        const size_t wo = po, bo = po + (size_t)out * in;
+        po += (size_t)out * in + out;
+        if (l < L) {
+          const int Kp = c->wp[l - 1], Np = c->wp[l];
+          std::vector<double> Bf((size_t)Kp * Np, pad), Bb((size_t)Np * Kp, pad);
+          for (int q = 0; q < out; ++q)
+            for (int k = 0; k < in; ++k) {
+              Bf[(size_t)k * Np + q] = P(s, wo + (size_t)q * in + k);  // forward: B[k][n] = W[n][k]
+              Bb[(size_t)q * Kp + k] = P(s, wo + (size_t)q * in + k);  // backward: B[k][n] = W[k][n]
+            }
+          packB(Bf.data(), Kp, Np, so[s].wf[l], 0);
+          packB(Bb.data(), Np, Kp, so[s].wb[l], 0);
+          if (pair1 && l == 1) {
+            packB(Bf.data(), Kp, Np, so[s].wf_lo, 1);
+            packB(Bb.data(), Np, Kp, so[s].wb_lo, 1);
           }
-        pack_b_operand(prec, Bf.data(), Kp, Np, Np, host.data() + so[s].wf[l]);
-        pack_b_operand(prec, Bb.data(), Np, Kp, Kp, host.data() + so[s].wb[l]);
-        if (pair1 && l == 1) {
-          pack_b_operand(prec, Bf.data(), Kp, Np, Np, host.data() + so[s].wf_lo, 1);
-          pack_b_operand(prec, Bb.data(), Np, Kp, Kp, host.data() + so[s].wb_lo, 1);
+          for (int q = 0; q < out; ++q) put(so[s].bias[l], q, P(s, bo + q));
+        } else {
+          for (int k = 0; k < in; ++k) put(so[s].wlast, k, P(s, wo + k));
+          blast(s, P(s, bo));
         }
-        for (int q = 0; q < out; ++q) put(so[s].bias[l], q, b[q]);
-      } else {
-        for (int k = 0; k < in; ++k) put(so[s].wlast, k, W[k]);
-        c->mlp.net[s].blast = b[0];
+      }
+      for (int k = 0; k < c->D; ++k) {
+        put(so[s].shift, k, shift_scale_mark < 0 ? shift_scale_mark : c->shift[(size_t)s * c->D + k]);
+        put(so[s].scale, k, shift_scale_mark < 0 ? shift_scale_mark : c->scale[(size_t)s * c->D + k]);
       }
     }
-    for (int k = 0; k < c->D; ++k) {
-      put(so[s].shift, k, c->shift[(size_t)s * c->D + k]);
-      put(so[s].scale, k, c->scale[(size_t)s * c->D + k]);
-    }
-    c->mlp.net[s].e_offset = c->e_off[s];
-  }
+  };
+  std::vector<unsigned char> host(total, 0);
+  double blast_v[kMaxSpecies] = {0};
+  fill([&](int s, size_t k) { return c->params[(size_t)s * c->nps + k]; },
+       [&](size_t o, int idx, double v) {
+         if (el == 8)
+           reinterpret_cast<double*>(host.data() + o)[idx] = v;
+         else
+           reinterpret_cast<float*>(host.data() + o)[idx] = (float)v;
+       },
+       [&](const double* B, int K, int N, size_t o, int part) {
+         pack_b_operand(prec, B, K, N, N, host.data() + o, part);
+       },
+       [&](int s, double v) { blast_v[s] = v; }, 0.0, 0.0);
   TRY(ensure(c, c->netbuf, total));
   HIP_TRY(c, hipMemcpy(c->netbuf.p, host.data(), total, hipMemcpyHostToDevice));
+  TRY(ensure(c, c->d_blast, kMaxSpecies * sizeof(double)));
+  HIP_TRY(c, hipMemcpy(c->d_blast.p, blast_v, kMaxSpecies * sizeof(double), hipMemcpyHostToDevice));
+  TRY(ensure(c, c->d_params, c->params.size() * sizeof(double)));
+  HIP_TRY(c, hipMemcpy(c->d_params.p, c->params.data(), c->params.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+  if (prec != 2 && c->n_pack == 0) {
+    // the element map (built once: the layout depends only on the shapes)
+    std::vector<double> map(total / el, -1.0);
+    fill([&](int s, size_t k) { return (double)((size_t)s * c->nps + k); },
+         [&](size_t o, int idx, double v) { map[o / el + idx] = v; },
+         [&](const double* B, int K, int N, size_t o, int) { pack_b_operand(0, B, K, N, N, map.data() + o / el); },
+         [&](int s, double v) { c->blast_src[s] = (int)v; }, -1.0, -2.0);
+    std::vector<int> imap(map.size());
+    for (size_t k = 0; k < map.size(); ++k) imap[k] = (int)map[k];
+    TRY(ensure(c, c->d_packmap, imap.size() * sizeof(int)));
+    HIP_TRY(c, hipMemcpy(c->d_packmap.p, imap.data(), imap.size() * sizeof(int), hipMemcpyHostToDevice));
+    TRY(ensure(c, c->d_blastsrc, kMaxSpecies * sizeof(int)));
+    HIP_TRY(c, hipMemcpy(c->d_blastsrc.p, c->blast_src, kMaxSpecies * sizeof(int), hipMemcpyHostToDevice));
+    c->n_pack = (int64_t)imap.size();
+  }
   unsigned char* base = c->netbuf.as<unsigned char>();
   for (int s = 0; s < S; ++s) {
     MlpNet& nt = c->mlp.net[s];
@@ -266,6 +308,8 @@ aenet_status pack_networks(aenet_ctx* c) {
     nt.scale = base + so[s].scale;
     nt.wf_lo = pair1 ? base + so[s].wf_lo : nullptr;
     nt.wb_lo = pair1 ? base + so[s].wb_lo : nullptr;
+    nt.blast = c->d_blast.as<double>() + s;
+    nt.e_offset = c->e_off[s];
   }
   return AENET_OK;
 }
@@ -741,6 +785,42 @@ void launch_take(int n, const int* idx, const double* src, double* dst, hipStrea
   if (n > 0) hipLaunchKernelGGL(k_take, dim3((n + 255) / 256), dim3(256), 0, s, n, idx, src, dst);
 }
 
+// parameters (device, API layout) -> the packed network operands: element k
+// of netbuf holds parameter map[k] (-1: zero padding, -2: left as is), and
+// blast[s] the output bias of species s; the same values the host packing
+// writes (a float context rounds to nearest as the host conversion does)
+template <class T>
+__global__ void k_pack_params(int64_t n, const int* map, const double* P, T* out, int S,
+                              const int* blast_src, double* blast) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < S) blast[k] = P[blast_src[k]];
+  if (k >= n) return;
+  const int src = map[k];
+  if (src == -2) return;
+  out[k] = src >= 0 ? (T)P[src] : T(0);
+}
+
+// flags[0] |= 1 if any of x[0..n) is not finite
+__global__ void k_any_nonfinite(int64_t n, const double* x, int* flag) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && !isfinite(x[k])) atomicOr(flag, 1);
+}
+
+// one Adam step (Kingma & Ba 2015) with bias corrections c1 = 1 - beta1^t,
+// c2 = 1 - beta2^t: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// p -= lr (m / c1) / (sqrt(v / c2) + eps)
+__global__ void k_adam(int64_t n, double* p, const double* g, double* m, double* v, double lr, double b1,
+                       double b2, double eps, double c1, double c2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double gk = g[k];
+  const double mk = b1 * m[k] + (1.0 - b1) * gk;
+  const double vk = b2 * v[k] + (1.0 - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  p[k] -= lr * (mk / c1) / (sqrt(vk / c2) + eps);
+}
+
 thread_local std::string g_setup_error;
 
 // ------------------------------------------------------------------ no-allocation workspace
@@ -999,7 +1079,69 @@ int64_t aenet_n_params(const aenet_ctx* c) { return c ? (int64_t)c->S * c->nps :
 
 aenet_status aenet_get_params(aenet_ctx* c, double* params) {
   if (!c || !params) return AENET_E_INVALID;
+  if (c->params_host_stale) {
+    TRY(check_ctx(c));
+    HIP_TRY(c, hipMemcpy(c->params.data(), c->d_params.p, c->params.size() * 8, hipMemcpyDeviceToHost));
+    c->params_host_stale = false;
+  }
   std::memcpy(params, c->params.data(), c->params.size() * 8);
+  return AENET_OK;
+}
+
+aenet_status aenet_set_params_dev(aenet_ctx* c, const double* params, void* stream) {
+  TRY(check_ctx(c));
+  if (!params) return fail(c, AENET_E_INVALID, "params is NULL");
+  if (c->prec == AENET_BF16 || c->n_pack == 0)
+    return fail(c, AENET_E_INVALID, "parameters from device memory need an FP64 or FP32 context");
+  hipStream_t s = pick_stream(c, stream);
+  const int64_t np = (int64_t)c->params.size();
+  TRY(ensure(c, c->d_flags, 16 * 4));
+  int* flag = c->d_flags.as<int>() + 15;
+  HIP_TRY(c, hipMemsetAsync(flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_any_nonfinite, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np, params, flag);
+  int bad = 0;
+  HIP_TRY(c, hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (bad) return fail(c, AENET_E_NONFINITE, "non-finite parameter");
+  c->md_state = false;  // the forces kept from the last MD call belong to the old parameters
+  HIP_TRY(c, hipMemcpyAsync(c->d_params.p, params, np * 8, hipMemcpyDeviceToDevice, s));
+  const int64_t n = std::max<int64_t>(c->n_pack, c->S);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (c->prec == AENET_FP64)
+    hipLaunchKernelGGL(k_pack_params<double>, grid, dim3(256), 0, s, c->n_pack, c->d_packmap.as<int>(),
+                       c->d_params.as<double>(), c->netbuf.as<double>(), c->S, c->d_blastsrc.as<int>(),
+                       c->d_blast.as<double>());
+  else
+    hipLaunchKernelGGL(k_pack_params<float>, grid, dim3(256), 0, s, c->n_pack, c->d_packmap.as<int>(),
+                       c->d_params.as<double>(), c->netbuf.as<float>(), c->S, c->d_blastsrc.as<int>(),
+                       c->d_blast.as<double>());
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->params_host_stale = true;
+  return AENET_OK;
+}
+
+aenet_status aenet_adam_step_dev(int64_t n, double* params, const double* grad, double* m, double* v,
+                                 double lr, double beta1, double beta2, double eps, int64_t step,
+                                 void* stream) {
+  if (n < 0 || (n > 0 && (!params || !grad || !m || !v)) || step < 1 || !(lr >= 0) ||
+      !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return AENET_E_INVALID;
+  if (n == 0) return AENET_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const double c1 = 1.0 - std::pow(beta1, (double)step), c2 = 1.0 - std::pow(beta2, (double)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, params, grad, m, v, lr,
+                     beta1, beta2, eps, c1, c2);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return AENET_E_DEVICE;
+  }
+  return AENET_OK;
+}
+
+aenet_status aenet_set_loss_form(aenet_ctx* c, int form) {
+  if (!c || (form != AENET_LOSS_MEAN_PER_ATOM && form != AENET_LOSS_EQ7)) return AENET_E_INVALID;
+  c->loss_form = form;
   return AENET_OK;
 }
 
@@ -1009,6 +1151,7 @@ aenet_status aenet_set_params(aenet_ctx* c, const double* params) {
   for (size_t k = 0; k < c->params.size(); ++k)
     if (!std::isfinite(params[k])) return fail(c, AENET_E_NONFINITE, "non-finite parameter");
   std::memcpy(c->params.data(), params, c->params.size() * 8);
+  c->params_host_stale = false;
   c->md_state = false;  // the forces kept from the last MD call belong to the old parameters
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return pack_networks(c);
@@ -1413,7 +1556,7 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   // loss terms: tmp[0..n) force part per atom, tmp[n..n+B) energy part per structure
   double* tmp = c->d_tmp.as<double>();
   launch_loss_terms(n, n_struct, c->d_seg.as<int>(), c->d_perm.as<int>(), c->d_F.as<double>(), f_ref,
-                    c->d_estruct.as<double>(), e_ref, c->d_segcount.as<int64_t>(), lambda_f,
+                    c->d_estruct.as<double>(), e_ref, c->d_segcount.as<int64_t>(), lambda_f, c->loss_form,
                     c->d_adj.as<double>(), c->d_eps.as<double>(), tmp, tmp + n, s);
   launch_sum((int64_t)n + n_struct, tmp, c->d_red.as<double>(), loss, s);
   // descriptor JVP along the force adjoint, then double back-propagation
@@ -1444,6 +1587,38 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   TRY(read_flags(c, s, hf));
   TRY(flag_status(c, hf[0]));
   c->counters_clean = true;
+  return AENET_OK;
+}
+
+aenet_status aenet_loss_grad(aenet_ctx* c, int n_struct, const int64_t* offsets, const double* pos,
+                             const int32_t* species, const double* boxes, const uint8_t pbc[3],
+                             const double* e_ref, const double* f_ref, double lambda_f, double* loss,
+                             double* grad) {
+  TRY(check_ctx(c));
+  if (n_struct < 1 || !offsets || offsets[0] != 0 || !pos || !boxes || !e_ref || !f_ref || !loss || !grad)
+    return fail(c, AENET_E_INVALID, "bad arguments");
+  for (int b = 0; b < n_struct; ++b)
+    if (offsets[b + 1] < offsets[b]) return fail(c, AENET_E_INVALID, "structure offsets must not decrease");
+  const int64_t n = offsets[n_struct];
+  if (n < 1) return fail(c, AENET_E_INVALID, "empty batch");
+  for (int64_t k = 0; k < 3 * n; ++k)
+    if (!std::isfinite(pos[k])) return fail(c, AENET_E_NONFINITE, "non-finite position");
+  const size_t np = c->params.size();
+  TRY(ensure(c, c->h_pos, (size_t)n * 24));
+  TRY(ensure(c, c->h_F, (size_t)n * 24));
+  TRY(ensure(c, c->h_E, ((size_t)n_struct + 1 + np) * 8));
+  hipStream_t s = c->stream;
+  double* dE = c->h_E.as<double>();
+  HIP_TRY(c, hipMemcpyAsync(c->h_pos.p, pos, (size_t)n * 24, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_F.p, f_ref, (size_t)n * 24, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(dE, e_ref, (size_t)n_struct * 8, hipMemcpyHostToDevice, s));
+  TRY(aenet_loss_grad_dev(c, n_struct, offsets, c->h_pos.as<double>(), species, boxes, pbc, dE,
+                          c->h_F.as<double>(), lambda_f, dE + n_struct, dE + n_struct + 1, s));
+  double out = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&out, dE + n_struct, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(grad, dE + n_struct + 1, np * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  *loss = out;
   return AENET_OK;
 }
 

@@ -332,9 +332,13 @@ __global__ void k_check_finite(int64_t n, const double* x, int* flags) {
 }
 
 // per-atom loss terms in internal order; f_ref in the caller's order
+// per-atom terms of the training cost and its adjoints: dC/dF (adj) and
+// dC/dE_s of the atom's structure (eps_atom).  form 0: per-atom mean
+// (1/B) sum_s [(dE_s/N_s)^2 + lambda_f/(3 N_s) sum |dF|^2]; form 1: Eq. 7's
+// half sum 1/2 sum_s dE_s^2 + lambda_f/2 sum |dF|^2
 __global__ void k_loss_atoms(int n, int n_struct, const int* seg, const int* perm, const double* F,
                              const double* f_ref, const double* e_struct, const double* e_ref,
-                             const int64_t* seg_count, double lambda_f, double* adj,
+                             const int64_t* seg_count, double lambda_f, int form, double* adj,
                              double* eps_atom, double* floss_atom) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
@@ -343,22 +347,33 @@ __global__ void k_loss_atoms(int n, int n_struct, const int* seg, const int* per
   const double B = (double)n_struct;
   const size_t o = (size_t)perm[p];
   double sq = 0.0;
-  const double c = 2.0 * lambda_f / (3.0 * Ns * B);
+  const double c = form == 0 ? 2.0 * lambda_f / (3.0 * Ns * B) : lambda_f;
   for (int a = 0; a < 3; ++a) {
     const double df = F[3 * (size_t)p + a] - f_ref[3 * o + a];
     adj[3 * (size_t)p + a] = c * df;
     sq += df * df;
   }
-  floss_atom[p] = lambda_f * sq / (3.0 * Ns * B);
-  eps_atom[p] = 2.0 * (e_struct[s] - e_ref[s]) / (Ns * Ns * B);
+  const double de = e_struct[s] - e_ref[s];
+  if (form == 0) {
+    floss_atom[p] = lambda_f * sq / (3.0 * Ns * B);
+    eps_atom[p] = 2.0 * de / (Ns * Ns * B);
+  } else {
+    floss_atom[p] = 0.5 * lambda_f * sq;
+    eps_atom[p] = de;
+  }
 }
 
 __global__ void k_loss_structs(int n_struct, const double* e_struct, const double* e_ref,
-                               const int64_t* seg_count, double* eloss) {
+                               const int64_t* seg_count, int form, double* eloss) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_struct) return;
-  const double de = (e_struct[s] - e_ref[s]) / (double)seg_count[s];
-  eloss[s] = de * de / (double)n_struct;
+  if (form == 0) {
+    const double de = (e_struct[s] - e_ref[s]) / (double)seg_count[s];
+    eloss[s] = de * de / (double)n_struct;
+  } else {
+    const double de = e_struct[s] - e_ref[s];
+    eloss[s] = 0.5 * de * de;
+  }
 }
 
 }  // namespace
@@ -447,14 +462,14 @@ void launch_check_finite(int64_t n, const double* x, int* flags, hipStream_t s) 
 
 void launch_loss_terms(int n, int n_struct, const int* seg, const int* perm, const double* F,
                        const double* f_ref, const double* e_struct, const double* e_ref,
-                       const int64_t* seg_count, double lambda_f, double* adj, double* eps_atom,
-                       double* floss_atom, double* eloss_struct, hipStream_t s) {
+                       const int64_t* seg_count, double lambda_f, int form, double* adj,
+                       double* eps_atom, double* floss_atom, double* eloss_struct, hipStream_t s) {
   if (n > 0)
     hipLaunchKernelGGL(k_loss_atoms, dim3(nblk(n, 256)), dim3(256), 0, s, n, n_struct, seg, perm, F,
-                       f_ref, e_struct, e_ref, seg_count, lambda_f, adj, eps_atom, floss_atom);
+                       f_ref, e_struct, e_ref, seg_count, lambda_f, form, adj, eps_atom, floss_atom);
   if (n_struct > 0)
     hipLaunchKernelGGL(k_loss_structs, dim3(nblk(n_struct, 256)), dim3(256), 0, s, n_struct,
-                       e_struct, e_ref, seg_count, eloss_struct);
+                       e_struct, e_ref, seg_count, form, eloss_struct);
 }
 
 }  // namespace aenet

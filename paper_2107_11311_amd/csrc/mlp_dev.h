@@ -279,6 +279,7 @@ struct MlpConsts {
   typename Mt<PREC>::T bias[kMaxLayers];
   typename Mt<PREC>::T wl[kMaxWidth / 16];
   typename Mt<PREC>::T sc;
+  double blast;  // output-layer bias (parameters may be replaced on the device)
 };
 template <int PREC>
 __device__ __forceinline__ void mlp_consts(const MlpParams& p, const MlpNet& net, int tid, MlpConsts<PREC>& c) {
@@ -294,6 +295,7 @@ __device__ __forceinline__ void mlp_consts(const MlpParams& p, const MlpNet& net
 #pragma unroll
   for (int m = 0; m < kMaxWidth / 16; ++m) c.wl[m] = wl[min((tid & 15) + 16 * m, KL - 1)];
   c.sc = reinterpret_cast<const T*>(net.scale)[min(col, p.w[0] - 1)];
+  c.blast = *net.blast;
 }
 
 // The network phase of a tile.  Stage 0 (the input layer) has its own
@@ -483,7 +485,7 @@ __device__ __forceinline__ void mlp_tile_n(const MlpParams& p, const TileInfo& t
     }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) e += __shfl_xor(e, o, 16);
-    if (c0 == 0 && r < ti.count) p.E[ti.first + r] = (double)e + net.blast + net.e_offset;
+    if (c0 == 0 && r < ti.count) p.E[ti.first + r] = (double)e + kc.blast + net.e_offset;
     if (!p.gG) return;
 #pragma unroll
     for (int m = 0; m < kMaxWidth / 16; ++m) {
