@@ -156,6 +156,13 @@ aenet_status aenet_energy_forces_virial(aenet_ctx* ctx, int64_t n, const double*
                                         const uint8_t pbc[3], double* e_total, double* forces,
                                         double virial[9]);
 
+/* aenet_energy_forces_virial with device pointers (pos, e_total[1] or NULL,
+ * forces or NULL, virial[9]) and a stream. */
+aenet_status aenet_energy_forces_virial_dev(aenet_ctx* ctx, int64_t n, const double* pos,
+                                            const int32_t* species, const double box[3],
+                                            const uint8_t pbc[3], double* e_total, double* forces,
+                                            double* virial, void* stream);
+
 /* Same with device pointers (pos, e_total[1], e_atom, forces) and a stream. */
 aenet_status aenet_energy_forces_dev(aenet_ctx* ctx, int64_t n, const double* pos,
                                      const int32_t* species, const double box[3],

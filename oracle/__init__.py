@@ -276,6 +276,28 @@ def energy_forces_subset(model, pos, species, box, pbc, sel):
     return E, F, G
 
 
+def _subset_worker(args):
+    model, pos, species, box, pbc, sel = args
+    build()
+    return energy_forces_subset(model, pos, species, box, pbc, sel)
+
+
+def energy_forces_subset_parallel(model, pos, species, box, pbc, sel, workers=None):
+    """energy_forces_subset with the selected atoms split over worker
+    processes (each runs the single-threaded oracle on its share); for sampled
+    checks of large structures.  Spawned processes: nothing of the calling
+    process (a GPU runtime, for instance) is inherited."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    sel = np.asarray(sel)
+    workers = max(1, min(workers or 8, sel.size))
+    parts = [p for p in np.array_split(sel, workers) if p.size]
+    with cf.ProcessPoolExecutor(max_workers=len(parts), mp_context=mp.get_context("spawn")) as ex:
+        out = list(ex.map(_subset_worker, [(model, pos, species, box, pbc, p) for p in parts]))
+    return (np.concatenate([o[0] for o in out]), np.vstack([o[1] for o in out]),
+            np.vstack([o[2] for o in out]))
+
+
 def forces_dense(model, pos, species, box, pbc):
     pos, box, pbc = _geom(pos, box, pbc)
     sp = _i32(species)

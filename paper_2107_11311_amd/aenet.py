@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "AENET_OK", -1: "AENET_E_INVALID", -2: "AENET_E_SPECIES", -3:
 # every entry point declared in include/aenet_gpu.h
 EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor_dim", "aenet_n_params",
            "aenet_get_params", "aenet_set_params", "aenet_supported_orders", "aenet_energy_forces",
-           "aenet_energy_forces_virial", "aenet_energy_forces_dev", "aenet_energy_forces_noalloc",
+           "aenet_energy_forces_virial", "aenet_energy_forces_virial_dev", "aenet_energy_forces_dev", "aenet_energy_forces_noalloc",
            "aenet_energy_forces_batch_dev", "aenet_descriptors",
            "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_loss_grad", "aenet_set_loss_form",
            "aenet_set_params_dev", "aenet_adam_step_dev", "aenet_get_stats",
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     L.aenet_supported_orders.argtypes = [_ip, C.c_int]
     L.aenet_energy_forces.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp, _dp, _dp]
     L.aenet_energy_forces_virial.argtypes = [ctxp, C.c_int64, _dp, _ip, _dp, _u8p, _dp, _dp, _dp]
+    L.aenet_energy_forces_virial_dev.argtypes = [ctxp, C.c_int64, _vp, _ip, _dp, _u8p, _vp, _vp, _vp, _vp]
     L.aenet_energy_forces_dev.argtypes = [ctxp, C.c_int64, _vp, _ip, _dp, _u8p, _vp, _vp, _vp, _vp]
     L.aenet_energy_forces_noalloc.argtypes = [ctxp, C.c_int64, _vp, _ip, _dp, _u8p, _vp, _vp, _vp, _vp]
     L.aenet_energy_forces_batch_dev.argtypes = [ctxp, C.c_int, _i64p, _vp, _ip, _dp, _u8p, _vp, _vp,
@@ -298,6 +299,17 @@ class Context:
                                                   _ptr(pbc, _u8p), C.byref(e), _ptr(ea), _ptr(F)))
         return e.value, ea, F
 
+    def energy(self, pos, species, box, pbc=(1, 1, 1)) -> float:
+        """aenet_energy_forces with no per-atom or force output: the force
+        pass is skipped (energy-only evaluation, e.g. for Monte Carlo)."""
+        pos = _f64(pos).reshape(-1, 3)
+        sp = _i32(species)
+        box, pbc = _box(box, pbc)
+        e = C.c_double()
+        self._check(self._lib.aenet_energy_forces(self._h, pos.shape[0], _ptr(pos), _ptr(sp, _ip), _ptr(box),
+                                                  _ptr(pbc, _u8p), C.byref(e), None, None))
+        return e.value
+
     def energy_forces_virial(self, pos, species, box, pbc=(1, 1, 1)):
         """aenet_energy_forces_virial: (E_total, F [n,3], W [3,3]) from host arrays."""
         pos = _f64(pos).reshape(-1, 3)
@@ -357,6 +369,15 @@ class Context:
         self._check(self._lib.aenet_energy_forces_dev(self._h, int(pos.shape[0]), _dev(pos), _ptr(sp, _ip),
                                                       _ptr(box), _ptr(pbc, _u8p), _dev(e_total), _dev(e_atom),
                                                       _dev(forces), _stream(stream)))
+
+    def energy_forces_virial_dev(self, pos, species, box, pbc=(1, 1, 1), e_total=None, forces=None,
+                                 virial=None, stream=None):
+        """aenet_energy_forces_virial_dev: virial (device [9] or [3, 3]) required."""
+        sp = _i32(species)
+        box, pbc = _box(box, pbc)
+        self._check(self._lib.aenet_energy_forces_virial_dev(self._h, int(pos.shape[0]), _dev(pos), _ptr(sp, _ip),
+                                                             _ptr(box), _ptr(pbc, _u8p), _dev(e_total),
+                                                             _dev(forces), _dev(virial), _stream(stream)))
 
     def energy_forces_noalloc(self, pos, species, box, pbc=(1, 1, 1), e_total=None, e_atom=None,
                               forces=None, stream=None):

@@ -1,7 +1,8 @@
-"""Trajectory analysis of the paper's water application (Sec. IV D): the
-diffusion coefficient from the mean-square displacement (Eq. 8), its
+"""Trajectory analysis of the paper's applications (Sec. IV): the diffusion
+coefficient of water from the mean-square displacement (Eq. 8), its
 finite-size correction (Eq. 9) and the direct extrapolation of D(L) against
-1/L.  Host-side numpy over frames written by the MD entry points (positions
+1/L; and the gliding average of the potential energy used to follow the
+equilibration of the Li_xSi nanoparticles.  Host-side numpy over frames written by the MD entry points (positions
 in the caller's order, wrapped into the box on list rebuilds).
 
 Units: positions in A, times in ps, D in A^2/ps, viscosity in Pa s,
@@ -68,3 +69,14 @@ def extrapolate_infinite(box_lengths, d_values):
     inv = 1.0 / np.asarray(box_lengths, dtype=np.float64)
     slope, intercept = np.polyfit(inv, np.asarray(d_values, dtype=np.float64), 1)
     return intercept, slope
+
+
+def gliding_average(values, window: int):
+    """Trailing moving average: out[k] = mean(values[k - window + 1 .. k]) for
+    k >= window - 1 (len(values) - window + 1 entries), the smoothed energy
+    curve of an equilibration run."""
+    x = np.asarray(values, dtype=np.float64)
+    if window < 1 or window > x.size:
+        raise ValueError("window must be 1..len(values)")
+    c = np.concatenate([[0.0], np.cumsum(x)])
+    return (c[window:] - c[:-window]) / window

@@ -1169,6 +1169,17 @@ aenet_status aenet_energy_forces_dev(aenet_ctx* c, int64_t n, const double* pos,
   return ef_core(c, 1, off, pos, species, box, pbc, nullptr, e_total, e_atom, forces, pick_stream(c, stream));
 }
 
+aenet_status aenet_energy_forces_virial_dev(aenet_ctx* c, int64_t n, const double* pos,
+                                            const int32_t* species, const double box[3],
+                                            const uint8_t pbc[3], double* e_total, double* forces,
+                                            double* virial, void* stream) {
+  TRY(check_ctx(c));
+  if (n < 0 || !box || (n > 0 && !pos) || !virial) return fail(c, AENET_E_INVALID, "bad arguments");
+  const int64_t off[2] = {0, n};
+  return ef_core(c, 1, off, pos, species, box, pbc, nullptr, e_total, nullptr, forces, pick_stream(c, stream),
+                 virial);
+}
+
 aenet_status aenet_energy_forces_batch_dev(aenet_ctx* c, int n_struct, const int64_t* offsets,
                                            const double* pos, const int32_t* species,
                                            const double* boxes, const uint8_t pbc[3],

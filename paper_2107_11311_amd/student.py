@@ -9,8 +9,10 @@ MD with the full network, and during production MD the full network re-checks
 the student's forces every few steps and takes over when they drift.
 
 Everything numerical runs through the C ABI (teacher MD, student energies and
-forces, the loss gradient by double back-propagation); torch only holds device
-buffers and applies the Adam update to the flat parameter vector.
+forces, the loss gradient by double back-propagation, the Adam update and the
+repacking of the parameters); torch only holds device buffers and gathers the
+snapshots of a mini-batch.  The final full-batch L-BFGS polish runs SciPy's
+optimiser on the host over the same GPU cost and gradient.
 """
 from __future__ import annotations
 
@@ -81,26 +83,37 @@ class TrainResult:
     losses: List[float] = field(default_factory=list)
     seconds: float = 0.0
     steps: int = 0
+    lbfgs_iterations: int = 0
+    lbfgs_seconds: float = 0.0
+
+
+def _batch_args(snaps: Snapshots, batch: int):
+    n = snaps.pos.shape[1]
+    offs = np.arange(batch + 1, dtype=np.int64) * n
+    species = np.tile(snaps.species, batch)
+    boxes = np.tile(np.asarray(snaps.box, dtype=np.float64).reshape(1, 3), (batch, 1))
+    return offs, species, boxes
 
 
 def train(student, snaps: Snapshots, train_idx: np.ndarray, steps: int, batch: int, lr: float,
           lambda_f: float = 1.0, seed: int = 0, lr_final: Optional[float] = None,
           log_every: int = 0, log: Callable[[str], None] = print) -> TrainResult:
-    """Adam on mini-batches of snapshots; the gradient of the energy+force loss
-    comes from aenet_loss_grad_dev (double back-propagation on the GPU)."""
+    """Adam on mini-batches of snapshots, entirely on the device: the gradient
+    of the energy+force loss from aenet_loss_grad_dev (double
+    back-propagation), the update by aenet_adam_step_dev, the new parameters
+    repacked by aenet_set_params_dev; parameters, moments and gradients never
+    leave the GPU.  The learning rate falls geometrically from lr to lr_final."""
     import torch
+    from . import aenet as A
     dev = snaps.pos.device
     rng = np.random.default_rng(seed)
     n = snaps.pos.shape[1]
     p = torch.from_numpy(student.get_params()).to(dev)
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
-    b1, b2, eps = 0.9, 0.999, 1e-8
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     grad = torch.zeros_like(p)
-    offs = np.arange(batch + 1, dtype=np.int64) * n
-    species = np.tile(snaps.species, batch)
-    boxes = np.tile(np.asarray(snaps.box, dtype=np.float64).reshape(1, 3), (batch, 1))
+    offs, species, boxes = _batch_args(snaps, batch)
     res = TrainResult(p.cpu().numpy())
     t0 = time.perf_counter()
     lr_final = lr if lr_final is None else lr_final
@@ -110,22 +123,42 @@ def train(student, snaps: Snapshots, train_idx: np.ndarray, steps: int, batch: i
         f_ref = snaps.forces.index_select(0, idx).reshape(batch * n, 3).to(torch.float64)
         e_ref = snaps.energy.index_select(0, idx)
         student.loss_grad_dev(offs, pos, species, boxes, snaps.pbc, e_ref, f_ref, lambda_f, loss, grad)
-        # Adam with a geometric learning-rate schedule
         a = lr * (lr_final / lr) ** (it / max(steps - 1, 1))
-        m.mul_(b1).add_(grad, alpha=1 - b1)
-        v.mul_(b2).addcmul_(grad, grad, value=1 - b2)
-        mh = m / (1 - b1 ** (it + 1))
-        vh = v / (1 - b2 ** (it + 1))
-        p.add_(-a * mh / (vh.sqrt() + eps))
-        student.set_params(p.cpu().numpy())
+        A.adam_step_dev(p, grad, m, v, a, 0.9, 0.999, 1e-8, it + 1)
+        student.set_params_dev(p)
         if log_every and (it % log_every == 0 or it == steps - 1):
             res.losses.append(loss.item())
-            log(f"step {it} loss {res.losses[-1]:.4e} lr {a:.2e}")
+            log(f"adam step {it} loss {res.losses[-1]:.4e} lr {a:.2e}")
     torch.cuda.synchronize()
     res.params = p.cpu().numpy()
     res.seconds = time.perf_counter() - t0
     res.steps = steps
     return res
+
+
+def polish_lbfgs(student, snaps: Snapshots, idx: np.ndarray, maxiter: int, lambda_f: float = 1.0,
+                 res: Optional[TrainResult] = None, log: Callable[[str], None] = print) -> TrainResult:
+    """Full-batch L-BFGS (the paper's optimiser, Sec. II C) over the snapshots
+    idx, starting from the student's current parameters; every cost and
+    gradient evaluation is aenet_loss_grad_dev over the whole set."""
+    import torch
+    from .train import fit_lbfgs
+    n = snaps.pos.shape[1]
+    k = len(idx)
+    offs, species, boxes = _batch_args(snaps, k)
+    sel = torch.from_numpy(np.asarray(idx, dtype=np.int64)).to(snaps.pos.device)
+    pos = snaps.pos.index_select(0, sel).reshape(k * n, 3).cpu().numpy()
+    f_ref = snaps.forces.index_select(0, sel).reshape(k * n, 3).to(torch.float64).cpu().numpy()
+    e_ref = snaps.energy.index_select(0, sel).cpu().numpy()
+    r = fit_lbfgs(student, offs, pos, species, boxes, snaps.pbc, e_ref, f_ref, lambda_f=lambda_f,
+                  maxiter=maxiter, history=20, log_every=250, log=log)
+    log(f"lbfgs: loss {r.loss0:.4e} -> {r.loss:.4e} in {r.iterations} iterations ({r.seconds:.1f} s)")
+    out = res if res is not None else TrainResult(r.params)
+    out.params = r.params
+    out.losses.append(r.loss)
+    out.lbfgs_iterations = r.iterations
+    out.lbfgs_seconds = r.seconds
+    return out
 
 
 def force_rmse(ctx, snaps: Snapshots, idx) -> float:

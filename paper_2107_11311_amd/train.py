@@ -33,7 +33,8 @@ class LbfgsResult:
 
 
 def fit_lbfgs(ctx, offsets, pos, species, boxes, pbc, e_ref, f_ref=None, lambda_f: float = 0.0,
-              maxiter: int = 100, history: int = 10, gtol: float = 1e-12) -> LbfgsResult:
+              maxiter: int = 100, history: int = 10, gtol: float = 1e-12, log_every: int = 0,
+              log=print) -> LbfgsResult:
     """Minimises the cost over the batch (offsets [B+1], pos [N,3] and
     species [N] in structure order, boxes [B,3], e_ref [B], f_ref [N,3] or
     None for an energy-only cost) starting from ctx's current parameters,
@@ -62,7 +63,14 @@ def fit_lbfgs(ctx, offsets, pos, species, boxes, pbc, e_ref, f_ref=None, lambda_
     p0 = ctx.get_params()
     l0, g0 = fun(p0)
     t0 = time.perf_counter()
-    res = minimize(fun, p0, jac=True, method="L-BFGS-B",
+    it = [0]
+
+    def progress(_xk):
+        it[0] += 1
+        if log_every and it[0] % log_every == 0:
+            log(f"lbfgs iteration {it[0]}: loss {trace[-1]:.4e} ({time.perf_counter() - t0:.0f} s)")
+
+    res = minimize(fun, p0, jac=True, method="L-BFGS-B", callback=progress,
                    options=dict(maxiter=maxiter, maxcor=history, gtol=gtol, ftol=0.0))
     seconds = time.perf_counter() - t0
     l1, g1 = fun(res.x)  # leaves ctx at the optimiser's result

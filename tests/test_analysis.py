@@ -48,3 +48,51 @@ def test_extrapolation_to_infinite_size():
     d = 0.25 - 0.9 / L
     d_inf, slope = AN.extrapolate_infinite(L, d)
     assert abs(d_inf - 0.25) < 1e-12 and abs(slope + 0.9) < 1e-10
+
+
+def test_gliding_average_against_direct_means():
+    """Every entry is the plain mean of its window; a constant stays constant
+    and a straight line is returned at the window centres."""
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=37)
+    for w in (1, 4, 37):
+        g = AN.gliding_average(x, w)
+        assert g.size == x.size - w + 1
+        np.testing.assert_allclose(g, [x[k - w + 1:k + 1].mean() for k in range(w - 1, x.size)], atol=1e-13)
+    np.testing.assert_allclose(AN.gliding_average(np.full(10, -3.25), 4), -3.25, atol=1e-15)
+    t = np.arange(20.0)
+    np.testing.assert_allclose(AN.gliding_average(2.0 * t + 1.0, 5), 2.0 * (t[4:] - 2.0) + 1.0, atol=1e-12)
+
+
+def test_metropolis_samples_boltzmann_harmonic():
+    """Energy-only Metropolis on independent harmonic degrees of freedom
+    E = k/2 sum x^2 samples the Boltzmann distribution: <x^2> = k_B T / k;
+    a move that lowers the energy is always accepted."""
+    from paper_2107_11311_amd import mc
+    rng = np.random.default_rng(3)
+    k, T = 2.0, 300.0
+    kT = mc.KB_EV * T
+    n, trials = 64, 6000
+    moves = np.zeros((trials, n, 3))
+    which = rng.integers(0, n, size=trials)
+    moves[np.arange(trials), which] = rng.uniform(-0.15, 0.15, size=(trials, 3))
+    u = rng.uniform(size=trials)
+
+    def energy(p):
+        return 0.5 * k * float(np.sum(p * p))
+
+    x, tr = mc.metropolis(energy, np.zeros((n, 3)), T, moves, u)
+    assert 0.3 < tr.acceptance < 0.95
+    x2, tr2 = mc.metropolis(energy, x, T, moves, u)
+    # a second run from equilibrium: average of x^2 over the run
+    xs = x.copy()
+    acc = []
+    for d, uu in zip(moves, u):
+        y = xs + d
+        if energy(y) <= energy(xs) or uu < np.exp(-(energy(y) - energy(xs)) / kT):
+            xs = y
+        acc.append(np.mean(xs * xs))
+    np.testing.assert_allclose(x2, xs, atol=1e-15)
+    assert abs(np.mean(acc) / (kT / k) - 1.0) < 0.15
+    down = mc.metropolis(energy, np.full((n, 3), 0.1), T, [np.full((n, 3), -0.05)], [0.999999])[1]
+    assert down.accepted == [True]
