@@ -96,6 +96,81 @@ def stored_traffic(kernel, workload, precision):
 
 KB_EV = 8.617333262e-5  # Boltzmann constant, eV/K
 
+# The three workloads of the line: water4096 is the headline (value); the
+# 120,000-atom amorphous Li/Si/O box (the full network with three species,
+# orders 18/6 within 8.0/6.5 A, 52-40-40-1, 200 steps of 1 fs) and the
+# 1,000,002-atom water box (the water4096 network) are carried in "modes".
+WORKLOADS = {
+    "water4096": dict(config="water4096", model="water4096", system="water4096",
+                      modes=("fp64", "fp32", "bf16"), steps=1000, oracle="full"),
+    "lisio120k": dict(config="lisio120k", model="lisio120k", system="lisio120k",
+                      modes=("fp64", "bf16"), steps=200, oracle="sampled"),
+    "water1M": dict(config="student", model="water4096", system="student",
+                    modes=("fp64", "fp32"), steps=100, oracle="sampled"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def roofline_of(kt, model, n, n_r, n_a, widths, mode, workload):
+    """Roofline position of the kernel class with the largest total time:
+    algorithmic flops per launch (formula above, measured mean neighbour
+    counts) over its mean launch time from HIP events on the launch stream,
+    against the vector-ALU peak of the descriptor arithmetic's type."""
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms, launches = kt[dom]
+    avg_s = ms / launches * 1e-3
+    fl = algorithmic_flops(dom, model.radial_order, model.angular_order, n_r, n_a, widths) * n
+    peak = FP64_VALU_PEAK if mode == "fp64" else FP32_VALU_PEAK
+    achieved = fl / avg_s
+    steps = max(kt.get("desc_bwd", (0, 1))[1], 1)
+    return dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
+                frac=achieved / peak, traffic=stored_traffic(dom, workload, mode),
+                avg_launch_ms=ms / launches, launches=launches, flops_per_launch=fl,
+                mean_neighbors_radial=n_r, mean_neighbors_angular=n_a,
+                kernel_ms_per_step={k: v[0] / steps for k, v in kt.items()})
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(oracle, model, sysm, res, calls):
+    """The oracle (single-threaded, brute-force neighbours) on the host:
+    energy+force evaluations of the full box (the final positions of every
+    mode, then the initial ones up to `calls`), and the brute-force neighbour
+    search alone, so the two parts of its time are known."""
+    import numpy as np
+    n = sysm.pos.shape[0]
+    times = []
+    for m in res:
+        t0 = time.perf_counter()
+        oracle.energy_forces(model, res[m]["final_pos"], sysm.species, sysm.box, sysm.pbc)
+        times.append(time.perf_counter() - t0)
+    while len(times) < calls:
+        t0 = time.perf_counter()
+        oracle.energy_forces(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
+        times.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    oracle.neighbors(sysm.pos, sysm.box, sysm.pbc, max(model.radial_cutoff, model.angular_cutoff), cap=256)
+    t_nb = time.perf_counter() - t0
+    t_call = float(np.mean(times))
+    return dict(value=n / t_call, unit="atom-steps/s", cores=1, kind="oracle",
+                cpu=cpu_model(), host_threads=os.cpu_count(),
+                seconds_per_step=t_call, neighbor_search_s=t_nb, descriptor_network_force_s=t_call - t_nb,
+                sample=f"{len(times)} single-threaded FP64 oracle energy+force evaluations of the full "
+                       f"{n}-atom water4096 box (brute-force neighbours), {t_call:.2f} s each, of which "
+                       f"{t_nb:.2f} s is the neighbour search; one MD step = one evaluation")
+
 
 def equilibrate(A, model, sysm, vel0, dt, steps, T, chunk=20):
     """Input preparation (untimed): MD under the model with the velocities
@@ -176,11 +251,13 @@ def run_student(args):
     snapshots -> student (orders 6/2, D = 20, 20-16-16-1) trained with the
     library's loss gradient (Adam on the device, then a full-batch L-BFGS
     polish) -> 1,000,002-atom water MD with the teacher as judge every 50
-    steps.  The teacher is the 52-25-25-1 water network whose input layer
-    ignores the descriptor components beyond the student's orders (a function
-    the student can represent; the unrestricted random network depends with
-    full weight on orders up to 16/8, which no 20-dimensional student sees).
-    Prints one JSON line."""
+    steps.  The teacher is the 52-25-25-1 water network reduced to a network
+    of the student's shape on the student's descriptor components (every
+    other weight zero, output rescaled to a force RMS of 1 eV/A): a function
+    the student can represent.  The unreduced random network depends with
+    full weight on orders up to 16/8 and 25 hidden units, which no 20-16-16-1
+    student follows (--control trains against the network reduced to the
+    student's orders only and reports that too).  Prints one JSON line."""
     import numpy as np
     import torch
     from paper_2107_11311_amd import aenet as A
@@ -194,7 +271,7 @@ def run_student(args):
     cfg = I.CONFIGS["water4096"]
     dt = cfg["dt_fs"] * 1e-3
     full_m = I.load_model("water4096")
-    teacher_m = ST.restrict_to_orders(full_m, 6, 2)
+    teacher_m = I.load_model("student_teacher")
     stud_m = I.load_model("student")
     c1 = I.make_system("water4096")
     v0 = I.maxwell_boltzmann(teacher_m.masses[c1.species], cfg["T"], I.seed_for(cfg["cfg"], 2))
@@ -219,6 +296,23 @@ def run_student(args):
     trained = stud_m.with_params(res.params)
     del snaps
     torch.cuda.empty_cache()
+    control = None
+    if args.control:
+        # the same pipeline against the water network reduced to the student's
+        # orders only (all 25 hidden units kept)
+        t2 = A.Context(ST.restrict_to_orders(full_m, 6, 2), "fp64", skin=0.5)
+        sn2 = ST.generate_snapshots(t2, c1, v0, args.snapshots, args.stride, dt)
+        s2 = A.Context(stud_m, args.train_prec, skin=0.5)
+        r2 = ST.train(s2, sn2, train_idx, steps=args.train_steps, batch=args.batch, lr=args.lr,
+                      lr_final=args.lr * 0.05)
+        r2 = ST.polish_lbfgs(s2, sn2, pol, args.lbfgs_iter, res=r2, log=log)
+        control = dict(teacher="water4096 network, first-layer weights beyond orders 6/2 zeroed",
+                       force_rmse_trained=ST.force_rmse(s2, sn2, test_idx),
+                       teacher_force_rms=float(torch.sqrt((sn2.forces[test_idx].to(torch.float64) ** 2)
+                                                          .mean()).item()))
+        log(f"control: {control}")
+        del sn2
+        torch.cuda.empty_cache()
 
     log("building the 1,000,002-atom water box")
     big = I.make_system("student")
@@ -260,8 +354,9 @@ def run_student(args):
         "dtype": "f32 student, f64 teacher",
         "data": "synthetic",
         "config": {"workload": "student: orders 6/2 (D=20), 20-16-16-1 tanh, cutoffs 6.5/4.0 A, trained on "
-                               f"{args.snapshots} snapshots of water4096 teacher MD (teacher: 52-25-25-1 water "
-                               "network restricted to orders 6/2); MD on 333,334 H2O (1,000,002 atoms, 215.24 A), "
+                               f"{args.snapshots} snapshots of water4096 teacher MD (teacher: the 52-25-25-1 water "
+                               "network reduced to a 20-16-16-1 sub-network, force RMS 1 eV/A); MD on 333,334 H2O "
+                               "(1,000,002 atoms, 215.24 A), "
                                "dt 0.25 fs, judge every 50 steps, threshold 3e-2 eV/A",
                    "atoms": n},
         "student": {"force_rmse_untrained": rmse0, "force_rmse_after_adam": rmse_adam, "force_rmse_trained": rmse1,
@@ -276,6 +371,7 @@ def run_student(args):
         "net_gain_vs_teacher_fp64": (n * rep.steps / wall) / (n * args.md_steps / wall_t),
         "atom_steps_per_s": speeds,
         "student_speedup_vs_teacher": speeds["student_fp32"] / speeds["teacher_fp64"],
+        "control_orders_only_teacher": control,
     }
     print(json.dumps(line))
 
@@ -305,7 +401,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--modes", default="fp64,fp32,bf16")
+    ap.add_argument("--modes", default="fp64,fp32,bf16", help="modes of the water4096 workload")
+    ap.add_argument("--workloads", default="water4096,lisio120k,water1M",
+                    help="water4096 (the headline), lisio120k (120,000-atom Li/Si/O), water1M "
+                         "(1,000,002-atom water with the water4096 network)")
+    ap.add_argument("--big-steps", type=int, default=0,
+                    help="timed steps of the two large workloads (0: their specified counts)")
+    ap.add_argument("--sample-atoms", type=int, default=64,
+                    help="atoms checked against the oracle in the large workloads")
     ap.add_argument("--equil", type=int, default=4000,
                     help="equilibration steps (velocity rescaling to 300 K) before the extra "
                          "'fp64_equilibrated' run; 0 skips that run")
@@ -323,7 +426,9 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lbfgs-snaps", type=int, default=48)
     ap.add_argument("--train-prec", default="fp32", help="arithmetic of the student's training context")
-    ap.add_argument("--lbfgs-iter", type=int, default=400)
+    ap.add_argument("--control", action="store_true",
+                    help="also train against the teacher reduced to the student's orders only")
+    ap.add_argument("--lbfgs-iter", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--md-steps", type=int, default=500)
     ap.add_argument("--speed-steps", type=int, default=50)
@@ -351,97 +456,86 @@ def main():
     from paper_2107_11311_amd import aenet as A
     from paper_2107_11311_amd import inputs as I
 
-    cfg = I.CONFIGS[WORKLOAD]
-    model = I.load_model(WORKLOAD)
-    sysm = I.make_system(WORKLOAD)
-    n = sysm.pos.shape[0]
-    vel0 = I.maxwell_boltzmann(model.masses[sysm.species], cfg["T"], I.seed_for(cfg["cfg"], 2))
-    dt = cfg["dt_fs"] * 1e-3
     A.load()
-
-    # the workload as specified: Maxwell-Boltzmann velocities at 300 K on the
-    # synthetic structure, then NVE
-    modes = [m for m in args.modes.split(",") if m]
-    res = {}
-    for m in modes:
-        res[m] = run_mode(A, model, sysm, vel0, m, args.steps, args.warmup, dt, profile=(m == "fp64"))
-    # extra: the same FP64 path from an equilibrated state (the random-weight
-    # network heats the synthetic structure far above 300 K in NVE, which makes
-    # the neighbour list rebuild every few steps)
-    if args.equil > 0 and "fp64" in modes:
-        pos_eq, vel_eq = equilibrate(A, model, sysm, vel0, dt, args.equil, cfg["T"])
-        sys_eq = I.System(pos_eq, sysm.species, sysm.box, sysm.pbc)
-        res["fp64_equilibrated"] = run_mode(A, model, sys_eq, vel_eq, "fp64", args.steps, args.warmup, dt,
-                                            profile=False)
-    main_mode = "fp64" if "fp64" in res else modes[0]
-    r = res[main_mode]
-    vir = virial_timing(A, model, sysm) if "fp64" in modes and not args.no_virial else None
-
-    # roofline of the dominant kernel of the FP64 path
-    roofline = None
-    if "kernel_times" in r:
-        kt = r["kernel_times"]
-        dom = max(kt, key=lambda k: kt[k][0])
-        ms, launches = kt[dom]
-        avg_s = ms / launches * 1e-3
+    wanted = [w for w in args.workloads.split(",") if w]
+    out_modes = {}
+    rooflines = {}
+    cpu = None
+    headline = None
+    virial = None
+    for wl in wanted:
+        spec = WORKLOADS[wl]
+        cfg = I.CONFIGS[spec["config"]]
+        model = I.load_model(spec["model"])
+        sysm = I.make_system(spec["system"])
+        n = sysm.pos.shape[0]
+        vel0 = I.maxwell_boltzmann(model.masses[sysm.species], cfg["T"], I.seed_for(cfg["cfg"], 2))
+        dt = cfg["dt_fs"] * 1e-3
+        steps = args.steps if wl == WORKLOAD else (args.big_steps or spec["steps"])
+        warm = args.warmup
+        modes = [m for m in (args.modes.split(",") if wl == WORKLOAD else spec["modes"]) if m]
+        log(f"{wl}: {n} atoms, modes {modes}, {steps} steps")
+        res = {m: run_mode(A, model, sysm, vel0, m, steps, warm, dt, profile=True) for m in modes}
+        if wl == WORKLOAD and args.equil > 0 and "fp64" in modes:
+            pos_eq, vel_eq = equilibrate(A, model, sysm, vel0, dt, args.equil, cfg["T"])
+            sys_eq = I.System(pos_eq, sysm.species, sysm.box, sysm.pbc)
+            res["fp64_equilibrated"] = run_mode(A, model, sys_eq, vel_eq, "fp64", steps, warm, dt, profile=False)
         n_r, n_a = mean_counts(sysm.pos, sysm.box, model.radial_cutoff, model.angular_cutoff)
         widths = [model.D] + [w.shape[0] for w in model.nets[0].W]
-        fl = algorithmic_flops(dom, model.radial_order, model.angular_order, n_r, n_a, widths) * n
-        achieved = fl / avg_s
-        roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=FP64_VALU_PEAK / 1e12,
-                        unit="TFLOP/s", frac=achieved / FP64_VALU_PEAK,
-                        traffic=stored_traffic(dom, WORKLOAD, main_mode),
-                        avg_launch_ms=ms / launches, launches=launches,
-                        flops_per_launch=fl, mean_neighbors_radial=n_r, mean_neighbors_angular=n_a,
-                        kernel_ms_per_step={k: v[0] / max(v[1], 1) * (v[1] / args.steps)
-                                            for k, v in kt.items()})
-
-    # oracle on the host: its throughput, and the force RMSE of every mode
-    cpu = None
-    modes_out = {}
-    if not args.no_cpu_baseline:
-        import oracle
-        oracle.build()
-        times = []
-        ref = {}
-        for m in res:
-            t0 = time.perf_counter()
-            E0, _, F0 = oracle.energy_forces(model, res[m]["final_pos"], sysm.species, sysm.box, sysm.pbc)
-            times.append(time.perf_counter() - t0)
-            ref[m] = (E0, F0)
-        while len(times) < args.cpu_sample_calls:
-            t0 = time.perf_counter()
-            oracle.energy_forces(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
-            times.append(time.perf_counter() - t0)
-        t_call = float(np.mean(times))
-        cpu = dict(value=n / t_call, unit="atom-steps/s", cores=1, kind="oracle",
-                   sample=f"{len(times)} single-threaded FP64 oracle energy+force evaluations of the full "
-                          f"{n}-atom box (brute-force neighbours), {t_call:.2f} s each; one MD step = one "
-                          f"evaluation")
-        for m in res:
-            E0, F0 = ref[m]
-            dF = res[m]["final_F"] - F0
-            modes_out[m] = dict(atom_steps_per_s=res[m]["atom_steps_per_s"],
-                                ms_per_step=res[m]["ms_per_step"],
-                                force_rmse=float(np.sqrt(np.mean(dF ** 2))),
-                                force_rms=float(np.sqrt(np.mean(F0 ** 2))),
-                                energy_rel_err=abs(res[m]["final_E"] - E0) / abs(E0),
-                                nve_drift_ev_per_atom=(res[m]["e_total_end"] - res[m]["e_total_start"]) / n,
-                                temperature_end_K=res[m]["t_end"], rebuilds=res[m]["rebuilds"])
-    else:
-        for m in res:
-            modes_out[m] = dict(atom_steps_per_s=res[m]["atom_steps_per_s"], ms_per_step=res[m]["ms_per_step"])
-    virial = None
-    if vir is not None:
-        virial = dict(ms_per_call=vir["ms_per_call"], ms_per_call_forces_only=vir["ms_per_call_forces_only"],
-                      W_eV=vir["W"].tolist(),
-                      note="aenet_energy_forces_virial vs aenet_energy_forces, host buffers in and out, "
-                           "water4096 initial positions, FP64")
+        for m, r in res.items():
+            key = f"{wl}/{m}"
+            entry = dict(atoms=n, steps=steps, atom_steps_per_s=r["atom_steps_per_s"], ms_per_step=r["ms_per_step"],
+                         rebuilds=r["rebuilds"], temperature_end_K=r["t_end"],
+                         nve_drift_ev_per_atom=(r["e_total_end"] - r["e_total_start"]) / n)
+            if "kernel_times" in r:
+                entry["roofline"] = roofline_of(r["kernel_times"], model, n, n_r, n_a, widths, m, wl)
+                rooflines[key] = entry["roofline"]
+            out_modes[key] = entry
+        # oracle: force RMSE on the final positions (all atoms for the small box,
+        # sampled atoms of the large ones)
         if not args.no_cpu_baseline:
             import oracle
-            _, _, W0 = oracle.energy_forces_virial(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
-            virial["max_rel_err_vs_oracle"] = float(np.abs(vir["W"] - W0).max() / np.abs(W0).max())
+            oracle.build()
+            for m, r in res.items():
+                if spec["oracle"] == "full":
+                    E0, _, F0 = oracle.energy_forces(model, r["final_pos"], sysm.species, sysm.box, sysm.pbc)
+                    dF = r["final_F"] - F0
+                    out_modes[f"{wl}/{m}"].update(force_rmse=float(np.sqrt(np.mean(dF ** 2))),
+                                                  force_max_abs_err=float(np.abs(dF).max()),
+                                                  force_rms=float(np.sqrt(np.mean(F0 ** 2))),
+                                                  energy_rel_err=abs(r["final_E"] - E0) / abs(E0))
+                else:
+                    sel = np.random.default_rng(5).choice(n, args.sample_atoms, replace=False)
+                    Ea0, F0, _ = oracle.energy_forces_subset_parallel(model, r["final_pos"], sysm.species,
+                                                                      sysm.box, sysm.pbc, sel,
+                                                                      min(16, os.cpu_count() or 1))
+                    dF = r["final_F"][sel] - F0
+                    out_modes[f"{wl}/{m}"].update(force_rmse_sampled=float(np.sqrt(np.mean(dF ** 2))),
+                                                  force_max_abs_err_sampled=float(np.abs(dF).max()),
+                                                  force_rms_sampled=float(np.sqrt(np.mean(F0 ** 2))),
+                                                  sampled_atoms=int(sel.size))
+            if wl == WORKLOAD:
+                cpu = cpu_baseline(oracle, model, sysm, res, args.cpu_sample_calls)
+        if wl == WORKLOAD:
+            main_mode = "fp64" if "fp64" in res else modes[0]
+            headline = (res[main_mode], main_mode, model, sysm)
+            if "fp64" in modes and not args.no_virial:
+                vir = virial_timing(A, model, sysm)
+                virial = dict(ms_per_call=vir["ms_per_call"], ms_per_call_forces_only=vir["ms_per_call_forces_only"],
+                              W_eV=vir["W"].tolist(),
+                              note="aenet_energy_forces_virial vs aenet_energy_forces, host buffers in and out, "
+                                   "water4096 initial positions, FP64")
+                if not args.no_cpu_baseline:
+                    import oracle
+                    _, _, W0 = oracle.energy_forces_virial(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
+                    virial["max_rel_err_vs_oracle"] = float(np.abs(vir["W"] - W0).max() / np.abs(W0).max())
+        del sysm
+        torch.cuda.empty_cache()
 
+    if headline is None:
+        print(json.dumps({"modes": out_modes}))
+        return
+    r, main_mode, model, sysm = headline
     line = {
         "metric": "atom-steps/s (energy+forces) on 1 MI355X; force RMSE vs FP64 oracle",
         "value": r["atom_steps_per_s"],
@@ -459,9 +553,9 @@ def main():
                                "radial order 16 / 6.5 A, angular order 8 / 4.0 A (D=52); 52-25-25-1 tanh; "
                                "NVE velocity Verlet from Maxwell-Boltzmann velocities at 300 K, dt 0.25 fs, "
                                "skin 0.5 A",
-                   "atoms": n, "mode": main_mode},
-        "modes": modes_out,
-        "roofline": roofline,
+                   "atoms": int(sysm.pos.shape[0]), "mode": main_mode},
+        "modes": out_modes,
+        "roofline": rooflines.get(f"{WORKLOAD}/{main_mode}"),
         "cpu_baseline": cpu,
         "virial": virial,
     }

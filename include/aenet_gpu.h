@@ -296,6 +296,22 @@ aenet_status aenet_set_rebuild_every(aenet_ctx* ctx, int rebuild_every);
  * 64 KiB of LDS per tile), or as two kernels (enable = 0).  The results are
  * bitwise the same.  Default: 1. */
 aenet_status aenet_set_fused(aenet_ctx* ctx, int enable);
+/* How the angular terms of Eq. 6 are evaluated.  AENET_ANGULAR_PAIRS: the
+ * sum over pairs of angular neighbours as written (cost ~ n_a^2 per atom).
+ * AENET_ANGULAR_FACTORISED: T_a expanded in Legendre polynomials and each
+ * P_l(cos theta_jk) split by the addition theorem into products of functions
+ * of u_j and of u_k, so the pair sum becomes squares of single sums over the
+ * neighbours minus the j = k terms (cost ~ n_a (N_a + 1)^2 per atom; angular
+ * orders 2, 3, 4, 6 and 8).  The results are the same up to rounding.
+ * AENET_ANGULAR_AUTO (default): factorised when more than 48 neighbours are
+ * expected within R_a. */
+typedef enum {
+  AENET_ANGULAR_AUTO = 0,
+  AENET_ANGULAR_PAIRS = 1,
+  AENET_ANGULAR_FACTORISED = 2
+} aenet_angular_method;
+aenet_status aenet_set_angular_method(aenet_ctx* ctx, int method);
+
 /* Neighbour-row capacities used from the next call on: row_capacity entries
  * per atom within R_r + skin, ang_capacity of them within R_a + skin
  * (1 <= ang_capacity <= row_capacity, ang_capacity <= 700, row_capacity <=

@@ -20,6 +20,7 @@ AENET_OK, AENET_E_INVALID, AENET_E_SPECIES, AENET_E_BOX = 0, -1, -2, -3
 AENET_E_OVERLAP, AENET_E_NONFINITE, AENET_E_DEVICE, AENET_E_OOM = -4, -5, -6, -7
 AENET_FP64, AENET_FP32, AENET_BF16 = 0, 1, 2
 AENET_LOSS_MEAN_PER_ATOM, AENET_LOSS_EQ7 = 0, 1
+ANGULAR_METHODS = {"auto": 0, "pairs": 1, "factorised": 2}
 PRECISIONS = {"fp64": AENET_FP64, "fp32": AENET_FP32, "bf16": AENET_BF16}
 STATUS_NAMES = {0: "AENET_OK", -1: "AENET_E_INVALID", -2: "AENET_E_SPECIES", -3: "AENET_E_BOX",
                 -4: "AENET_E_OVERLAP", -5: "AENET_E_NONFINITE", -6: "AENET_E_DEVICE", -7: "AENET_E_OOM"}
@@ -31,7 +32,7 @@ EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor
            "aenet_energy_forces_batch_dev", "aenet_descriptors",
            "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_loss_grad", "aenet_set_loss_form",
            "aenet_set_params_dev", "aenet_adam_step_dev", "aenet_get_stats",
-           "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_profiling", "aenet_get_kernel_times"]
+           "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_angular_method", "aenet_set_profiling", "aenet_get_kernel_times"]
 KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate", "fwd_network"]
 
 
@@ -124,6 +125,7 @@ def load(path: str = LIB_PATH):
     L.aenet_set_rebuild_every.argtypes = [ctxp, C.c_int]
     L.aenet_set_capacity.argtypes = [ctxp, C.c_int, C.c_int]
     L.aenet_set_fused.argtypes = [ctxp, C.c_int]
+    L.aenet_set_angular_method.argtypes = [ctxp, C.c_int]
     L.aenet_set_profiling.argtypes = [ctxp, C.c_int]
     L.aenet_get_kernel_times.argtypes = [ctxp, _dp, _i64p]
     for name in EXPORTS:
@@ -270,6 +272,10 @@ class Context:
     def set_fused(self, on: bool) -> None:
         """Descriptor forward pass and networks in one kernel (default) or two."""
         self._check(self._lib.aenet_set_fused(self._h, 1 if on else 0))
+
+    def set_angular_method(self, method: str) -> None:
+        """'auto', 'pairs' (Eq. 6 as a pair sum) or 'factorised' (addition theorem)."""
+        self._check(self._lib.aenet_set_angular_method(self._h, ANGULAR_METHODS[method]))
 
     def set_capacity(self, row: int, ang: int) -> None:
         """Starting neighbour-row capacities (0, 0: estimate from the density)."""

@@ -147,6 +147,13 @@ struct DescParams {
   double* Fself;         // [n*3]  sum_e dE_i/dd_e
   double* vir;           // [9][n] per-atom virial -sum_e (dE_i/dd_e)_a (d_e)_b
                          // (component 3a+b at vir[(3a+b) n + i]); NULL: none
+  // factorised angular descriptor (angular.hip): t1 = N_r + 1 (first angular
+  // component of G), t2 = N_r + N_a + 2 (offset of the weighted half);
+  // shA [n x 2 (N_a+1)^2] the per-atom sums of the forward pass; gang
+  // [n x cap_ang x 3] the angular part of dE_i/dd_e per angular row position
+  int t1, t2;
+  void* shA;
+  void* gang;
   const double* adj;     // [n*3] JVP direction (loss adjoint of the forces)
   void* U;               // [n x ldG] JVP output
   int* flags;
@@ -157,8 +164,15 @@ struct DescParams {
 bool fits_one_round(const void* kernel, int threads, size_t lds, int grid);
 bool desc_supported(int nr, int na);
 int desc_supported_list(int* orders, int max_pairs);
-void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s);
-void launch_desc_bwd(int prec, int nr, int na, const DescParams& p, hipStream_t s);
+// angular: false = the radial terms only (the angular components of G are
+// written as zero, for the factorised angular kernel to fill);
+// ang_ext: the angular part of each entry's gradient is read from p.gang
+void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s, bool angular = true);
+void launch_desc_bwd(int prec, int nr, int na, const DescParams& p, hipStream_t s, bool ang_ext = false);
+// factorised angular descriptor: fwd = the sums and G's angular components,
+// else the angular entry gradients (p.gang); false if na is not compiled in
+bool launch_ang_sh(bool fwd, int prec, int na, const DescParams& p, hipStream_t s);
+size_t ang_sh_terms(int na);
 void launch_desc_jvp(int prec, int nr, int na, const DescParams& p, hipStream_t s);
 
 // ---------------------------------------------------------------- networks

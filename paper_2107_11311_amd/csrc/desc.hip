@@ -21,7 +21,7 @@ namespace aenet {
 
 namespace {
 // ------------------------------------------------------------------ forward
-template <typename R, int NR, int NA, int LPA>
+template <typename R, int NR, int NA, int LPA, bool ANG>
 __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (p.prio) __builtin_amdgcn_s_setprio(3);
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
   const int i = blockIdx.x * apb + g;
   const bool active = i < p.n;
   R* G = reinterpret_cast<R*>(p.G) + (size_t)(active ? i : 0) * p.ldG;
-  desc_fwd_group<R, NR, NA, LPA>(p, i, active, g, l, smem, [&](int c, R v) { G[c] = v; });
+  auto out = [&](int c, R v) { G[c] = v; };
+  desc_fwd_group<R, NR, NA, LPA, decltype(out)&, ANG>(p, i, active, g, l, smem, out);
 }
 
 // ------------------------------------------------------------------ backward
@@ -52,7 +53,9 @@ __host__ __device__ constexpr size_t bwd_coef_offset(int ca) {
 //     gradient of the entry and writing pg.
 // VIR: also the atom's virial -sum_e (dE_i/dd_e) d_e^T (a separate
 // instance, so that the force pass of MD keeps its registers).
-template <typename R, int NR, int NA, bool VIR>
+// AEXT: the angular part of every entry's gradient comes from p.gang (the
+// factorised angular kernel), so the compaction and the pair loop are skipped.
+template <typename R, int NR, int NA, bool VIR, bool AEXT>
 __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   // one wavefront per block and atom; the launch covers exactly the n atoms,
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
 
   // compact the entries within R_a (lanes past the end reread the last one)
   int nv = 0;
-  for (int base = 0; base < na; base += 64) {
+  for (int base = 0; !AEXT && base < na; base += 64) {
     const int e = base + l;
     const NbrLoad nl = load_nbr(p, row[min(e, na - 1)]);
     double d0, d1, d2;
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   __syncthreads();
 
   // angular terms: d/dd_k of sum over ordered pairs = 2 x the unordered pairs
-  {
+  if (!AEXT) {
     R ga[NA + 1], gw[NA + 1];
 #pragma unroll
     for (int a = 0; a <= NA; ++a) {
@@ -309,7 +312,14 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
     cheb_series_tab<R, NR>(cq, x, &S, &dS);
     const R sc = mq * (dS * inv_rr2 * fc + S * fcp) * ir;
     R px = sc * dx, py = sc * dy, pz = sc * dz;
-    if (he && e < na) {
+    if (AEXT) {
+      if (he && e < na) {
+        const R* ga = reinterpret_cast<const R*>(p.gang) + ((size_t)i * p.cap_ang + e) * 3;
+        px += ga[0];
+        py += ga[1];
+        pz += ga[2];
+      }
+    } else if (he && e < na) {
       const int ka = kidx[e];
       if (ka >= 0) {
         px += gx[ka];
@@ -549,7 +559,7 @@ enum Kind { FWD = 0, BWD = 1, JVP = 2 };
 constexpr int lds_words(int kind) { return kind == FWD ? 5 : (kind == BWD ? 10 : 11); }
 
 template <typename R, int NR, int NA, int LPA>
-void launch_kind(int kind, const DescParams& p, hipStream_t s) {
+void launch_kind(int kind, const DescParams& p, hipStream_t s, bool ang) {
   // atoms per block: as many as keep LDS <= 64 KiB and the block <= 256 lanes
   const size_t per_atom = (size_t)p.cap_ang * (lds_words(kind) * sizeof(R) + (kind == BWD ? sizeof(int) : 0));
   int apb = 256 / LPA;
@@ -557,10 +567,15 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
   const size_t lds = (size_t)apb * per_atom;
   const int blocks = (p.n + apb - 1) / apb;
   const dim3 grid(blocks), block(apb * LPA);
-  if (kind == FWD) {
+  if (kind == FWD && ang) {
     DescParams q = p;
-    q.prio = fits_one_round(reinterpret_cast<const void*>(&k_desc_fwd<R, NR, NA, LPA>), apb * LPA, lds, blocks);
-    hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA>), grid, block, lds, s, q);
+    q.prio = fits_one_round(reinterpret_cast<const void*>(&k_desc_fwd<R, NR, NA, LPA, true>), apb * LPA, lds,
+                            blocks);
+    hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA, true>), grid, block, lds, s, q);
+  } else if (kind == FWD) {
+    DescParams q = p;
+    q.prio = 0;
+    hipLaunchKernelGGL((k_desc_fwd<R, NR, NA, LPA, false>), grid, block, 0, s, q);
   } else {
     hipLaunchKernelGGL((k_desc_jvp<R, NR, NA, LPA>), grid, block, lds, s, p);
   }
@@ -569,36 +584,40 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s) {
 // the force pass: one wavefront per atom and per block (single-wave blocks
 // schedule with the finest grain: measured ~2 % faster than four per block)
 template <typename R, int NR, int NA>
-void launch_bwd(const DescParams& p, hipStream_t s) {
+void launch_bwd(const DescParams& p, hipStream_t s, bool ext) {
   const size_t per_atom = (bwd_coef_offset<R>(p.cap_ang) + (size_t)p.n_species * (NR + 1)) * sizeof(R);
-  if (p.vir)
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true>), dim3(p.n), dim3(64), per_atom, s, p);
+  if (p.vir && ext)
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, true>), dim3(p.n), dim3(64), per_atom, s, p);
+  else if (p.vir)
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, false>), dim3(p.n), dim3(64), per_atom, s, p);
+  else if (ext)
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false, true>), dim3(p.n), dim3(64), per_atom, s, p);
   else
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false>), dim3(p.n), dim3(64), per_atom, s, p);
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false, false>), dim3(p.n), dim3(64), per_atom, s, p);
 }
 
 template <typename R, int NR, int NA>
-void launch_orders(int kind, const DescParams& p, hipStream_t s) {
+void launch_orders(int kind, const DescParams& p, hipStream_t s, bool flag) {
   // Lanes per atom from the expected number of angular neighbours within R_a:
   // narrow groups keep the cross-lane reductions short for sparse shells
   // (water: ~30), wide ones give crowded shells (dense amorphous: ~110)
   // enough lanes.  The force pass takes a wavefront per atom.
   if (kind == BWD) {
-    launch_bwd<R, NR, NA>(p, s);
+    launch_bwd<R, NR, NA>(p, s, flag);
     return;
   }
   const int na = p.ang_hint > 0 ? p.ang_hint : p.cap_ang;
   if (na > 48)
-    launch_kind<R, NR, NA, 64>(kind, p, s);
+    launch_kind<R, NR, NA, 64>(kind, p, s, kind != FWD || flag);
   else
-    launch_kind<R, NR, NA, 16>(kind, p, s);
+    launch_kind<R, NR, NA, 16>(kind, p, s, kind != FWD || flag);
 }
 
 template <typename R>
-bool dispatch(int kind, int nr, int na, const DescParams& p, hipStream_t s) {
+bool dispatch(int kind, int nr, int na, const DescParams& p, hipStream_t s, bool flag) {
 #define AENET_CASE(A, B)                       \
   if (nr == A && na == B) {                    \
-    launch_orders<R, A, B>(kind, p, s);        \
+    launch_orders<R, A, B>(kind, p, s, flag);  \
     return true;                               \
   }
   AENET_ORDERS(AENET_CASE)
@@ -606,12 +625,12 @@ bool dispatch(int kind, int nr, int na, const DescParams& p, hipStream_t s) {
   return false;
 }
 
-void launch_any(int kind, int prec, int nr, int na, const DescParams& p, hipStream_t s) {
+void launch_any(int kind, int prec, int nr, int na, const DescParams& p, hipStream_t s, bool flag) {
   if (p.n <= 0) return;
   if (prec == 0)
-    dispatch<double>(kind, nr, na, p, s);
+    dispatch<double>(kind, nr, na, p, s, flag);
   else
-    dispatch<float>(kind, nr, na, p, s);
+    dispatch<float>(kind, nr, na, p, s, flag);
 }
 
 }  // namespace
@@ -661,14 +680,14 @@ int desc_supported_list(int* orders, int max_pairs) {
   return k;
 }
 
-void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s) {
-  launch_any(FWD, prec, nr, na, p, s);
+void launch_desc_fwd(int prec, int nr, int na, const DescParams& p, hipStream_t s, bool angular) {
+  launch_any(FWD, prec, nr, na, p, s, angular);
 }
-void launch_desc_bwd(int prec, int nr, int na, const DescParams& p, hipStream_t s) {
-  launch_any(BWD, prec, nr, na, p, s);
+void launch_desc_bwd(int prec, int nr, int na, const DescParams& p, hipStream_t s, bool ang_ext) {
+  launch_any(BWD, prec, nr, na, p, s, ang_ext);
 }
 void launch_desc_jvp(int prec, int nr, int na, const DescParams& p, hipStream_t s) {
-  launch_any(JVP, prec, nr, na, p, s);
+  launch_any(JVP, prec, nr, na, p, s, true);
 }
 
 }  // namespace aenet

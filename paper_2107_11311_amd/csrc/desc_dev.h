@@ -263,7 +263,9 @@ __device__ inline void cheb_series_tab(const R* c, R x, R* S, R* dS) {
 // the group's compaction buffers are at smem + g * 5 * cap_ang elements.  Every
 // group of the block must call it (it holds a block barrier).  The G
 // components are handed to out(c, value) (c < D, one lane per component).
-template <typename R, int NR, int NA, int LPA, typename Out>
+// ANG = false: the radial terms only (the angular components are handed out
+// as zero, for the factorised angular kernel to overwrite).
+template <typename R, int NR, int NA, int LPA, typename Out, bool ANG = true>
 __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, int g, int l,
                                       unsigned char* smem, Out&& out) {
   R* ux = reinterpret_cast<R*>(smem) + (size_t)g * p.cap_ang * 5;
@@ -372,7 +374,7 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
 
   // compact the angular entries into LDS
   int nv = 0;
-  for (int base = 0; base < na; base += LPA) {
+  for (int base = 0; ANG && base < na; base += LPA) {
     const int e = base + l;
     bool valid = false;
     R vx = 0, vy = 0, vz = 0, vf = 0, vw = 0;
@@ -404,7 +406,7 @@ __device__ inline void desc_fwd_group(const DescParams& p, int i, bool active, i
     }
     nv += __popcll(m);
   }
-  __syncthreads();
+  if (ANG) __syncthreads();
 
   // angular terms, Eq. 6, over the unordered pairs {e, (e + t) mod nv},
   // t = 1..floor(nv/2) (for even nv the pairs at t = nv/2 are counted from

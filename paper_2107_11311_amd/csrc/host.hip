@@ -97,6 +97,7 @@ struct aenet_ctx {
   // blocks' descriptor work, so two kernels are as fast
   bool fused = true;
   int ang_mean = 0;  // expected mean number of neighbours within R_a (densest structure)
+  int ang_method = 0;  // AENET_ANGULAR_*: pair sums, factorised, or chosen by the shell size
   bool nbr_valid = false;
   // the cell counters and the build's block counter are zero (what a build
   // expects; every successful call leaves them so)
@@ -115,6 +116,7 @@ struct aenet_ctx {
   DevMem d_cell_count, d_cell_start, d_cell_fill, d_cell_atoms, d_atom_cell, d_nbr, d_segs, d_nnb, d_nang, d_rev;
   DevMem d_bin_count, d_bin_atoms;  // MD: cell bins filled by the integrator
   DevMem d_ridx, d_nrad;            // contributing entries, from the forward pass
+  DevMem d_shA, d_gang;             // factorised angular descriptor: per-atom sums, entry gradients
   DevMem d_vir;                     // [9][n] per-atom virial, then its 9 sums
   bool want_vir = false;            // the next force pass also forms the virial
   DevMem d_build;  // [2] ints: decision of the current build, block counter
@@ -604,7 +606,22 @@ DescParams desc_params(aenet_ctx* c) {
   p.adj = c->d_adj.as<double>();
   p.U = c->d_U.p;
   p.flags = c->d_flags.as<int>();
+  p.t1 = c->nr + 1;
+  p.t2 = c->nr + c->na + 2;
+  p.shA = c->d_shA.p;
+  p.gang = c->d_gang.p;
   return p;
+}
+
+// The angular descriptor by its factorised form (angular.hip) where the
+// expected angular shell is crowded (more than 48 neighbours within R_a: its
+// cost grows with the shell size, the pair sum's with its square), or as the
+// caller chose.
+bool use_factorised(const aenet_ctx* c) {
+  const bool ok = c->na == 2 || c->na == 3 || c->na == 4 || c->na == 6 || c->na == 8;
+  if (c->ang_method == AENET_ANGULAR_PAIRS || !ok) return false;
+  if (c->ang_method == AENET_ANGULAR_FACTORISED) return true;
+  return c->ang_mean > 48;
 }
 
 MlpParams mlp_params(aenet_ctx* c, bool want_grad) {
@@ -714,9 +731,23 @@ void build_neighbors_timed(aenet_ctx* c, const NbrParams& p, hipStream_t s) {
 aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, double half_dt,
                      const DriftArgs* next = nullptr, bool keep_G = false) {
   if (c->n == 0) return AENET_OK;
+  const bool sh = use_factorised(c);
+  if (sh) {
+    const size_t el = real_size(c);
+    TRY(ensure(c, c->d_shA, (size_t)c->n * 2 * ang_sh_terms(c->na) * el));
+    if (forces) TRY(ensure(c, c->d_gang, (size_t)c->n * c->cap_ang * 3 * el));
+  }
   DescParams dp = desc_params(c);
   MlpParams mp = mlp_params(c, forces);
-  if (c->fused && fwd_mlp_fits(c->prec, dp, mp)) {
+  if (sh) {
+    prof_begin(c, s, AENET_K_DESC_FWD);
+    launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s, false);
+    launch_ang_sh(true, desc_prec(c), c->na, dp, s);
+    prof_end(c, s);
+    prof_begin(c, s, AENET_K_NETWORK);
+    launch_mlp(c->prec, mp, n_tiles(mp), s);
+    prof_end(c, s);
+  } else if (c->fused && fwd_mlp_fits(c->prec, dp, mp)) {
     DescParams dq = dp;
     if (!keep_G) dq.G = nullptr;
     prof_begin(c, s, AENET_K_FWD_NETWORK);
@@ -732,7 +763,8 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
   }
   if (forces) {
     prof_begin(c, s, AENET_K_DESC_BWD);
-    launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s);
+    if (sh) launch_ang_sh(false, desc_prec(c), c->na, dp, s);
+    launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s, sh);
     prof_end(c, s);
     prof_begin(c, s, AENET_K_FORCE_GATHER);
     launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nrad.as<int>(), c->d_ridx.as<uint16_t>(), c->d_pg.p,
@@ -1211,7 +1243,7 @@ aenet_status aenet_energy_forces_noalloc(aenet_ctx* c, int64_t n, const double* 
                     &c->d_Eorig, &c->d_G, &c->d_gG, &c->d_U, &c->d_adj, &c->d_eps, &c->d_tmp, &c->d_red,
                     &c->d_scal, &c->d_flags, &c->d_cell_count, &c->d_cell_start, &c->d_cell_fill,
                     &c->d_cell_atoms, &c->d_atom_cell, &c->d_nbr, &c->d_segs, &c->d_nnb, &c->d_nang,
-                    &c->d_rev, &c->d_ridx, &c->d_nrad, &c->d_vir, &c->d_build};
+                    &c->d_rev, &c->d_ridx, &c->d_nrad, &c->d_vir, &c->d_build, &c->d_shA, &c->d_gang};
   constexpr int nbufs = (int)(sizeof(bufs) / sizeof(bufs[0]));
   struct Saved {
     void* p;
@@ -1316,8 +1348,11 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
   launch_gather_in((int)n, c->d_perm.as<int>(), c->h_pos.as<double>(), c->d_pos.as<double>(),
                    c->d_flags.as<int>(), s);
   TRY(build_checked(c, s));
+  const bool sh = use_factorised(c);
+  if (sh) TRY(ensure(c, c->d_shA, (size_t)n * 2 * ang_sh_terms(c->na) * real_size(c)));
   DescParams dp = desc_params(c);
-  launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s);
+  launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s, !sh);
+  if (sh) launch_ang_sh(true, desc_prec(c), c->na, dp, s);
   HIP_TRY(c, hipGetLastError());
   const size_t el = real_size(c);
   std::vector<unsigned char> buf((size_t)n * c->ldG * el);
@@ -1645,6 +1680,14 @@ aenet_status aenet_get_stats(const aenet_ctx* c, aenet_stats* out) {
 aenet_status aenet_set_rebuild_every(aenet_ctx* c, int k) {
   if (!c || k < 1) return AENET_E_INVALID;
   c->rebuild_every = k;
+  return AENET_OK;
+}
+
+aenet_status aenet_set_angular_method(aenet_ctx* c, int method) {
+  TRY(check_ctx(c));
+  if (method != AENET_ANGULAR_AUTO && method != AENET_ANGULAR_PAIRS && method != AENET_ANGULAR_FACTORISED)
+    return fail(c, AENET_E_INVALID, "unknown angular method");
+  c->ang_method = method;
   return AENET_OK;
 }
 

@@ -312,6 +312,34 @@ def apply_normalisation(model: ModelSpec, norm: dict) -> ModelSpec:
                      list(model.species_names))
 
 
+def sub_network(model: ModelSpec, radial_order: int, angular_order: int, hidden) -> ModelSpec:
+    """A copy of a model whose networks keep only a smaller network inside
+    them: the first-layer weights of descriptor components up to the given
+    orders (the components of a descriptor with those orders and the same
+    cutoffs) and the first hidden[l] units of each hidden layer; every other
+    weight is set to zero (biases of dropped units too).  Its energy is then
+    exactly a network of the smaller shape on the smaller descriptor."""
+    NR, NA = model.radial_order, model.angular_order
+    T1, T2 = NR + 1, NR + NA + 2
+    keep = [a for a in range(NR + 1) if a <= radial_order] + [T1 + a for a in range(NA + 1) if a <= angular_order]
+    if model.n_species > 1:
+        keep = keep + [T2 + k for k in keep]
+    cols = np.zeros(model.D, dtype=bool)
+    cols[keep] = True
+    nets = []
+    for n in model.nets:
+        W = [w.copy() for w in n.W]
+        b = [x.copy() for x in n.b]
+        W[0][:, ~cols] = 0.0
+        for l, h in enumerate(hidden):
+            W[l][h:, :] = 0.0
+            b[l][h:] = 0.0
+            W[l + 1][:, h:] = 0.0
+        nets.append(NetSpec(W, b, list(n.act), n.shift, n.scale, n.e_offset))
+    return ModelSpec(model.n_species, model.type_weight, model.masses, model.radial_order, model.radial_cutoff,
+                     model.angular_order, model.angular_cutoff, nets, list(model.species_names))
+
+
 def model_file(tag: str) -> str:
     return os.path.join(_GOLDEN, f"model_{tag}.json")
 
@@ -322,4 +350,7 @@ def load_model(tag: str) -> ModelSpec:
     with open(model_file(tag)) as f:
         norm = json.load(f)
     m = raw_model(norm["config"], int(norm.get("net_seed_offset", 0)))
+    sub = norm.get("sub_network")
+    if sub:
+        m = sub_network(m, sub["radial_order"], sub["angular_order"], sub["hidden"])
     return apply_normalisation(m, norm)

@@ -34,13 +34,21 @@ TAGS = {
     "water4096_ref": ("water4096", "water4096", 1000),
     "lisio120k": ("lisio120k", "lisio120k", 0),
     "student": ("student", "water4096", 0),
+    # the distillation teacher: the water4096 network reduced to a
+    # 20-16-16-1 network on the student's descriptor components (see
+    # paper_2107_11311_amd.inputs.sub_network), force RMS 1 eV/A on frame 0
+    "student_teacher": ("water4096", "water4096", 0),
 }
+SUB_NETWORK = {"student_teacher": {"radial_order": 6, "angular_order": 2, "hidden": [16, 16]}}
 
 
 def fit(tag: str) -> dict:
     cfg, frame_cfg, seed_off = TAGS[tag]
     t0 = time.time()
     model = I.raw_model(cfg, seed_off)
+    sub = SUB_NETWORK.get(tag)
+    if sub:
+        model = I.sub_network(model, sub["radial_order"], sub["angular_order"], sub["hidden"])
     sysm = I.make_system(frame_cfg)
     G = oracle.descriptors(model, sysm.pos, sysm.species, sysm.box, sysm.pbc)
     shift, scale = [], []
@@ -53,6 +61,8 @@ def fit(tag: str) -> dict:
         scale.append((1.0 / sd).tolist())
     norm = dict(config=cfg, frame=frame_cfg, net_seed_offset=seed_off, shift=shift, scale=scale,
                 out_scale=1.0)
+    if sub:
+        norm["sub_network"] = sub
     m1 = I.apply_normalisation(model, norm)
     _, _, F = oracle.energy_forces(m1, sysm.pos, sysm.species, sysm.box, sysm.pbc)
     rms = float(np.sqrt(np.mean(F * F)))

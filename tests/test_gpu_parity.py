@@ -461,3 +461,62 @@ def test_md_continuation_detects_changed_state(A):
     assert np.array_equal(r5, r4) and np.array_equal(u5, u4) and e5 == e4
     np.testing.assert_array_equal(F5, F4)
     ctx.close()
+
+
+def _dense_lisio_box():
+    n = int(round(0.0964 * 17.0 ** 3))
+    return I.amorphous_box(n, (n // 3, n // 6, n - n // 3 - n // 6), 17.0, 4242)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_factorised_angular_matches_oracle(A, orc, precision, tol):
+    """The angular terms of Eq. 6 by the addition theorem (forced) against
+    the oracle's pair sums: water64 (angular order 4), a three-species open
+    cluster with weights 1, 2, 3 (order 2), a small box with several images
+    of one atom, and the dense Li/Si/O box (order 6, ~110 angular
+    neighbours); descriptors element by element, energies and forces to the
+    bars of each precision."""
+    g = np.random.default_rng(5)
+    pos = I.rsa(60, 14.0, 1.6, 77) + 30.0
+    sp = g.integers(0, 3, size=60).astype(np.int32)
+    cluster = I.System(pos, sp, np.array([80.0, 80.0, 80.0]), np.zeros(3, dtype=np.uint8))
+    small = I.water_box(8, 908)
+    cases = [("water64", I.load_model("water64"), I.make_system("water64")),
+             ("cluster3", small_model(S=3, nr=4, na=2, rr=5.0, ra=4.0, tw=(1.0, 2.0, 3.0)), cluster),
+             ("images", small_model(nr=5, na=3, rr=min(6.5, small.box[0] * 0.99), ra=4.0), small),
+             ("lisio_dense", I.load_model("lisio120k"), _dense_lisio_box())]
+    for name, m, s in cases:
+        ctx = A.Context(m, precision)
+        ctx.set_angular_method("factorised")
+        E, Ea, F = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
+        G = ctx.descriptors(s.pos, s.species, s.box, s.pbc)
+        ctx.close()
+        E0, Ea0, F0, G0 = orc.energy_forces(m, s.pos, s.species, s.box, s.pbc, want_G=True)
+        dG = float(np.abs(G - G0).max() / np.abs(G0).max())
+        de = abs(E - E0) / abs(E0)
+        df = rel_rmse(F, F0)
+        dmax = float(np.abs(F - F0).max() / np.abs(F0).max())
+        print(f"{name} {precision}: max|dG|/max|G| {dG:.2e} rel dE {de:.2e} rel F rmse {df:.2e} max {dmax:.2e}")
+        assert dG <= (1e-12 if precision == "fp64" else 1e-5), name
+        assert de <= (1e-10 if precision == "fp64" else 1e-5), name
+        assert df <= tol and dmax <= (1.0 if precision == "fp64" else 10.0) * tol, name
+
+
+def test_factorised_and_pair_paths_agree(A):
+    """On the dense Li/Si/O box the two evaluations of the angular terms give
+    the same energies and forces to rounding, and MD over both agrees."""
+    m = I.load_model("lisio120k")
+    s = _dense_lisio_box()
+    out = {}
+    for method in ("pairs", "factorised"):
+        ctx = A.Context(m, "fp64", skin=0.5)
+        ctx.set_angular_method(method)
+        out[method] = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
+        v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 3)
+        out[method + "_md"] = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 1e-3, 8)
+        ctx.close()
+    (E1, Ea1, F1), (E2, Ea2, F2) = out["pairs"], out["factorised"]
+    assert abs(E1 - E2) <= 1e-12 * abs(E1)
+    assert np.abs(F1 - F2).max() <= 1e-12 * np.abs(F1).max()
+    p1, p2 = out["pairs_md"][0], out["factorised_md"][0]
+    assert np.abs((p1 - p2 + s.box / 2) % s.box - s.box / 2).max() <= 1e-10
