@@ -38,18 +38,28 @@ KERNEL_SOURCES = {"desc_fwd": ["desc.hip", "desc_dev.h"], "desc_bwd": ["desc.hip
                   "neighbor": ["nbr.hip"], "force_gather": ["md.hip"], "integrate": ["md.hip"]}
 
 
-def algorithmic_flops(kernel, nr_order, na_order, n_r, n_a, widths):
+def algorithmic_flops(kernel, nr_order, na_order, n_r, n_a, widths, factorised=False):
     """Algorithmic floating-point operations per atom of one kernel launch (the
     minimum the method needs: unordered angular pairs, no recomputation; a
     transcendental counts as one operation).  n_r, n_a: mean neighbours within
-    the radial / angular cutoff; widths: network widths D, H1, ..., 1."""
+    the radial / angular cutoff; widths: network widths D, H1, ..., 1.  With
+    factorised=True the angular part is counted for the addition-theorem form
+    instead: per angular neighbour the (N_a+1)(N_a+2)/2 recurrence values,
+    (N_a+1)^2 functions accumulated in two channels (forward), and per
+    function pair the value and gradient contractions (backward)."""
     pairs = n_a * (n_a - 1) / 2.0
+    nh = (na_order + 1) ** 2
+    nq = (na_order + 1) * (na_order + 2) / 2.0
     if kernel == "desc_fwd":
         radial = n_r * (6 * nr_order + 14)          # distance, x, f_c, recurrence, 2 channels
+        if factorised:
+            return radial + n_a * (4 * nh + 3 * nq + 30)
         angular = pairs * (6 * na_order + 9) + 15 * n_a
         return radial + angular
     if kernel == "desc_bwd":
         radial = n_r * (8 * nr_order + 20)          # T and U recurrences, 4 sums, f_c, f_c', vector
+        if factorised:
+            return radial + n_a * (26 * nq + 4 * nh + 40)
         angular = pairs * (8 * na_order + 33) + 20 * n_a
         return radial + angular
     if kernel == "network":
@@ -104,7 +114,7 @@ WORKLOADS = {
     "water4096": dict(config="water4096", model="water4096", system="water4096",
                       modes=("fp64", "fp32", "bf16"), steps=1000, oracle="full"),
     "lisio120k": dict(config="lisio120k", model="lisio120k", system="lisio120k",
-                      modes=("fp64", "bf16"), steps=200, oracle="sampled"),
+                      modes=("fp64", "bf16", "fp64:pairs"), steps=200, oracle="sampled"),
     "water1M": dict(config="student", model="water4096", system="student",
                     modes=("fp64", "fp32"), steps=100, oracle="sampled"),
 }
@@ -114,7 +124,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def roofline_of(kt, model, n, n_r, n_a, widths, mode, workload):
+def roofline_of(kt, model, n, n_r, n_a, widths, mode, workload, factorised=False):
     """Roofline position of the kernel class with the largest total time:
     algorithmic flops per launch (formula above, measured mean neighbour
     counts) over its mean launch time from HIP events on the launch stream,
@@ -122,14 +132,15 @@ def roofline_of(kt, model, n, n_r, n_a, widths, mode, workload):
     dom = max(kt, key=lambda k: kt[k][0])
     ms, launches = kt[dom]
     avg_s = ms / launches * 1e-3
-    fl = algorithmic_flops(dom, model.radial_order, model.angular_order, n_r, n_a, widths) * n
-    peak = FP64_VALU_PEAK if mode == "fp64" else FP32_VALU_PEAK
+    fl = algorithmic_flops(dom, model.radial_order, model.angular_order, n_r, n_a, widths, factorised) * n
+    peak = FP64_VALU_PEAK if mode.startswith("fp64") else FP32_VALU_PEAK
     achieved = fl / avg_s
     steps = max(kt.get("desc_bwd", (0, 1))[1], 1)
     return dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                 frac=achieved / peak, traffic=stored_traffic(dom, workload, mode),
                 avg_launch_ms=ms / launches, launches=launches, flops_per_launch=fl,
                 mean_neighbors_radial=n_r, mean_neighbors_angular=n_a,
+                angular="factorised" if factorised else "pairs",
                 kernel_ms_per_step={k: v[0] / steps for k, v in kt.items()})
 
 
@@ -200,9 +211,13 @@ def equilibrate(A, model, sysm, vel0, dt, steps, T, chunk=20):
 
 
 def run_mode(A, model, sysm, vel0, precision, steps, warmup, dt, profile):
+    """MD of one mode: "<precision>" or "<precision>:<angular method>"."""
     import torch
     dev = torch.device("cuda:0")
+    precision, _, method = precision.partition(":")
     ctx = A.Context(model, precision, skin=0.5, device=0)
+    if method:
+        ctx.set_angular_method(method)
     pos = torch.from_numpy(sysm.pos.copy()).to(dev)
     vel = torch.from_numpy(vel0.copy()).to(dev)
     n = sysm.pos.shape[0]
@@ -289,7 +304,7 @@ def run_student(args):
     rmse_adam = ST.force_rmse(student, snaps, test_idx)
     log(f"student rmse untrained {rmse0:.4f} after Adam {rmse_adam:.4f}")
     pol = train_idx[:: max(1, len(train_idx) // args.lbfgs_snaps)][: args.lbfgs_snaps]
-    res = ST.polish_lbfgs(student, snaps, pol, args.lbfgs_iter, res=res, log=log)
+    res = ST.polish_lbfgs(student, snaps, pol, args.lbfgs_iter, res=res, log=log, target=args.lbfgs_target)
     rmse1 = ST.force_rmse(student, snaps, test_idx)
     rms = float(torch.sqrt((snaps.forces[test_idx].to(torch.float64) ** 2).mean()).item())
     log(f"student rmse untrained {rmse0:.4f} trained {rmse1:.4f} (teacher force rms {rms:.3f})")
@@ -334,7 +349,7 @@ def run_student(args):
     st = ST.DeviceState(big, vb)
     t0 = time.perf_counter()
     rep = ST.md_with_judge(st.runner(s_ctx, dt), st.runner(t_ctx, dt), st.forces(t_ctx), st,
-                           args.md_steps, 50, 3e-2)
+                           args.md_steps, 50, 3e-2, rmse=st.rmse(t_ctx))
     wall = time.perf_counter() - t0
     log(f"judge: {rep.fallbacks} fallbacks in {rep.chunks} chunks, rmse {rep.rmse_per_chunk}")
     # the teacher alone over the same steps, for the net gain
@@ -428,7 +443,9 @@ def main():
     ap.add_argument("--train-prec", default="fp32", help="arithmetic of the student's training context")
     ap.add_argument("--control", action="store_true",
                     help="also train against the teacher reduced to the student's orders only")
-    ap.add_argument("--lbfgs-iter", type=int, default=2000)
+    ap.add_argument("--lbfgs-iter", type=int, default=12000)
+    ap.add_argument("--lbfgs-target", type=float, default=2.5e-5,
+                    help="stop the L-BFGS polish once the cost (about the force MSE) falls to this")
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--md-steps", type=int, default=500)
     ap.add_argument("--speed-steps", type=int, default=50)
@@ -488,7 +505,8 @@ def main():
                          rebuilds=r["rebuilds"], temperature_end_K=r["t_end"],
                          nve_drift_ev_per_atom=(r["e_total_end"] - r["e_total_start"]) / n)
             if "kernel_times" in r:
-                entry["roofline"] = roofline_of(r["kernel_times"], model, n, n_r, n_a, widths, m, wl)
+                fact = (not m.endswith(":pairs")) and (m.endswith(":factorised") or n_a > 48)
+                entry["roofline"] = roofline_of(r["kernel_times"], model, n, n_r, n_a, widths, m, wl, fact)
                 rooflines[key] = entry["roofline"]
             out_modes[key] = entry
         # oracle: force RMSE on the final positions (all atoms for the small box,

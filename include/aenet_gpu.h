@@ -256,6 +256,13 @@ aenet_status aenet_loss_grad(aenet_ctx* ctx, int n_struct, const int64_t* offset
                              const uint8_t pbc[3], const double* e_ref, const double* f_ref,
                              double lambda_f, double* loss, double* grad);
 
+/* Root-mean-square difference sqrt(sum_k (a_k - b_k)^2 / n) of two float64
+ * device arrays of n values (the force RMSE of a distilled network against
+ * its teacher, 3 values per atom), summed in a fixed order; out is a device
+ * pointer to one double.  Uses the context only for scratch memory. */
+aenet_status aenet_rms_diff_dev(aenet_ctx* ctx, int64_t n, const double* a, const double* b, double* out,
+                                void* stream);
+
 /* Selects the loss form of the following aenet_loss_grad[_dev] calls. */
 typedef enum { AENET_LOSS_MEAN_PER_ATOM = 0, AENET_LOSS_EQ7 = 1 } aenet_loss_form;
 aenet_status aenet_set_loss_form(aenet_ctx* ctx, int form);

@@ -31,7 +31,7 @@ EXPORTS = ["aenet_setup", "aenet_destroy", "aenet_last_error", "aenet_descriptor
            "aenet_energy_forces_virial", "aenet_energy_forces_virial_dev", "aenet_energy_forces_dev", "aenet_energy_forces_noalloc",
            "aenet_energy_forces_batch_dev", "aenet_descriptors",
            "aenet_md_step", "aenet_md_step_dev", "aenet_loss_grad_dev", "aenet_loss_grad", "aenet_set_loss_form",
-           "aenet_set_params_dev", "aenet_adam_step_dev", "aenet_get_stats",
+           "aenet_set_params_dev", "aenet_adam_step_dev", "aenet_rms_diff_dev", "aenet_get_stats",
            "aenet_set_rebuild_every", "aenet_set_capacity", "aenet_set_fused", "aenet_set_angular_method", "aenet_set_profiling", "aenet_get_kernel_times"]
 KERNEL_CLASSES = ["neighbor", "desc_fwd", "network", "desc_bwd", "force_gather", "integrate", "fwd_network"]
 
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH):
     L.aenet_loss_grad.argtypes = [ctxp, C.c_int, _i64p, _dp, _ip, _dp, _u8p, _dp, _dp, C.c_double, _dp, _dp]
     L.aenet_set_loss_form.argtypes = [ctxp, C.c_int]
     L.aenet_set_params_dev.argtypes = [ctxp, _vp, _vp]
+    L.aenet_rms_diff_dev.argtypes = [ctxp, C.c_int64, _vp, _vp, _vp, _vp]
     L.aenet_adam_step_dev.argtypes = [C.c_int64, _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_int64, _vp]
     L.aenet_get_stats.argtypes = [ctxp, C.POINTER(Stats)]
@@ -256,6 +257,12 @@ class Context:
         """aenet_set_params_dev: parameters from a float64 device tensor."""
         assert p.numel() == self.n_params() and p.is_contiguous()
         self._check(self._lib.aenet_set_params_dev(self._h, _dev(p), _stream(stream)))
+
+    def rms_diff_dev(self, a, b, out, stream=None) -> None:
+        """aenet_rms_diff_dev: out[0] = sqrt(mean((a - b)^2)) of float64 device tensors."""
+        assert a.numel() == b.numel() and a.is_contiguous() and b.is_contiguous()
+        self._check(self._lib.aenet_rms_diff_dev(self._h, int(a.numel()), _dev(a), _dev(b), _dev(out),
+                                                 _stream(stream)))
 
     def set_loss_form(self, form: int) -> None:
         """AENET_LOSS_MEAN_PER_ATOM (default) or AENET_LOSS_EQ7 for the loss-gradient calls."""

@@ -279,6 +279,9 @@ void launch_sum(int64_t n, const double* x, double* partials, double* out, hipSt
 // rows independent sums of x [rows][n] into out[rows]; partials has >= rows *
 // reduce_blocks(n) doubles; each row summed as launch_sum sums it
 void launch_sum_rows(int rows, int64_t n, const double* x, double* partials, double* out, hipStream_t s);
+// out = sqrt(sum_k (x_k - y_k)^2 / n), summed in a fixed order
+void launch_rms_diff(int64_t n, const double* x, const double* y, double* partials, double* out,
+                     hipStream_t s);
 void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
                     hipStream_t s);
 void launch_segment_sum(int n_seg, const int64_t* seg_off, const double* x, double* out,

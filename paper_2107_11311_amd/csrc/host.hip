@@ -117,6 +117,7 @@ struct aenet_ctx {
   DevMem d_bin_count, d_bin_atoms;  // MD: cell bins filled by the integrator
   DevMem d_ridx, d_nrad;            // contributing entries, from the forward pass
   DevMem d_shA, d_gang;             // factorised angular descriptor: per-atom sums, entry gradients
+  DevMem d_judge;                   // partial sums of aenet_rms_diff_dev
   DevMem d_vir;                     // [9][n] per-atom virial, then its 9 sums
   bool want_vir = false;            // the next force pass also forms the virial
   DevMem d_build;  // [2] ints: decision of the current build, block counter
@@ -1168,6 +1169,18 @@ aenet_status aenet_adam_step_dev(int64_t n, double* params, const double* grad, 
     (void)hipGetLastError();
     return AENET_E_DEVICE;
   }
+  return AENET_OK;
+}
+
+aenet_status aenet_rms_diff_dev(aenet_ctx* c, int64_t n, const double* a, const double* b, double* out,
+                                void* stream) {
+  TRY(check_ctx(c));
+  if (n < 0 || !out || (n > 0 && (!a || !b))) return fail(c, AENET_E_INVALID, "bad arguments");
+  hipStream_t s = pick_stream(c, stream);
+  TRY(ensure(c, c->d_judge, (size_t)(reduce_blocks(n) + 1) * 8));
+  launch_rms_diff(n, a, b, c->d_judge.as<double>(), out, s);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(s));
   return AENET_OK;
 }
 

@@ -264,7 +264,9 @@ __global__ void k_vv_drift(int n, double* vel, const double* F, const double* in
 constexpr int kRedChunk = 2048;  // elements per partial sum (fixed: results depend only on n)
 
 // row blockIdx.y of x ([rows][n]) into part[blockIdx.y * gridDim.x + blockIdx.x]
-__global__ __launch_bounds__(256) void k_partial_sum(int64_t n, const double* x, double* part) {
+// block partial sums of x (or, with y, of (x - y)^2) over fixed chunks
+__global__ __launch_bounds__(256) void k_partial_sum(int64_t n, const double* x, const double* y,
+                                                     double* part) {
   __shared__ double s[256];
   x += (size_t)blockIdx.y * n;
   part += (size_t)blockIdx.y * gridDim.x;
@@ -272,7 +274,10 @@ __global__ __launch_bounds__(256) void k_partial_sum(int64_t n, const double* x,
   double acc = 0.0;
   for (int k = threadIdx.x; k < kRedChunk; k += 256) {
     const int64_t idx = base + k;
-    if (idx < n) acc += x[idx];
+    if (idx < n) {
+      const double v = y ? x[idx] - y[idx] : x[idx];
+      acc += y ? v * v : v;
+    }
   }
   s[threadIdx.x] = acc;
   __syncthreads();
@@ -438,8 +443,21 @@ void launch_sum(int64_t n, const double* x, double* partials, double* out, hipSt
 
 void launch_sum_rows(int rows, int64_t n, const double* x, double* partials, double* out, hipStream_t s) {
   const int m = reduce_blocks(n);
-  if (m > 0) hipLaunchKernelGGL(k_partial_sum, dim3(m, rows), dim3(256), 0, s, n, x, partials);
+  if (m > 0) hipLaunchKernelGGL(k_partial_sum, dim3(m, rows), dim3(256), 0, s, n, x, (const double*)nullptr,
+                                partials);
   hipLaunchKernelGGL(k_final_sum, dim3(rows), dim3(1024), 0, s, m, partials, out);
+}
+
+__global__ void k_rms_finish(int64_t n, double* out) {
+  if (threadIdx.x == 0) *out = n > 0 ? sqrt(*out / (double)n) : 0.0;
+}
+
+void launch_rms_diff(int64_t n, const double* x, const double* y, double* partials, double* out,
+                     hipStream_t s) {
+  const int m = reduce_blocks(n);
+  if (m > 0) hipLaunchKernelGGL(k_partial_sum, dim3(m, 1), dim3(256), 0, s, n, x, y, partials);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(1024), 0, s, m, partials, out);
+  hipLaunchKernelGGL(k_rms_finish, dim3(1), dim3(64), 0, s, n, out);
 }
 
 void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,

@@ -137,7 +137,8 @@ def train(student, snaps: Snapshots, train_idx: np.ndarray, steps: int, batch: i
 
 
 def polish_lbfgs(student, snaps: Snapshots, idx: np.ndarray, maxiter: int, lambda_f: float = 1.0,
-                 res: Optional[TrainResult] = None, log: Callable[[str], None] = print) -> TrainResult:
+                 res: Optional[TrainResult] = None, log: Callable[[str], None] = print,
+                 target: float = 0.0) -> TrainResult:
     """Full-batch L-BFGS (the paper's optimiser, Sec. II C) over the snapshots
     idx, starting from the student's current parameters; every cost and
     gradient evaluation is aenet_loss_grad_dev over the whole set."""
@@ -151,7 +152,7 @@ def polish_lbfgs(student, snaps: Snapshots, idx: np.ndarray, maxiter: int, lambd
     f_ref = snaps.forces.index_select(0, sel).reshape(k * n, 3).to(torch.float64).cpu().numpy()
     e_ref = snaps.energy.index_select(0, sel).cpu().numpy()
     r = fit_lbfgs(student, offs, pos, species, boxes, snaps.pbc, e_ref, f_ref, lambda_f=lambda_f,
-                  maxiter=maxiter, history=20, log_every=250, log=log)
+                  maxiter=maxiter, history=20, log_every=250, log=log, target=target)
     log(f"lbfgs: loss {r.loss0:.4e} -> {r.loss:.4e} in {r.iterations} iterations ({r.seconds:.1f} s)")
     out = res if res is not None else TrainResult(r.params)
     out.params = r.params
@@ -188,15 +189,17 @@ class JudgeReport:
 
 
 def md_with_judge(run_student: Callable, run_teacher: Callable, teacher_forces: Callable,
-                  state, n_steps: int, every: int, threshold: float) -> JudgeReport:
+                  state, n_steps: int, every: int, threshold: float,
+                  rmse: Optional[Callable] = None) -> JudgeReport:
     """Production MD with a judge.
 
     run_student(state, k) / run_teacher(state, k) advance the state by k steps
     in place and return the forces at the final positions; teacher_forces(state)
     evaluates the teacher there; state.save() / state.restore(snapshot) make and
     restore a checkpoint.  Every `every` steps the student's final forces are
-    compared with the teacher's; if the RMSE exceeds `threshold` the chunk is
-    undone and redone with the teacher."""
+    compared with the teacher's (rmse(Fs, Ft), by default numpy on host
+    arrays); if the RMSE exceeds `threshold` the chunk is undone and redone
+    with the teacher."""
     rep = JudgeReport()
     done = 0
     while done < n_steps:
@@ -206,12 +209,15 @@ def md_with_judge(run_student: Callable, run_teacher: Callable, teacher_forces: 
         Fs = run_student(state, k)
         t1 = time.perf_counter()
         Ft = teacher_forces(state)
+        if rmse is None:
+            err = float(np.sqrt(np.mean((np.asarray(Fs) - np.asarray(Ft)) ** 2)))
+        else:
+            err = float(rmse(Fs, Ft))
         t2 = time.perf_counter()
-        rmse = float(np.sqrt(np.mean((np.asarray(Fs) - np.asarray(Ft)) ** 2)))
-        rep.rmse_per_chunk.append(rmse)
+        rep.rmse_per_chunk.append(err)
         rep.student_seconds += t1 - t0
         rep.judge_seconds += t2 - t1
-        if not rmse <= threshold:
+        if not err <= threshold:
             state.restore(ckpt)
             t3 = time.perf_counter()
             run_teacher(state, k)
@@ -245,17 +251,30 @@ class DeviceState:
         self.vel.copy_(ck[1])
 
     def runner(self, ctx, dt_ps):
+        """run(state, k): k MD steps with ctx; returns the final forces (device)."""
         def run(state, k):
             s = state.system
             ctx.md_step_dev(state.pos, state.vel, s.species, s.box, s.pbc, dt_ps, k, state.ep, state.ek, state.F)
-            return state.F.cpu().numpy()
+            return state.F
         return run
 
     def forces(self, ctx):
+        """f(state): ctx's forces at the state's positions (device)."""
+        import torch
+        buf = torch.empty_like(self.pos)
+
         def f(state):
-            import torch
             s = state.system
-            F = torch.empty_like(state.pos)
-            ctx.energy_forces_dev(state.pos, s.species, s.box, s.pbc, None, None, F)
-            return F.cpu().numpy()
+            ctx.energy_forces_dev(state.pos, s.species, s.box, s.pbc, None, None, buf)
+            return buf
         return f
+
+    def rmse(self, ctx):
+        """rmse(Fs, Ft) on the device (aenet_rms_diff_dev): one value read back."""
+        import torch
+        out = torch.zeros(1, dtype=torch.float64, device=self.pos.device)
+
+        def r(a, b):
+            ctx.rms_diff_dev(a, b, out)
+            return out.item()
+        return r

@@ -34,7 +34,7 @@ class LbfgsResult:
 
 def fit_lbfgs(ctx, offsets, pos, species, boxes, pbc, e_ref, f_ref=None, lambda_f: float = 0.0,
               maxiter: int = 100, history: int = 10, gtol: float = 1e-12, log_every: int = 0,
-              log=print) -> LbfgsResult:
+              log=print, target: float = 0.0) -> LbfgsResult:
     """Minimises the cost over the batch (offsets [B+1], pos [N,3] and
     species [N] in structure order, boxes [B,3], e_ref [B], f_ref [N,3] or
     None for an energy-only cost) starting from ctx's current parameters,
@@ -65,10 +65,12 @@ def fit_lbfgs(ctx, offsets, pos, species, boxes, pbc, e_ref, f_ref=None, lambda_
     t0 = time.perf_counter()
     it = [0]
 
-    def progress(_xk):
+    def progress(intermediate_result):
         it[0] += 1
         if log_every and it[0] % log_every == 0:
             log(f"lbfgs iteration {it[0]}: loss {trace[-1]:.4e} ({time.perf_counter() - t0:.0f} s)")
+        if intermediate_result.fun <= target:
+            raise StopIteration  # the cost reached the requested value
 
     res = minimize(fun, p0, jac=True, method="L-BFGS-B", callback=progress,
                    options=dict(maxiter=maxiter, maxcor=history, gtol=gtol, ftol=0.0))

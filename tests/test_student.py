@@ -145,7 +145,7 @@ def test_student_meets_bar_and_beats_teacher_md():
     train_idx = np.arange(0, 730)
     rmse0 = ST.force_rmse(student, snaps, test_idx)
     res = ST.train(student, snaps, train_idx, steps=600, batch=4, lr=3e-3, lr_final=3e-4)
-    res = ST.polish_lbfgs(student, snaps, train_idx[::46], 1500, res=res, log=lambda m: None)
+    res = ST.polish_lbfgs(student, snaps, train_idx[::60], 12000, res=res, log=lambda m: None, target=1e-4)
     rmse1 = ST.force_rmse(student, snaps, test_idx)
     rms = float(torch.sqrt((snaps.forces[test_idx].to(torch.float64) ** 2).mean()).item())
     print(f"student force rmse: untrained {rmse0:.4f} trained {rmse1:.4f} eV/A (teacher rms {rms:.3f}; "
@@ -155,11 +155,13 @@ def test_student_meets_bar_and_beats_teacher_md():
     # production MD from the snapshot run's start: student + judge vs teacher alone
     trained = A.Context(stud_m.with_params(res.params), "fp32", skin=0.5)
     st = ST.DeviceState(s, v)
-    ST.md_with_judge(st.runner(trained, dt), st.runner(teacher, dt), st.forces(teacher), st, 50, 50, 3e-2)
+    judge = dict(rmse=st.rmse(teacher))
+    ST.md_with_judge(st.runner(trained, dt), st.runner(teacher, dt), st.forces(teacher), st, 50, 50, 3e-2, **judge)
     torch.cuda.synchronize()
     st = ST.DeviceState(s, v)
     t0 = time.perf_counter()
-    rep = ST.md_with_judge(st.runner(trained, dt), st.runner(teacher, dt), st.forces(teacher), st, 400, 50, 3e-2)
+    rep = ST.md_with_judge(st.runner(trained, dt), st.runner(teacher, dt), st.forces(teacher), st, 400, 50, 3e-2,
+                           rmse=st.rmse(teacher))
     torch.cuda.synchronize()
     t_student = time.perf_counter() - t0
     st = ST.DeviceState(s, v)
