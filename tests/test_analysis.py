@@ -35,6 +35,27 @@ def test_msd_of_ballistic_motion():
     np.testing.assert_allclose(m, (v @ v) * (np.arange(50) * 0.1) ** 2, rtol=1e-12, atol=1e-15)
 
 
+def test_eq9_constant_is_the_cubic_lattice_sum():
+    """The constant xi of Eq. 9 is the lattice sum of the simple cubic
+    lattice (the periodic Oseen tensor's leading term has the same sum as a
+    1/r interaction with a uniform background): computed here by Ewald
+    summation, independent of the splitting parameter."""
+    from scipy.special import erfc
+    vals = []
+    for alpha in (1.5, 2.0, 3.0):
+        n = np.arange(-6, 7)
+        X, Y, Z = np.meshgrid(n, n, n, indexing="ij")
+        r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2).ravel()
+        r = r[r > 0]
+        k2 = (X ** 2 + Y ** 2 + Z ** 2).ravel()
+        k2 = k2[k2 > 0]
+        psi = (np.sum(erfc(alpha * r) / r) + np.sum(np.exp(-np.pi ** 2 * k2 / alpha ** 2) / (np.pi * k2))
+               - 2 * alpha / np.sqrt(np.pi) - np.pi / alpha ** 2)
+        vals.append(-psi)
+    assert max(vals) - min(vals) < 1e-12
+    assert abs(vals[0] - AN.XI_CUBIC) < 1e-6
+
+
 def test_finite_size_correction_closed_form():
     # water near 300 K: eta = 0.89 mPa s, L = 30 A
     d_inf = AN.finite_size_correction(0.20, 30.0, 300.0, 0.89e-3)
