@@ -75,8 +75,9 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   R* gy = gx + ca;
   R* gz = gy + ca;
   int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)ca * 10);
-  // radial series coefficients of each species s (NR + 1 per species)
-  R* s_c = reinterpret_cast<R*>(smem) + bwd_coef_offset<R>(ca);
+  // radial series coefficients of each species s (NR + 1 per species); with
+  // AEXT the angular arrays are not needed and the table starts the LDS
+  R* s_c = reinterpret_cast<R*>(smem) + (AEXT ? 0 : bwd_coef_offset<R>(ca));
 
   const BoxInfo b = p.boxes[p.seg[i]];
   const double xi0 = p.pos[3 * (size_t)i];
@@ -585,7 +586,7 @@ void launch_kind(int kind, const DescParams& p, hipStream_t s, bool ang) {
 // schedule with the finest grain: measured ~2 % faster than four per block)
 template <typename R, int NR, int NA>
 void launch_bwd(const DescParams& p, hipStream_t s, bool ext) {
-  const size_t per_atom = (bwd_coef_offset<R>(p.cap_ang) + (size_t)p.n_species * (NR + 1)) * sizeof(R);
+  const size_t per_atom = ((ext ? 0 : bwd_coef_offset<R>(p.cap_ang)) + (size_t)p.n_species * (NR + 1)) * sizeof(R);
   if (p.vir && ext)
     hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, true>), dim3(p.n), dim3(64), per_atom, s, p);
   else if (p.vir)
@@ -606,8 +607,9 @@ void launch_orders(int kind, const DescParams& p, hipStream_t s, bool flag) {
     launch_bwd<R, NR, NA>(p, s, flag);
     return;
   }
+  // (the radial terms alone, flag false in the forward pass, take narrow groups)
   const int na = p.ang_hint > 0 ? p.ang_hint : p.cap_ang;
-  if (na > 48)
+  if (na > 48 && (kind != FWD || flag))
     launch_kind<R, NR, NA, 64>(kind, p, s, kind != FWD || flag);
   else
     launch_kind<R, NR, NA, 16>(kind, p, s, kind != FWD || flag);
