@@ -66,7 +66,10 @@ typedef enum { AENET_ACT_LINEAR = 0, AENET_ACT_TANH = 1 } aenet_act;
  * layers (1..AENET_MAX_LAYERS), widths[0] = descriptor dimension D,
  * widths[n_layers] = 1, every width <= AENET_MAX_WIDTH.  W[l] is row-major
  * [widths[l+1] x widths[l]], b[l] has widths[l+1] entries.  in_shift/in_scale
- * may be NULL (0 / 1).  All species must share one set of widths. */
+ * may be NULL (0 / 1).  All species have the same number of layers and the
+ * same activations; their hidden widths may differ (internally every species
+ * runs at the largest width of each layer, the extra units with zero weights
+ * and biases, which leaves every energy and force unchanged). */
 #define AENET_MAX_LAYERS 4
 #define AENET_MAX_WIDTH 64
 typedef struct {
@@ -89,7 +92,14 @@ typedef struct {
  * G = [rad_typ (N_r+1) | ang_typ (N_a+1) | rad_wt (N_r+1) | ang_wt (N_a+1)],
  * D = 2(N_r+1) + 2(N_a+1); with S = 1 only the typed half (D = N_r+N_a+2).
  * The angular sum runs over ordered pairs of distinct neighbours.
- * Supported orders: see aenet_supported_orders().  mass_amu is used by MD.
+ * Orders: any pair that some compiled pair (aenet_supported_orders) reaches
+ * in both orders; the model then runs on the smallest such pair, whose
+ * descriptor holds the model's as a subset (same cutoffs, the lower orders of
+ * each block), with the other components entering the networks with zero
+ * weight (exact, at that pair's cost).  The pair's descriptor dimension must
+ * not exceed AENET_MAX_WIDTH (the networks' input layer): with S > 1 species
+ * orders up to 20 / 10 are reached, with one species up to 24 / 12.  Other
+ * orders give AENET_E_INVALID.  mass_amu is used by MD.
  * skin (A) enlarges the neighbour list so it is rebuilt only when an atom
  * has moved more than skin/2 (0 = rebuild every evaluation).  device is the
  * HIP device index. */
@@ -132,7 +142,9 @@ aenet_status aenet_get_params(aenet_ctx* ctx, double* params);
 aenet_status aenet_set_params(aenet_ctx* ctx, const double* params);
 
 /* Writes into orders[2*k], orders[2*k+1] the (radial, angular) order pairs the
- * library was compiled for; returns their count (at most max_pairs written). */
+ * library was compiled for; returns their count (at most max_pairs written).
+ * A model's orders (N_r, N_a) are accepted when some pair has both orders at
+ * least as large. */
 int aenet_supported_orders(int* orders, int max_pairs);
 
 /* Total energy E = sum_i E_i (Sec. II A, Eq. 2), per-atom energies and forces

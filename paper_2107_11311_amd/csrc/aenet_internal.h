@@ -162,7 +162,6 @@ struct DescParams {
 // true if `grid` blocks of the kernel are all resident at once on the current
 // device (occupancy from the runtime, cached per kernel, block size and LDS)
 bool fits_one_round(const void* kernel, int threads, size_t lds, int grid);
-bool desc_supported(int nr, int na);
 int desc_supported_list(int* orders, int max_pairs);
 // angular: false = the radial terms only (the angular components of G are
 // written as zero, for the factorised angular kernel to fill);

@@ -661,14 +661,6 @@ bool fits_one_round(const void* kernel, int threads, size_t lds, int grid) {
   return grid <= it->second;
 }
 
-bool desc_supported(int nr, int na) {
-#define AENET_CHECK(A, B) \
-  if (nr == A && na == B) return true;
-  AENET_ORDERS(AENET_CHECK)
-#undef AENET_CHECK
-  return false;
-}
-
 int desc_supported_list(int* orders, int max_pairs) {
   int k = 0;
 #define AENET_LIST(A, B)          \

@@ -6,14 +6,18 @@
 #include "aenet_internal.h"
 
 // (radial order, angular order) pairs compiled in; every descriptor kernel
-// is instantiated for each pair
+// is instantiated for each pair.  A model of other orders runs on the
+// smallest pair that reaches both of them (its descriptor is a subset of that
+// pair's); the last two pairs are there to reach orders up to 24 / 12.
 #define AENET_ORDERS(X) \
   X(10, 4)              \
   X(16, 8)              \
   X(18, 6)              \
   X(6, 2)               \
   X(5, 3)               \
-  X(4, 2)
+  X(4, 2)               \
+  X(20, 10)             \
+  X(24, 12)
 
 namespace aenet {
 

@@ -50,15 +50,28 @@ struct Arena {
 
 struct aenet_ctx {
   // model
-  int S = 0, nr = 0, na = 0, D = 0, ldG = 0, prec = 0, device = 0;
+  // nr, na, D: the model's descriptor orders and dimension; knr, kna, kD:
+  // those of the compiled kernels that compute it (the smallest compiled
+  // pair with knr >= nr and kna >= na).  The model's components are a subset
+  // of the kernels' (same cutoffs, the lower orders of each block): colmap[k]
+  // is the kernel column of model column k; the other kernel columns enter
+  // the networks with input scale 0 and zero weights, so they add nothing.
+  int S = 0, nr = 0, na = 0, D = 0, knr = 0, kna = 0, kD = 0, ldG = 0, prec = 0, device = 0;
+  std::vector<int> colmap;                 // [D]
   double rr = 0, ra = 0, skin = 0, rlist = 0;
   double tw[kMaxSpecies] = {0}, mass[kMaxSpecies] = {0};
   bool have_mass = false;
+  // Networks: L weight layers for every species.  w/wp are the kernels'
+  // widths: the kernel descriptor dimension, then per hidden layer the
+  // largest width of any species (a narrower species' extra units have zero
+  // weights and bias: tanh(0) = 0 and nothing reads them), then 1.
   int L = 0;
   int w[kMaxLayers + 1] = {0}, wp[kMaxLayers + 1] = {0}, act[kMaxLayers] = {0};
-  int64_t nps = 0;                         // parameters per species (API layout)
-  std::vector<double> params;              // [S * nps]
-  std::vector<double> shift, scale;        // [S * D]
+  std::vector<int64_t> poff;               // [S + 1] first parameter of each species (API layout)
+  int64_t nps_int = 0;                     // kernel-shape (unpadded) parameters per species
+  std::vector<int> imap;                   // [S * nps_int] API parameter of each, -1: structural zero
+  std::vector<double> params;              // [poff[S]] the parameters (API layout)
+  std::vector<double> shift, scale;        // [S * kD] (kernel columns)
   double e_off[kMaxSpecies] = {0};
   int npad_species = 0;                    // padded parameters per species (training layout)
   hipStream_t stream = nullptr;
@@ -68,7 +81,7 @@ struct aenet_ctx {
 
   DevMem netbuf;        // packed network operands
   DevMem d_blast;       // [kMaxSpecies] output-layer bias per species
-  DevMem d_params;      // [S * nps] the parameters (API layout), device copy
+  DevMem d_params;      // [poff[S]] the parameters (API layout), device copy
   DevMem d_packmap;     // [n_pack] netbuf element -> parameter index (FP64/FP32)
   DevMem d_blastsrc;    // [S] parameter index of each species' output bias
   int64_t n_pack = 0;
@@ -226,7 +239,8 @@ aenet_status pack_networks(aenet_ctx* c) {
     so[s].shift = take((size_t)c->ldG * el);
     so[s].scale = take((size_t)c->ldG * el);
   }
-  // Fills the layout from per-species parameter values P(s) (API order);
+  // Fills the layout from per-species parameter values P(s, k), k indexing
+  // the kernel-shape parameters (layer by layer W_l row-major, then b_l);
   // put(o, idx, v) stores element idx of the section at byte offset o,
   // packB(B, K, N, o, part) a B operand, blast(s, v) the output bias;
   // pad is the value of padded B-operand entries.
@@ -257,15 +271,16 @@ aenet_status pack_networks(aenet_ctx* c) {
           blast(s, P(s, bo));
         }
       }
-      for (int k = 0; k < c->D; ++k) {
-        put(so[s].shift, k, shift_scale_mark < 0 ? shift_scale_mark : c->shift[(size_t)s * c->D + k]);
-        put(so[s].scale, k, shift_scale_mark < 0 ? shift_scale_mark : c->scale[(size_t)s * c->D + k]);
+      for (int k = 0; k < c->kD; ++k) {
+        put(so[s].shift, k, shift_scale_mark < 0 ? shift_scale_mark : c->shift[(size_t)s * c->kD + k]);
+        put(so[s].scale, k, shift_scale_mark < 0 ? shift_scale_mark : c->scale[(size_t)s * c->kD + k]);
       }
     }
   };
   std::vector<unsigned char> host(total, 0);
   double blast_v[kMaxSpecies] = {0};
-  fill([&](int s, size_t k) { return c->params[(size_t)s * c->nps + k]; },
+  auto api = [&](int s, size_t k) { return c->imap[(size_t)s * c->nps_int + k]; };
+  fill([&](int s, size_t k) { return api(s, k) >= 0 ? c->params[api(s, k)] : 0.0; },
        [&](size_t o, int idx, double v) {
          if (el == 8)
            reinterpret_cast<double*>(host.data() + o)[idx] = v;
@@ -286,7 +301,7 @@ aenet_status pack_networks(aenet_ctx* c) {
   if (prec != 2 && c->n_pack == 0) {
     // the element map (built once: the layout depends only on the shapes)
     std::vector<double> map(total / el, -1.0);
-    fill([&](int s, size_t k) { return (double)((size_t)s * c->nps + k); },
+    fill([&](int s, size_t k) { return (double)api(s, k); },
          [&](size_t o, int idx, double v) { map[o / el + idx] = v; },
          [&](const double* B, int K, int N, size_t o, int) { pack_b_operand(0, B, K, N, N, map.data() + o / el); },
          [&](int s, double v) { c->blast_src[s] = (int)v; }, -1.0, -2.0);
@@ -607,8 +622,8 @@ DescParams desc_params(aenet_ctx* c) {
   p.adj = c->d_adj.as<double>();
   p.U = c->d_U.p;
   p.flags = c->d_flags.as<int>();
-  p.t1 = c->nr + 1;
-  p.t2 = c->nr + c->na + 2;
+  p.t1 = c->knr + 1;
+  p.t2 = c->knr + c->kna + 2;
   p.shA = c->d_shA.p;
   p.gang = c->d_gang.p;
   return p;
@@ -619,7 +634,7 @@ DescParams desc_params(aenet_ctx* c) {
 // cost grows with the shell size, the pair sum's with its square), or as the
 // caller chose.
 bool use_factorised(const aenet_ctx* c) {
-  const bool ok = c->na == 2 || c->na == 3 || c->na == 4 || c->na == 6 || c->na == 8;
+  const bool ok = c->kna == 2 || c->kna == 3 || c->kna == 4 || c->kna == 6 || c->kna == 8;
   if (c->ang_method == AENET_ANGULAR_PAIRS || !ok) return false;
   if (c->ang_method == AENET_ANGULAR_FACTORISED) return true;
   return c->ang_mean > 48;
@@ -735,15 +750,15 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
   const bool sh = use_factorised(c);
   if (sh) {
     const size_t el = real_size(c);
-    TRY(ensure(c, c->d_shA, (size_t)c->n * 2 * ang_sh_terms(c->na) * el));
+    TRY(ensure(c, c->d_shA, (size_t)c->n * 2 * ang_sh_terms(c->kna) * el));
     if (forces) TRY(ensure(c, c->d_gang, (size_t)c->n * c->cap_ang * 3 * el));
   }
   DescParams dp = desc_params(c);
   MlpParams mp = mlp_params(c, forces);
   if (sh) {
     prof_begin(c, s, AENET_K_DESC_FWD);
-    launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s, false);
-    launch_ang_sh(true, desc_prec(c), c->na, dp, s);
+    launch_desc_fwd(desc_prec(c), c->knr, c->kna, dp, s, false);
+    launch_ang_sh(true, desc_prec(c), c->kna, dp, s);
     prof_end(c, s);
     prof_begin(c, s, AENET_K_NETWORK);
     launch_mlp(c->prec, mp, n_tiles(mp), s);
@@ -752,11 +767,11 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
     DescParams dq = dp;
     if (!keep_G) dq.G = nullptr;
     prof_begin(c, s, AENET_K_FWD_NETWORK);
-    launch_fwd_mlp(c->prec, c->nr, c->na, dq, mp, n_tiles(mp), s);
+    launch_fwd_mlp(c->prec, c->knr, c->kna, dq, mp, n_tiles(mp), s);
     prof_end(c, s);
   } else {
     prof_begin(c, s, AENET_K_DESC_FWD);
-    launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s);
+    launch_desc_fwd(desc_prec(c), c->knr, c->kna, dp, s);
     prof_end(c, s);
     prof_begin(c, s, AENET_K_NETWORK);
     launch_mlp(c->prec, mp, n_tiles(mp), s);
@@ -764,8 +779,8 @@ aenet_status compute(aenet_ctx* c, hipStream_t s, bool forces, double* vel, doub
   }
   if (forces) {
     prof_begin(c, s, AENET_K_DESC_BWD);
-    if (sh) launch_ang_sh(false, desc_prec(c), c->na, dp, s);
-    launch_desc_bwd(desc_prec(c), c->nr, c->na, dp, s, sh);
+    if (sh) launch_ang_sh(false, desc_prec(c), c->kna, dp, s);
+    launch_desc_bwd(desc_prec(c), c->knr, c->kna, dp, s, sh);
     prof_end(c, s);
     prof_begin(c, s, AENET_K_FORCE_GATHER);
     launch_force_gather(desc_prec(c), (int)c->n, c->cap, c->d_nrad.as<int>(), c->d_ridx.as<uint16_t>(), c->d_pg.p,
@@ -954,7 +969,6 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
   };
   if (m->n_species < 1 || m->n_species > kMaxSpecies) return bad("n_species must be 1..8");
   if (m->radial_order < 0 || m->angular_order < 0) return bad("orders must be >= 0");
-  if (!desc_supported(m->radial_order, m->angular_order)) return bad("descriptor orders not compiled in");
   if (!(m->radial_cutoff > 0) || !(m->angular_cutoff > 0)) return bad("cutoffs must be positive");
   if (!(m->skin >= 0) || !std::isfinite(m->skin)) return bad("skin must be >= 0");
   if (m->precision < 0 || m->precision > 2) return bad("unknown precision");
@@ -980,51 +994,109 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
     }
   }
   c->have_mass = m->mass_amu != nullptr;
+  // the compiled order pair that holds the model's descriptor: the one with
+  // the smallest dimension (then the lowest angular order) among those that
+  // reach both orders and whose descriptor the networks' input layer takes
+  // (at most kMaxWidth components)
+  {
+    int pairs[2 * 64];
+    const int np = std::min(desc_supported_list(pairs, 64), 64);
+    int best = -1;
+    for (int k = 0; k < np; ++k) {
+      const int a = pairs[2 * k], b = pairs[2 * k + 1];
+      if (a < c->nr || b < c->na || (c->S > 1 ? 2 : 1) * (a + b + 2) > kMaxWidth) continue;
+      if (best < 0 || a + b < pairs[2 * best] + pairs[2 * best + 1] ||
+          (a + b == pairs[2 * best] + pairs[2 * best + 1] && b < pairs[2 * best + 1]))
+        best = k;
+    }
+    if (best < 0) {
+      std::string list;
+      for (int k = 0; k < np; ++k)
+        list += (k ? ", " : "") + std::to_string(pairs[2 * k]) + "/" + std::to_string(pairs[2 * k + 1]);
+      return bad("descriptor orders " + std::to_string(c->nr) + "/" + std::to_string(c->na) +
+                 " exceed every compiled pair (" + list + ") whose descriptor dimension is at most " +
+                 std::to_string(kMaxWidth) + " with " + std::to_string(c->S) + " species");
+    }
+    c->knr = pairs[2 * best];
+    c->kna = pairs[2 * best + 1];
+  }
+  const int ktyped = c->knr + 1 + c->kna + 1;
+  c->kD = c->S > 1 ? 2 * ktyped : ktyped;
+  c->colmap.resize(c->D);
+  for (int k = 0; k < c->D; ++k) {
+    const int half = k / typed, r = k % typed;  // channel (typed, weighted) and place in it
+    c->colmap[k] = half * ktyped + (r <= c->nr ? r : c->knr + 1 + (r - c->nr - 1));
+  }
+  // networks: every species has the same number of layers and activations;
+  // the hidden widths may differ (the kernels use the largest of each layer)
   const aenet_net& n0 = m->nets[0];
   if (n0.n_layers < 1 || n0.n_layers > kMaxLayers) return bad("n_layers must be 1..4");
   c->L = n0.n_layers;
-  for (int l = 0; l <= c->L; ++l) {
-    c->w[l] = n0.widths[l];
-    if (c->w[l] < 1 || c->w[l] > kMaxWidth) return bad("widths must be 1..64");
-    c->wp[l] = pad_to(c->w[l], kPad);
-  }
-  if (c->w[0] != c->D) return bad("widths[0] must equal the descriptor dimension " + std::to_string(c->D));
-  if (c->w[c->L] != 1) return bad("the last width must be 1");
   for (int l = 0; l < c->L; ++l) {
     c->act[l] = n0.act[l];
     if (c->act[l] != AENET_ACT_LINEAR && c->act[l] != AENET_ACT_TANH) return bad("unknown activation");
   }
   if (c->act[c->L - 1] != AENET_ACT_LINEAR) return bad("the output layer must be linear");
-  c->ldG = c->wp[0];
-  c->nps = 0;
-  for (int l = 1; l <= c->L; ++l) c->nps += (int64_t)c->w[l] * (c->w[l - 1] + 1);
-  c->params.assign((size_t)c->S * c->nps, 0.0);
-  c->shift.assign((size_t)c->S * c->D, 0.0);
-  c->scale.assign((size_t)c->S * c->D, 1.0);
+  c->poff.assign(c->S + 1, 0);
   for (int s = 0; s < c->S; ++s) {
     const aenet_net& nt = m->nets[s];
-    if (nt.n_layers != c->L) return bad("all species need the same network shape");
-    for (int l = 0; l <= c->L; ++l)
-      if (nt.widths[l] != c->w[l]) return bad("all species need the same network shape");
+    if (nt.n_layers != c->L) return bad("all species need the same number of layers");
+    if (!nt.widths || !nt.act) return bad("widths or act is NULL");
     for (int l = 0; l < c->L; ++l)
       if (nt.act[l] != c->act[l]) return bad("all species need the same activations");
-    double* P = c->params.data() + (size_t)s * c->nps;
-    size_t po = 0;
-    for (int l = 0; l < c->L; ++l) {
-      const size_t nw = (size_t)c->w[l + 1] * c->w[l];
-      if (!nt.W || !nt.b || !nt.W[l] || !nt.b[l]) return bad("missing weights");
-      std::memcpy(P + po, nt.W[l], nw * 8);
-      po += nw;
-      std::memcpy(P + po, nt.b[l], (size_t)c->w[l + 1] * 8);
-      po += c->w[l + 1];
+    for (int l = 0; l <= c->L; ++l)
+      if (nt.widths[l] < 1 || nt.widths[l] > kMaxWidth) return bad("widths must be 1..64");
+    if (nt.widths[0] != c->D) return bad("widths[0] must equal the descriptor dimension " + std::to_string(c->D));
+    if (nt.widths[c->L] != 1) return bad("the last width must be 1");
+    int64_t np = 0;
+    for (int l = 1; l <= c->L; ++l) np += (int64_t)nt.widths[l] * (nt.widths[l - 1] + 1);
+    c->poff[s + 1] = c->poff[s] + np;
+  }
+  c->w[0] = c->kD;
+  c->w[c->L] = 1;
+  for (int l = 1; l < c->L; ++l) {
+    c->w[l] = 0;
+    for (int s = 0; s < c->S; ++s) c->w[l] = std::max(c->w[l], m->nets[s].widths[l]);
+  }
+  for (int l = 0; l <= c->L; ++l) c->wp[l] = pad_to(c->w[l], kPad);
+  c->ldG = c->wp[0];
+  c->nps_int = 0;
+  for (int l = 1; l <= c->L; ++l) c->nps_int += (int64_t)c->w[l] * (c->w[l - 1] + 1);
+  c->params.assign((size_t)c->poff[c->S], 0.0);
+  c->imap.assign((size_t)c->S * c->nps_int, -1);
+  // input normalisation on the kernel columns: the model's columns take its
+  // shift and scale, the others scale 0 (their input is exactly zero)
+  c->shift.assign((size_t)c->S * c->kD, 0.0);
+  c->scale.assign((size_t)c->S * c->kD, 0.0);
+  for (int s = 0; s < c->S; ++s) {
+    const aenet_net& nt = m->nets[s];
+    if (!nt.W || !nt.b) return bad("missing weights");
+    int64_t pa = c->poff[s];         // API index
+    size_t ko = (size_t)s * c->nps_int;  // kernel-shape index of the layer
+    for (int l = 1; l <= c->L; ++l) {
+      const int in = nt.widths[l - 1], out = nt.widths[l], kin = c->w[l - 1];
+      if (!nt.W[l - 1] || !nt.b[l - 1]) return bad("missing weights");
+      for (int q = 0; q < out; ++q)
+        for (int k = 0; k < in; ++k) {
+          c->params[pa] = nt.W[l - 1][(size_t)q * in + k];
+          c->imap[ko + (size_t)q * kin + (l == 1 ? c->colmap[k] : k)] = (int)pa;
+          ++pa;
+        }
+      ko += (size_t)c->w[l] * kin;
+      for (int q = 0; q < out; ++q) {
+        c->params[pa] = nt.b[l - 1][q];
+        c->imap[ko + q] = (int)pa;
+        ++pa;
+      }
+      ko += c->w[l];
     }
     for (int k = 0; k < c->D; ++k) {
-      if (nt.in_shift) c->shift[(size_t)s * c->D + k] = nt.in_shift[k];
-      if (nt.in_scale) c->scale[(size_t)s * c->D + k] = nt.in_scale[k];
+      c->shift[(size_t)s * c->kD + c->colmap[k]] = nt.in_shift ? nt.in_shift[k] : 0.0;
+      c->scale[(size_t)s * c->kD + c->colmap[k]] = nt.in_scale ? nt.in_scale[k] : 1.0;
     }
     c->e_off[s] = nt.e_offset;
-    for (size_t k = 0; k < (size_t)c->nps; ++k)
-      if (!std::isfinite(P[k])) return bad("non-finite network parameter");
+    for (int64_t k = c->poff[s]; k < c->poff[s + 1]; ++k)
+      if (!std::isfinite(c->params[k])) return bad("non-finite network parameter");
   }
   // MLP shape
   c->mlp.n_layers = c->L;
@@ -1066,15 +1138,19 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
   // masses (kappa / m per species) and the API -> padded parameter map
   double invmk[kMaxSpecies] = {0};
   for (int s = 0; s < c->S; ++s) invmk[s] = c->mass[s] > 0 ? kKappa / c->mass[s] : 0.0;
-  std::vector<int> pidx((size_t)c->S * c->nps);
+  std::vector<int> pidx(c->params.size());
   for (int s = 0; s < c->S; ++s) {
-    size_t po = (size_t)s * c->nps, go = 0;
+    size_t ko = (size_t)s * c->nps_int, go = 0;
+    auto put = [&](int pad_index) {
+      const int a = c->imap[ko++];
+      if (a >= 0) pidx[a] = (int)((size_t)s * c->npad_species + pad_index);
+    };
     for (int l = 1; l <= c->L; ++l) {
       const int in = c->w[l - 1], out = c->w[l];
       const int outp = l == c->L ? 1 : c->wp[l], inp = c->wp[l - 1];
       for (int q = 0; q < out; ++q)
-        for (int k = 0; k < in; ++k) pidx[po++] = (int)((size_t)s * c->npad_species + go + (size_t)q * inp + k);
-      for (int q = 0; q < out; ++q) pidx[po++] = (int)((size_t)s * c->npad_species + go + (size_t)outp * inp + q);
+        for (int k = 0; k < in; ++k) put((int)(go + (size_t)q * inp + k));
+      for (int q = 0; q < out; ++q) put((int)(go + (size_t)outp * inp + q));
       go += (size_t)outp * inp + outp;
     }
   }
@@ -1108,7 +1184,7 @@ const char* aenet_last_error(const aenet_ctx* c) { return c ? c->err.c_str() : g
 
 int aenet_descriptor_dim(const aenet_ctx* c) { return c ? c->D : -1; }
 
-int64_t aenet_n_params(const aenet_ctx* c) { return c ? (int64_t)c->S * c->nps : -1; }
+int64_t aenet_n_params(const aenet_ctx* c) { return c ? (int64_t)c->params.size() : -1; }
 
 aenet_status aenet_get_params(aenet_ctx* c, double* params) {
   if (!c || !params) return AENET_E_INVALID;
@@ -1362,10 +1438,10 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
                    c->d_flags.as<int>(), s);
   TRY(build_checked(c, s));
   const bool sh = use_factorised(c);
-  if (sh) TRY(ensure(c, c->d_shA, (size_t)n * 2 * ang_sh_terms(c->na) * real_size(c)));
+  if (sh) TRY(ensure(c, c->d_shA, (size_t)n * 2 * ang_sh_terms(c->kna) * real_size(c)));
   DescParams dp = desc_params(c);
-  launch_desc_fwd(desc_prec(c), c->nr, c->na, dp, s, !sh);
-  if (sh) launch_ang_sh(true, desc_prec(c), c->na, dp, s);
+  launch_desc_fwd(desc_prec(c), c->knr, c->kna, dp, s, !sh);
+  if (sh) launch_ang_sh(true, desc_prec(c), c->kna, dp, s);
   HIP_TRY(c, hipGetLastError());
   const size_t el = real_size(c);
   std::vector<unsigned char> buf((size_t)n * c->ldG * el);
@@ -1374,9 +1450,10 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
   c->counters_clean = true;
   for (int64_t p = 0; p < n; ++p) {
     double* dst = G + (size_t)c->perm[p] * c->D;
-    for (int k = 0; k < c->D; ++k)
-      dst[k] = el == 8 ? reinterpret_cast<double*>(buf.data())[(size_t)p * c->ldG + k]
-                       : (double)reinterpret_cast<float*>(buf.data())[(size_t)p * c->ldG + k];
+    for (int k = 0; k < c->D; ++k) {
+      const size_t at = (size_t)p * c->ldG + c->colmap[k];
+      dst[k] = el == 8 ? reinterpret_cast<double*>(buf.data())[at] : (double)reinterpret_cast<float*>(buf.data())[at];
+    }
   }
   return AENET_OK;
 }
@@ -1620,7 +1697,7 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   launch_sum((int64_t)n + n_struct, tmp, c->d_red.as<double>(), loss, s);
   // descriptor JVP along the force adjoint, then double back-propagation
   DescParams dp = desc_params(c);
-  launch_desc_jvp(desc_prec(c), c->nr, c->na, dp, s);
+  launch_desc_jvp(desc_prec(c), c->knr, c->kna, dp, s);
   MlpParams mp = mlp_params(c, false);
   mp.U = c->d_U.p;
   mp.eps_atom = c->d_eps.as<double>();
@@ -1640,7 +1717,7 @@ aenet_status aenet_loss_grad_dev(aenet_ctx* c, int n_struct, const int64_t* offs
   launch_mlp_train(c->prec == 0 ? 0 : 1, mp, nblocks, s);
   launch_grad_reduce(nblocks, npad, c->d_gradpart.as<double>(), c->d_gradpad.as<double>(), s);
   // padded -> API layout
-  launch_take((int)(c->S * c->nps), c->d_pidx.as<int>(), c->d_gradpad.as<double>(), grad, s);
+  launch_take((int)c->params.size(), c->d_pidx.as<int>(), c->d_gradpad.as<double>(), grad, s);
   HIP_TRY(c, hipGetLastError());
   int hf[8];
   TRY(read_flags(c, s, hf));
