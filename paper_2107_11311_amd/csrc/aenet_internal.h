@@ -152,6 +152,10 @@ struct DescParams {
   // shA [n x 2 (N_a+1)^2] the per-atom sums of the forward pass; gang
   // [n x cap_ang x 3] the angular part of dE_i/dd_e per angular row position
   int t1, t2;
+  // the force pass's blocks: block k computes atom xmap[k] (-1: none); n_grid
+  // blocks (the atoms in an XCD-aware order, see prepare())
+  const int* xmap;
+  int n_grid;
   void* shA;
   void* gang;
   const double* adj;     // [n*3] JVP direction (loss adjoint of the forces)

@@ -58,10 +58,11 @@ __host__ __device__ constexpr size_t bwd_coef_offset(int ca) {
 template <typename R, int NR, int NA, bool VIR, bool AEXT>
 __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // one wavefront per block and atom; the launch covers exactly the n atoms,
-  // so every load below is unconditional (loads under a branch are issued
-  // one after another, each waiting for the last)
-  const int i = blockIdx.x;
+  // one wavefront per block and atom (a block without an atom returns at
+  // once), so every load below is unconditional (loads under a branch are
+  // issued one after another, each waiting for the last)
+  const int i = p.xmap[blockIdx.x];
+  if (i < 0) return;
   const int l = threadIdx.x & 63;
   const int ca = p.cap_ang;
   R* ux = reinterpret_cast<R*>(smem);
@@ -588,13 +589,13 @@ template <typename R, int NR, int NA>
 void launch_bwd(const DescParams& p, hipStream_t s, bool ext) {
   const size_t per_atom = ((ext ? 0 : bwd_coef_offset<R>(p.cap_ang)) + (size_t)p.n_species * (NR + 1)) * sizeof(R);
   if (p.vir && ext)
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, true>), dim3(p.n), dim3(64), per_atom, s, p);
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, true>), dim3(p.n_grid), dim3(64), per_atom, s, p);
   else if (p.vir)
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, false>), dim3(p.n), dim3(64), per_atom, s, p);
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, true, false>), dim3(p.n_grid), dim3(64), per_atom, s, p);
   else if (ext)
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false, true>), dim3(p.n), dim3(64), per_atom, s, p);
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false, true>), dim3(p.n_grid), dim3(64), per_atom, s, p);
   else
-    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false, false>), dim3(p.n), dim3(64), per_atom, s, p);
+    hipLaunchKernelGGL((k_desc_bwd<R, NR, NA, false, false>), dim3(p.n_grid), dim3(64), per_atom, s, p);
 }
 
 template <typename R, int NR, int NA>

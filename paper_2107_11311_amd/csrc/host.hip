@@ -130,6 +130,8 @@ struct aenet_ctx {
   DevMem d_bin_count, d_bin_atoms;  // MD: cell bins filled by the integrator
   DevMem d_ridx, d_nrad;            // contributing entries, from the forward pass
   DevMem d_shA, d_gang;             // factorised angular descriptor: per-atom sums, entry gradients
+  DevMem d_xmap;                    // [n_grid] atom of each force-pass block (-1: none)
+  int n_grid = 0;
   DevMem d_judge;                   // partial sums of aenet_rms_diff_dev
   DevMem d_vir;                     // [9][n] per-atom virial, then its 9 sums
   bool want_vir = false;            // the next force pass also forms the virial
@@ -453,6 +455,32 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
     }
     HIP_TRY(c, hipMemcpy(c->d_segoff.p, offsets, (n_struct + 1) * 8, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->d_segcount.p, segcount.data(), n_struct * 8, hipMemcpyHostToDevice));
+    // XCD-aware order of the force pass's blocks (one atom each): the
+    // hardware hands block k to XCD k mod 8, and XCD x is given the x-th
+    // eighth of every species' atoms (a compact region in the Z-order), so
+    // that the gradients the pass scatters to a region's neighbour rows meet
+    // in that XCD's L2 and leave it as whole lines
+    {
+      std::vector<int> reg_n(8, 0);
+      std::vector<int> xm;
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int> fill(8, 0);
+        for (int s = 0; s < c->S; ++s) {
+          const int a0 = c->sp_off[s], cs = c->sp_off[s + 1] - a0;
+          for (int r = 0; r < cs; ++r) {
+            const int x = (int)((int64_t)r * 8 / cs);
+            if (pass == 0)
+              ++reg_n[x];
+            else
+              xm[8 * (size_t)fill[x]++ + x] = a0 + r;
+          }
+        }
+        if (pass == 0) xm.assign(8 * (size_t)std::max(1, *std::max_element(reg_n.begin(), reg_n.end())), -1);
+      }
+      c->n_grid = (int)xm.size();
+      TRY(ensure(c, c->d_xmap, xm.size() * 4));
+      HIP_TRY(c, hipMemcpy(c->d_xmap.p, xm.data(), xm.size() * 4, hipMemcpyHostToDevice));
+    }
     c->nbr_valid = false;
     c->cap = 0;
   }
@@ -625,6 +653,8 @@ DescParams desc_params(aenet_ctx* c) {
   p.t1 = c->knr + 1;
   p.t2 = c->knr + c->kna + 2;
   p.shA = c->d_shA.p;
+  p.xmap = c->d_xmap.as<int>();
+  p.n_grid = c->n_grid;
   p.gang = c->d_gang.p;
   return p;
 }
@@ -1332,7 +1362,8 @@ aenet_status aenet_energy_forces_noalloc(aenet_ctx* c, int64_t n, const double* 
                     &c->d_Eorig, &c->d_G, &c->d_gG, &c->d_U, &c->d_adj, &c->d_eps, &c->d_tmp, &c->d_red,
                     &c->d_scal, &c->d_flags, &c->d_cell_count, &c->d_cell_start, &c->d_cell_fill,
                     &c->d_cell_atoms, &c->d_atom_cell, &c->d_nbr, &c->d_segs, &c->d_nnb, &c->d_nang,
-                    &c->d_rev, &c->d_ridx, &c->d_nrad, &c->d_vir, &c->d_build, &c->d_shA, &c->d_gang};
+                    &c->d_rev, &c->d_ridx, &c->d_nrad, &c->d_vir, &c->d_build, &c->d_shA, &c->d_gang,
+                    &c->d_pg, &c->d_xmap};
   constexpr int nbufs = (int)(sizeof(bufs) / sizeof(bufs[0]));
   struct Saved {
     void* p;

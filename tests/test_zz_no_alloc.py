@@ -75,3 +75,24 @@ def test_noalloc_rejects_structures_beyond_the_workspace(A):
     assert E1 == E0 and np.array_equal(F1, F0)
     ctx.close()
     ctx2.close()
+
+
+def test_noalloc_first_then_larger_dev_call(A):
+    """A fresh context whose first call is the no-allocation one, then the
+    context's own entry point on a larger structure, then the no-allocation
+    one again: every per-call buffer the no-allocation call used is the
+    workspace's and goes back afterwards, so the context's own buffers grow
+    from nothing and the results match a context that never used the
+    workspace."""
+    import torch
+    m = I.load_model("water64")
+    small, large = I.water_box(20, 4321), I.make_system("water64")
+    ctx = A.Context(m, "fp64")
+    ref = A.Context(m, "fp64")
+    for s, noalloc in ((small, True), (large, False), (large, True), (small, False)):
+        E1, Ea1, F1 = _run(torch, ctx, s, noalloc)
+        E0, Ea0, F0 = _run(torch, ref, s, False)
+        print(f"n={len(s.pos)} noalloc={noalloc}: E {E1:.15g} ref {E0:.15g}")
+        assert E1 == E0 and np.array_equal(Ea1, Ea0) and np.array_equal(F1, F0)
+    ctx.close()
+    ref.close()
