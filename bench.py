@@ -124,6 +124,148 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Arithmetic peaks measured on the GPU by microbenchmarks (libaenet_probe.so:
+# FMA chains on the vector ALUs, matrix-core instruction chains), beside the
+# published figures they are compared with.
+PEAK_PROBES = {
+    "fp64_vector_fma": ("probe_fma_f64", "float64", 78.6e12),
+    "fp32_vector_fma": ("probe_fma_f32", "float32", 157.3e12),
+    "fp64_mfma": ("probe_mfma_f64", "float64", 78.6e12),
+    "fp32_mfma": ("probe_mfma_f32", "float32", 157.3e12),
+    "bf16_mfma": ("probe_mfma_bf16", "float32", 2.5e15),
+}
+
+
+def measure_peaks(target_ms=10.0):
+    """Rates of the probe kernels (2048 blocks of 256 threads, timed with HIP
+    events on torch's stream, the iteration count scaled to about target_ms
+    per launch; best of three launches)."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2107_11311_amd", "libaenet_probe.so"))
+    blocks = 2048
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, (fn, dtype, published) in PEAK_PROBES.items():
+        f = getattr(lib, fn)
+        f.argtypes = [C.c_int64, C.c_int, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+        f.restype = C.c_int
+        buf = torch.zeros(blocks * 256, dtype=getattr(torch, dtype), device="cuda:0")
+        flops = C.c_double()
+
+        def run(iters):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            code = f(int(iters), blocks, C.c_void_p(buf.data_ptr()), C.byref(flops), C.c_void_p(stream.cuda_stream))
+            e1.record()
+            torch.cuda.synchronize()
+            if code != 0:
+                raise RuntimeError(f"{fn}: HIP error {code}")
+            return e0.elapsed_time(e1)
+
+        iters = 256
+        run(iters)
+        ms = run(iters)
+        iters = max(256, int(iters * target_ms / max(ms, 1e-3)))
+        best = min(run(iters) for _ in range(3))
+        rate = flops.value / (best * 1e-3)
+        out[name] = dict(tflops=rate / 1e12, published_tflops=published / 1e12, frac_of_published=rate / published,
+                         iterations=iters, ms=best)
+    return out
+
+
+# The small case and the training batch, measured in their own units
+SMALL_CALLS = 300      # energy+force calls of the 192-atom box
+BATCH_LAUNCHES = 10    # loss-gradient launches of the 256-box batch
+
+
+def run_water64(A, I, oracle_mod, precision):
+    """192-atom water box, one energy+force call at a time (device buffers,
+    list rebuilt every call): calls/s x 192 atoms; a latency-bound case."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    model = I.load_model("water64")
+    s = I.make_system("water64")
+    n = s.pos.shape[0]
+    ctx = A.Context(model, precision, skin=0.0, device=0)
+    pos = torch.from_numpy(s.pos).to(dev)
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    F = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+    for _ in range(10):
+        ctx.energy_forces_dev(pos, s.species, s.box, s.pbc, e, None, F)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(SMALL_CALLS):
+        ctx.energy_forces_dev(pos, s.species, s.box, s.pbc, e, None, F)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = dict(atoms=n, calls=SMALL_CALLS, calls_per_s=SMALL_CALLS / wall, atom_evals_per_s=n * SMALL_CALLS / wall,
+               ms_per_call=1e3 * wall / SMALL_CALLS, bound="latency (one 192-atom structure per call)")
+    if oracle_mod is not None:
+        E0, _, F0 = oracle_mod.energy_forces(model, s.pos, s.species, s.box, s.pbc)
+        dF = F.cpu().numpy() - F0
+        out.update(force_rmse=float(np.sqrt(np.mean(dF ** 2))), force_max_abs_err=float(np.abs(dF).max()),
+                   force_rms=float(np.sqrt(np.mean(F0 ** 2))), energy_rel_err=abs(e.item() - E0) / abs(E0))
+    ctx.close()
+    return out
+
+
+def run_waterbatch(A, I, oracle_mod, precisions):
+    """The 256 water boxes of 64-512 H2O (221,184 atoms) in one launch of the
+    energy+force loss and its parameter gradient (aenet_loss_grad_dev):
+    atoms x launches / s.  References from the second water network on the
+    GPU in FP64; the first structure's loss and gradient against the oracle."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    model = I.load_model("water4096")
+    ref = I.load_model("water4096_ref")
+    boxes = I.make_batch("waterbatch256")
+    offs = np.concatenate([[0], np.cumsum([len(b.pos) for b in boxes])]).astype(np.int64)
+    pos_np = np.vstack([b.pos for b in boxes])
+    sp = np.concatenate([b.species for b in boxes])
+    bx = np.vstack([b.box for b in boxes])
+    n = int(offs[-1])
+    pos = torch.from_numpy(pos_np).to(dev)
+    ctx_ref = A.Context(ref, "fp64", device=0)
+    e_ref = torch.zeros(len(boxes), dtype=torch.float64, device=dev)
+    f_ref = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+    ctx_ref.energy_forces_batch_dev(offs, pos, sp, bx, (1, 1, 1), e_ref, None, f_ref)
+    torch.cuda.synchronize()
+    ctx_ref.close()
+    out = {}
+    for prec in precisions:
+        ctx = A.Context(model, prec, device=0)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        grad = torch.zeros(ctx.n_params(), dtype=torch.float64, device=dev)
+        for _ in range(2):
+            ctx.loss_grad_dev(offs, pos, sp, bx, (1, 1, 1), e_ref, f_ref, 1.0, loss, grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(BATCH_LAUNCHES):
+            ctx.loss_grad_dev(offs, pos, sp, bx, (1, 1, 1), e_ref, f_ref, 1.0, loss, grad)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r = dict(atoms=n, structures=len(boxes), launches=BATCH_LAUNCHES, ms_per_launch=1e3 * wall / BATCH_LAUNCHES,
+                 atoms_per_s=n * BATCH_LAUNCHES / wall, loss=loss.item(), grad_norm=float(grad.norm().item()))
+        if oracle_mod is not None:
+            a, b = int(offs[0]), int(offs[1])
+            l1 = torch.zeros(1, dtype=torch.float64, device=dev)
+            g1 = torch.zeros_like(grad)
+            ctx.loss_grad_dev(np.array([0, b - a]), pos[a:b].contiguous(), sp[a:b], bx[:1], (1, 1, 1),
+                              e_ref[:1].contiguous(), f_ref[a:b].contiguous(), 1.0, l1, g1)
+            torch.cuda.synchronize()
+            L0, G0 = oracle_mod.loss_grad(model, [0, b - a], pos_np[a:b], sp[a:b], bx[:1], (1, 1, 1),
+                                          e_ref[:1].cpu().numpy(), f_ref[a:b].cpu().numpy(), 1.0)
+            g1 = g1.cpu().numpy()
+            r.update(oracle_structure_atoms=b - a, loss_rel_err=abs(l1.item() - L0) / abs(L0),
+                     grad_max_rel_err=float(np.abs(g1 - G0).max() / np.abs(G0).max()))
+        out[prec] = r
+        ctx.close()
+    return out
+
+
 def roofline_of(kt, model, n, n_r, n_a, widths, mode, workload, factorised=False):
     """Roofline position of the kernel class with the largest total time:
     algorithmic flops per launch (formula above, measured mean neighbour
@@ -417,9 +559,11 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--modes", default="fp64,fp32,bf16", help="modes of the water4096 workload")
-    ap.add_argument("--workloads", default="water4096,lisio120k,water1M",
+    ap.add_argument("--workloads", default="water4096,lisio120k,water1M,water64,waterbatch256",
                     help="water4096 (the headline), lisio120k (120,000-atom Li/Si/O), water1M "
-                         "(1,000,002-atom water with the water4096 network)")
+                         "(1,000,002-atom water with the water4096 network), water64 (192-atom "
+                         "energy+force calls), waterbatch256 (loss gradient of 256 boxes in one launch)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the arithmetic peak microbenchmarks")
     ap.add_argument("--big-steps", type=int, default=0,
                     help="timed steps of the two large workloads (0: their specified counts)")
     ap.add_argument("--sample-atoms", type=int, default=64,
@@ -474,13 +618,33 @@ def main():
     from paper_2107_11311_amd import inputs as I
 
     A.load()
+    peaks = None if args.no_peaks else measure_peaks()
     wanted = [w for w in args.workloads.split(",") if w]
     out_modes = {}
     rooflines = {}
     cpu = None
     headline = None
     virial = None
+
+    def oracle_or_none():
+        if args.no_cpu_baseline:
+            return None
+        import oracle
+        oracle.build()
+        return oracle
+
     for wl in wanted:
+        if wl == "water64":
+            log("water64: 192 atoms, energy+force calls")
+            for m in ("fp64", "fp32", "bf16"):
+                out_modes[f"water64/{m}"] = run_water64(A, I, oracle_or_none(), m)
+            continue
+        if wl == "waterbatch256":
+            log("waterbatch256: 256 boxes, 221,184 atoms, loss gradient")
+            for m, r in run_waterbatch(A, I, oracle_or_none(), ("fp64", "fp32")).items():
+                out_modes[f"waterbatch256/{m}"] = r
+            torch.cuda.empty_cache()
+            continue
         spec = WORKLOADS[wl]
         cfg = I.CONFIGS[spec["config"]]
         model = I.load_model(spec["model"])
@@ -507,6 +671,10 @@ def main():
             if "kernel_times" in r:
                 fact = (not m.endswith(":pairs")) and (m.endswith(":factorised") or n_a > 48)
                 entry["roofline"] = roofline_of(r["kernel_times"], model, n, n_r, n_a, widths, m, wl, fact)
+                if peaks:
+                    pm = peaks["fp64_vector_fma" if m.startswith("fp64") else "fp32_vector_fma"]["tflops"]
+                    entry["roofline"].update(peak_measured=pm,
+                                             frac_of_measured=entry["roofline"]["achieved"] / pm)
                 rooflines[key] = entry["roofline"]
             out_modes[key] = entry
         # oracle: force RMSE on the final positions (all atoms for the small box,
@@ -576,6 +744,7 @@ def main():
         "roofline": rooflines.get(f"{WORKLOAD}/{main_mode}"),
         "cpu_baseline": cpu,
         "virial": virial,
+        "peaks_measured": peaks,
     }
     print(json.dumps(line))
 

@@ -39,3 +39,22 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_2107_11311_amd import aenet
     with pytest.raises(RuntimeError):
         aenet.load(str(tmp_path / "missing.so"))
+
+
+PROBE_LIB = os.path.join(ROOT, "paper_2107_11311_amd", "libaenet_probe.so")
+
+
+@pytest.mark.skipif(not os.path.exists(PROBE_LIB), reason="probe library not built")
+def test_peak_probes_export_what_the_benchmark_calls():
+    """bench.py's arithmetic peak microbenchmarks (a separate library; no part
+    of the method) export every probe the benchmark names."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    lib = ctypes.CDLL(PROBE_LIB)
+    for fn, _, published in bench.PEAK_PROBES.values():
+        assert hasattr(lib, fn), fn
+        assert published > 0
+    # the probe library is not part of the C ABI
+    assert not any(n.startswith("probe_") for n in declared())
