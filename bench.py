@@ -366,7 +366,12 @@ def run_mode(A, model, sysm, vel0, precision, steps, warmup, dt, profile):
     ep = torch.zeros(1, dtype=torch.float64, device=dev)
     ek = torch.zeros(1, dtype=torch.float64, device=dev)
     F = torch.zeros(n, 3, dtype=torch.float64, device=dev)
-    if warmup:
+    # the warm-up steps in two calls, so that the timed call is not the first
+    # to continue from the state a call left (first-use costs of that path)
+    if warmup >= 2:
+        ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, warmup - 1, ep, ek, F)
+        ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, 1, ep, ek, F)
+    elif warmup:
         ctx.md_step_dev(pos, vel, sysm.species, sysm.box, sysm.pbc, dt, warmup, ep, ek, F)
     torch.cuda.synchronize()
     e0 = (ep + ek).item()
@@ -401,6 +406,17 @@ def run_mode(A, model, sysm, vel0, precision, steps, warmup, dt, profile):
     out["final_E"] = et.item()
     ctx.close()
     return out
+
+
+def warm_process(A, model, sysm, vel0, dt):
+    """Untimed, once per workload before its first timed mode: the timing
+    sequence of run_mode on a throwaway context (a few steps, result
+    discarded).  The first pass of a process through that sequence pays
+    one-time costs of the runtime, torch's events and the library (about
+    0.3 ms, on the host and on the first call that continues from a kept
+    state) that no later pass sees; they are kept out of every mode's timed
+    steps."""
+    run_mode(A, model, sysm, vel0, "fp64", 4, 2, dt, profile=False)
 
 
 def run_student(args):
@@ -656,6 +672,7 @@ def main():
         warm = args.warmup
         modes = [m for m in (args.modes.split(",") if wl == WORKLOAD else spec["modes"]) if m]
         log(f"{wl}: {n} atoms, modes {modes}, {steps} steps")
+        warm_process(A, model, sysm, vel0, dt)
         res = {m: run_mode(A, model, sysm, vel0, m, steps, warm, dt, profile=True) for m in modes}
         if wl == WORKLOAD and args.equil > 0 and "fp64" in modes:
             pos_eq, vel_eq = equilibrate(A, model, sysm, vel0, dt, args.equil, cfg["T"])

@@ -138,6 +138,7 @@ struct aenet_ctx {
   DevMem d_build;  // [2] ints: decision of the current build, block counter
   DevMem d_save_pos, d_save_vel, d_save_F, d_estruct, d_gradpart, d_gradpad;
   DevMem h_pos, h_vel, h_F, h_E;  // device staging for the host-pointer entry points
+  int* h_flags = nullptr;          // [16] pinned host copy of the status words
 
   // kernel timing
   bool profiling = false;
@@ -709,9 +710,12 @@ aenet_status grow_caps(aenet_ctx* c, const int* hf) {
   return ensure_rows(c);
 }
 
-aenet_status read_flags(aenet_ctx* c, hipStream_t s, int* hf) {
-  HIP_TRY(c, hipMemcpyAsync(hf, c->d_flags.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+// the first `count` status words of d_flags, through the context's pinned
+// buffer (a copy into pageable memory goes through the runtime's staging path)
+aenet_status read_flags(aenet_ctx* c, hipStream_t s, int* hf, int count = 8) {
+  HIP_TRY(c, hipMemcpyAsync(c->h_flags, c->d_flags.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  std::memcpy(hf, c->h_flags, count * sizeof(int));
   return AENET_OK;
 }
 
@@ -1154,6 +1158,13 @@ aenet_status aenet_setup(const aenet_model* m, aenet_ctx** out) {
     delete c;
     return AENET_E_DEVICE;
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    c->h_flags = nullptr;
+    g_setup_error = "pinned host memory for the status words could not be allocated";
+    aenet_destroy(c);
+    return AENET_E_DEVICE;
+  }
   // the device's no-allocation workspace (looked up once per device)
   if (!scratch_address(c->device)) {
     g_setup_error = "hipGetSymbolAddress of the no-allocation workspace failed";
@@ -1207,6 +1218,7 @@ void aenet_destroy(aenet_ctx* c) {
     (void)hipStreamDestroy(c->stream);
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->h_flags) (void)hipHostFree(c->h_flags);
   delete c;
 }
 
@@ -1524,8 +1536,7 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
     launch_same_wrapped(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
                         c->d_boxes.as<BoxInfo>(), c->pbc, pos, flags + 9, s);
     int hf[10];
-    HIP_TRY(c, hipMemcpyAsync(hf, c->d_flags.p, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
+    TRY(read_flags(c, s, hf, 10));
     if (hf[0] & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
     resume = hf[9] == 0;
   }
@@ -1621,8 +1632,7 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
       if (last) outputs();
       HIP_TRY(c, hipGetLastError());
       int hf[10];
-      HIP_TRY(c, hipMemcpyAsync(hf, c->d_flags.p, 10 * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(c, hipStreamSynchronize(s));
+      TRY(read_flags(c, s, hf, 10));
       if (!(hf[0] & kFlagOverflow)) {
         TRY(flag_status(c, hf[0]));
         dev_builds = hf[8];
