@@ -238,10 +238,8 @@ void launch_gather_in(int n, const int* perm, const double* src, double* dst, in
                       hipStream_t s);
 void launch_scatter_out(int n, const int* perm, const double* src3, double* dst3,
                         const double* src1, double* dst1, hipStream_t s);
-void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
-                             const BoxInfo* boxes, const int pbc[3], double* dst, hipStream_t s);
 // *differ |= 1 unless every caller-order position src[perm[p]] equals, bitwise,
-// the wrapped internal position pos[p] (what launch_wrap_scatter_out writes)
+// the wrapped internal position pos[p] (what launch_md_outputs writes)
 void launch_same_wrapped(int n, const int* perm, const double* pos, const int* seg,
                          const BoxInfo* boxes, const int pbc[3], const double* src, int* differ,
                          hipStream_t s);
@@ -285,8 +283,14 @@ void launch_sum_rows(int rows, int64_t n, const double* x, double* partials, dou
 // out = sqrt(sum_k (x_k - y_k)^2 / n), summed in a fixed order
 void launch_rms_diff(int64_t n, const double* x, const double* y, double* partials, double* out,
                      hipStream_t s);
-void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
-                    hipStream_t s);
+// the outputs of an MD call: E = sum E_i and the kinetic energy into *e_pot
+// and *e_kin (partials: 2 * reduce_blocks(n) doubles), the wrapped positions,
+// velocities and (F_out non-NULL) forces scattered to the caller's order;
+// nothing is written if flags[0] or flags[9] is set when the kernels run
+void launch_md_outputs(int n, const int* perm, const double* E, const double* pos, const double* vel,
+                       const double* F, const double* mass, const int* species, const int* seg,
+                       const BoxInfo* boxes, const int pbc[3], const int* flags, double* partials, double* e_pot,
+                       double* e_kin, double* pos_out, double* vel_out, double* F_out, hipStream_t s);
 void launch_segment_sum(int n_seg, const int64_t* seg_off, const double* x, double* out,
                         hipStream_t s);
 void launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_t s);

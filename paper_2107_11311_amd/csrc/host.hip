@@ -506,7 +506,7 @@ aenet_status prepare(aenet_ctx* c, int n_struct, const int64_t* offsets, const i
   TRY(ensure(c, c->d_tmp, (nb + n_struct) * 8));
   TRY(ensure(c, c->d_G, nb * c->ldG * el));
   TRY(ensure(c, c->d_gG, nb * c->ldG * el));
-  TRY(ensure(c, c->d_red, (size_t)(reduce_blocks(n + n_struct) + 1) * 8));
+  TRY(ensure(c, c->d_red, (size_t)(2 * reduce_blocks(n + n_struct) + 1) * 8));  // two rows of partials
   TRY(ensure(c, c->d_scal, 8 * 8));
   TRY(ensure(c, c->d_flags, 16 * 4));
   TRY(ensure(c, c->d_cell_count, (size_t)std::max(cells, (int64_t)1) * 4));
@@ -1528,23 +1528,27 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   // [9] positions differ from the kept state
   HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 16 * sizeof(int), s));
   launch_gather_in(N, c->d_perm.as<int>(), vel, c->d_vel.as<double>(), flags, s);
-  if (resume) {
-    // positions the caller hands back unchanged (bitwise what the last call
-    // wrote) continue from the kept device state: its forces, rows and list
-    // reference stay valid, so neither a build nor a force evaluation is
-    // needed before the first step
-    launch_same_wrapped(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
-                        c->d_boxes.as<BoxInfo>(), c->pbc, pos, flags + 9, s);
-    int hf[10];
-    TRY(read_flags(c, s, hf, 10));
-    if (hf[0] & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
-    resume = hf[9] == 0;
-  }
-  if (!resume) {
+  // The start from the caller's positions: a list build and a force
+  // evaluation.
+  auto fresh_start = [&]() -> aenet_status {
     launch_gather_in(N, c->d_perm.as<int>(), pos, c->d_pos.as<double>(), flags, s);
     TRY(build_checked(c, s));
-    TRY(compute(c, s, true, nullptr, 0.0));
-  }
+    return compute(c, s, true, nullptr, 0.0);
+  };
+  // Positions the caller hands back unchanged (bitwise what the last call
+  // wrote) continue from the kept device state: its forces, rows and list
+  // reference stay valid, so neither a build nor a force evaluation is
+  // needed before the first step.  The comparison runs on the device and the
+  // call goes on as if it held (no wait here); its result is read with the
+  // first chunk's status words, and if the state was stale (flags[9]) that
+  // chunk, which wrote nothing to the caller, is discarded and the call
+  // starts over from the caller's positions and velocities.
+  bool speculative = resume;
+  if (resume)
+    launch_same_wrapped(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
+                        c->d_boxes.as<BoxInfo>(), c->pbc, pos, flags + 9, s);
+  else
+    TRY(fresh_start());
   const double half_dt = 0.5 * dt;
   const double hs2 = 0.25 * c->skin * c->skin;
   const int K = std::max(1, c->rebuild_every);
@@ -1554,18 +1558,14 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   // read is the call's only wait
   auto outputs = [&]() {
     double* scal = c->d_scal.as<double>();
-    launch_sum(N, c->d_E.as<double>(), c->d_red.as<double>(), e_pot ? e_pot : scal, s);
-    launch_kinetic(N, c->d_vel.as<double>(), c->d_mass.as<double>(), c->d_species.as<int>(),
-                   c->d_tmp.as<double>(), s);
-    launch_sum(N, c->d_tmp.as<double>(), c->d_red.as<double>(), e_kin ? e_kin : scal + 1, s);
-    launch_wrap_scatter_out(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
-                            c->d_boxes.as<BoxInfo>(), c->pbc, pos, s);
-    launch_scatter_out(N, c->d_perm.as<int>(), c->d_vel.as<double>(), vel, nullptr, nullptr, s);
-    if (forces) launch_scatter_out(N, c->d_perm.as<int>(), c->d_F.as<double>(), forces, nullptr, nullptr, s);
+    launch_md_outputs(N, c->d_perm.as<int>(), c->d_E.as<double>(), c->d_pos.as<double>(), c->d_vel.as<double>(),
+                      c->d_F.as<double>(), c->d_mass.as<double>(), c->d_species.as<int>(), c->d_seg.as<int>(),
+                      c->d_boxes.as<BoxInfo>(), c->pbc, flags, c->d_red.as<double>(), e_pot ? e_pot : scal,
+                      e_kin ? e_kin : scal + 1, pos, vel, forces, s);
   };
   int t = 0;  // steps done
   bool bins_clean = false;
-  do {
+  for (;;) {
     const int len = std::min(K - (t % K), n_steps - t);
     const bool last = t + len >= n_steps;
     // checkpoint for a capacity retry
@@ -1573,6 +1573,7 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
       launch_copy3(3 * (int64_t)N, c->d_pos.as<double>(), c->d_save_pos.as<double>(), c->d_vel.as<double>(),
                    c->d_save_vel.as<double>(), c->d_F.as<double>(), c->d_save_F.as<double>(), s);
     bool force_first = false;
+    bool restart = false;
     for (int attempt = 0;; ++attempt) {
       // With the per-cell row kernel the integrator bins the atoms for the
       // next build as it moves them (two halves of counts by step parity:
@@ -1633,6 +1634,19 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
       HIP_TRY(c, hipGetLastError());
       int hf[10];
       TRY(read_flags(c, s, hf, 10));
+      if (speculative) {
+        speculative = false;
+        if (hf[9] != 0) {
+          HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 16 * sizeof(int), s));
+          launch_gather_in(N, c->d_perm.as<int>(), vel, c->d_vel.as<double>(), flags, s);
+          TRY(fresh_start());
+          restart = true;
+          break;
+        }
+      }
+      // non-finite inputs (or a run that blew up) end the call whatever else
+      // the chunk flagged: a capacity retry would clear the status word
+      if (hf[0] & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
       if (!(hf[0] & kFlagOverflow)) {
         TRY(flag_status(c, hf[0]));
         dev_builds = hf[8];
@@ -1648,8 +1662,14 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
       bins_clean = false;
       force_first = true;
     }
+    if (restart) {
+      t = 0;
+      bins_clean = false;
+      continue;
+    }
     t += len;
-  } while (t < n_steps);
+    if (t >= n_steps) break;
+  }
   c->stats.n_rebuilds += dev_builds;
   c->counters_clean = true;
   c->md_state = true;

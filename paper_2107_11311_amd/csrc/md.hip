@@ -41,22 +41,8 @@ __global__ void k_scatter_out(int n, const int* perm, const double* src3, double
   if (dst1) dst1[o] = src1[p];
 }
 
-__global__ void k_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
-                                   const BoxInfo* boxes, int px, int py, int pz, double* dst) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const BoxInfo b = boxes[seg[p]];
-  const int pb[3] = {px, py, pz};
-  const size_t o = (size_t)perm[p];
-  for (int a = 0; a < 3; ++a) {
-    double x = pos[3 * (size_t)p + a];
-    if (pb[a]) x = wrap_coord(x, b.L[a]);
-    dst[3 * o + a] = x;
-  }
-}
-
 // raises *differ if any caller-order position in src is not bitwise what
-// k_wrap_scatter_out writes for the internal positions pos
+// k_md_outputs writes for the internal positions pos
 __global__ void k_same_wrapped(int n, const int* perm, const double* pos, const int* seg,
                                const BoxInfo* boxes, int px, int py, int pz, const double* src,
                                int* differ) {
@@ -304,12 +290,81 @@ __global__ __launch_bounds__(1024) void k_final_sum(int m, const double* part, d
   if (threadIdx.x == 0) *out = s[0];
 }
 
-__global__ void k_kinetic(int n, const double* vel, const double* mass, const int* species,
-                          double* tmp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double vx = vel[3 * (size_t)i], vy = vel[3 * (size_t)i + 1], vz = vel[3 * (size_t)i + 2];
-  tmp[i] = 0.5 * mass[species[i]] * (vx * vx + vy * vy + vz * vz) / kKappa;
+// The outputs of an MD call in two launches: per chunk of kRedChunk atoms
+// the partial sums of E_i (row 0) and of the kinetic energies (row 1), with
+// the same chunks and tree as k_partial_sum, while the same threads write
+// the atoms' wrapped positions, velocities and (if F_out) forces to the
+// caller's order; then k_final_sum2 adds each row's partials.  Nothing is
+// written to the caller when the call's status words hold an error or a
+// retry (flags[0]) or the state the call continued from was stale
+// (flags[9]): the call is then redone or fails with its outputs untouched.
+__device__ inline bool md_outputs_blocked(const int* flags) { return (flags[0] | flags[9]) != 0; }
+
+__global__ __launch_bounds__(256) void k_md_outputs(int n, const int* perm, const double* E, const double* pos,
+                                                    const double* vel, const double* F, const double* mass,
+                                                    const int* species, const int* seg, const BoxInfo* boxes,
+                                                    int px, int py, int pz, const int* flags, double* part,
+                                                    double* pos_out, double* vel_out, double* F_out) {
+  if (md_outputs_blocked(flags)) return;
+  __shared__ double s_e[256], s_k[256];
+  const int64_t base = (int64_t)blockIdx.x * kRedChunk;
+  const int pb[3] = {px, py, pz};
+  double ae = 0.0, ak = 0.0;
+  for (int k = threadIdx.x; k < kRedChunk; k += 256) {
+    const int64_t p = base + k;
+    if (p < n) {
+      ae += E[p];
+      const double vx = vel[3 * p], vy = vel[3 * p + 1], vz = vel[3 * p + 2];
+      ak += 0.5 * mass[species[p]] * (vx * vx + vy * vy + vz * vz) / kKappa;
+      const size_t o = (size_t)perm[p];
+      const BoxInfo b = boxes[seg[p]];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * p + a];
+        if (pb[a]) x = wrap_coord(x, b.L[a]);
+        pos_out[3 * o + a] = x;
+      }
+      vel_out[3 * o] = vx;
+      vel_out[3 * o + 1] = vy;
+      vel_out[3 * o + 2] = vz;
+      if (F_out) {
+        F_out[3 * o] = F[3 * p];
+        F_out[3 * o + 1] = F[3 * p + 1];
+        F_out[3 * o + 2] = F[3 * p + 2];
+      }
+    }
+  }
+  s_e[threadIdx.x] = ae;
+  s_k[threadIdx.x] = ak;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s_e[threadIdx.x] += s_e[threadIdx.x + o];
+      s_k[threadIdx.x] += s_k[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_e[0];
+    part[gridDim.x + blockIdx.x] = s_k[0];
+  }
+}
+
+// rows 0 and 1 of part ([2][m]) into *out0 and *out1 (k_final_sum's tree)
+__global__ __launch_bounds__(1024) void k_final_sum2(int m, const double* part, const int* flags, double* out0,
+                                                     double* out1) {
+  if (md_outputs_blocked(flags)) return;
+  __shared__ double s[1024];
+  part += (size_t)blockIdx.x * m;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < m; k += 1024) acc += part[k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *(blockIdx.x == 0 ? out0 : out1) = s[0];
 }
 
 __global__ __launch_bounds__(256) void k_segment_sum(const int64_t* off, const double* x, double* out) {
@@ -394,13 +449,6 @@ void launch_scatter_out(int n, const int* perm, const double* src3, double* dst3
     hipLaunchKernelGGL(k_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, src3, dst3, src1, dst1);
 }
 
-void launch_wrap_scatter_out(int n, const int* perm, const double* pos, const int* seg,
-                             const BoxInfo* boxes, const int pbc[3], double* dst, hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_wrap_scatter_out, dim3(nblk(n, 256)), dim3(256), 0, s, n, perm, pos, seg,
-                       boxes, pbc[0], pbc[1], pbc[2], dst);
-}
-
 void launch_same_wrapped(int n, const int* perm, const double* pos, const int* seg,
                          const BoxInfo* boxes, const int pbc[3], const double* src, int* differ,
                          hipStream_t s) {
@@ -460,9 +508,15 @@ void launch_rms_diff(int64_t n, const double* x, const double* y, double* partia
   hipLaunchKernelGGL(k_rms_finish, dim3(1), dim3(64), 0, s, n, out);
 }
 
-void launch_kinetic(int n, const double* vel, const double* mass, const int* species, double* tmp,
-                    hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_kinetic, dim3(nblk(n, 256)), dim3(256), 0, s, n, vel, mass, species, tmp);
+void launch_md_outputs(int n, const int* perm, const double* E, const double* pos, const double* vel,
+                       const double* F, const double* mass, const int* species, const int* seg,
+                       const BoxInfo* boxes, const int pbc[3], const int* flags, double* partials, double* e_pot,
+                       double* e_kin, double* pos_out, double* vel_out, double* F_out, hipStream_t s) {
+  const int m = reduce_blocks(n);
+  if (m > 0)
+    hipLaunchKernelGGL(k_md_outputs, dim3(m), dim3(256), 0, s, n, perm, E, pos, vel, F, mass, species, seg, boxes,
+                       pbc[0], pbc[1], pbc[2], flags, partials, pos_out, vel_out, F_out);
+  hipLaunchKernelGGL(k_final_sum2, dim3(2), dim3(1024), 0, s, m, partials, flags, e_pot, e_kin);
 }
 
 void launch_segment_sum(int n_seg, const int64_t* seg_off, const double* x, double* out,

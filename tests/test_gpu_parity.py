@@ -460,6 +460,55 @@ def test_md_continuation_detects_changed_state(A):
     r5, u5, e5, _, F5 = ctx.md_step(r4, u4, s.species, s.box, s.pbc, dt, 0)
     assert np.array_equal(r5, r4) and np.array_equal(u5, u4) and e5 == e4
     np.testing.assert_array_equal(F5, F4)
+    # a changed state found after the first of several chunks (the call goes
+    # on as if it continued and is redone from the caller's inputs)
+    ctx.set_rebuild_every(3)
+    p6 = r5.copy()
+    p6[7] += np.array([0.02, 0.01, -0.04])
+    r6, u6, e6, _, F6 = ctx.md_step(p6, u5, s.species, s.box, s.pbc, dt, 8)
+    q6, w6, f6, _, G6 = fresh(m2, p6, u5, 8)
+    assert np.abs(r6 - q6).max() <= 1e-10 and abs(e6 - f6) <= 1e-10 * abs(f6)
+    np.testing.assert_allclose(F6, G6, rtol=0, atol=1e-10 * np.abs(G6).max())
+    # ... and with zero steps: the forces of the caller's positions
+    p7 = r6.copy()
+    p7[3] -= np.array([0.01, 0.02, 0.0])
+    r7, u7, e7, _, F7 = ctx.md_step(p7, u6, s.species, s.box, s.pbc, dt, 0)
+    q7, w7, f7, _, G7 = fresh(m2, p7, u6, 0)
+    assert np.abs(r7 - q7).max() <= 1e-12 and abs(e7 - f7) <= 1e-10 * abs(f7)
+    np.testing.assert_allclose(F7, G7, rtol=0, atol=1e-10 * np.abs(G7).max())
+    ctx.close()
+
+
+def test_md_continuation_error_leaves_outputs(A):
+    """A device call that would continue from the kept state but gets a
+    non-finite velocity fails with AENET_E_NONFINITE and writes nothing to
+    the caller's buffers; the next call starts over."""
+    import torch
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    dev = torch.device("cuda:0")
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 6)
+    ctx = A.Context(m, "fp64", skin=0.3)
+    pos = torch.from_numpy(s.pos.copy()).to(dev)
+    vel = torch.from_numpy(v.copy()).to(dev)
+    n = len(s.pos)
+    ep = torch.zeros(1, dtype=torch.float64, device=dev)
+    ek = torch.zeros(1, dtype=torch.float64, device=dev)
+    F = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+    ctx.md_step_dev(pos, vel, s.species, s.box, s.pbc, 5e-4, 4, ep, ek, F)
+    torch.cuda.synchronize()
+    vel[11, 1] = float("nan")
+    before = (pos.clone(), vel.clone(), ep.clone(), ek.clone(), F.clone())
+    with pytest.raises(A.AenetError) as e:
+        ctx.md_step_dev(pos, vel, s.species, s.box, s.pbc, 5e-4, 3, ep, ek, F)
+    assert e.value.code == A.AENET_E_NONFINITE
+    torch.cuda.synchronize()
+    for a, b in zip((pos, vel, ep, ek, F), before):
+        assert torch.equal(a, b) or (torch.isnan(a).any() and torch.equal(torch.nan_to_num(a), torch.nan_to_num(b)))
+    vel[11, 1] = 0.0
+    ctx.md_step_dev(pos, vel, s.species, s.box, s.pbc, 5e-4, 3, ep, ek, F)
+    torch.cuda.synchronize()
+    assert torch.isfinite(pos).all() and torch.isfinite(F).all()
     ctx.close()
 
 
