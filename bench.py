@@ -32,10 +32,12 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK = 78.6e12     # MI355X vector FP64, FLOP/s
 FP32_VALU_PEAK = 157.3e12    # MI355X vector FP32 (packed), FLOP/s
 WORKLOAD = "water4096"
-KERNEL_SOURCES = {"desc_fwd": ["desc.hip", "desc_dev.h"], "desc_bwd": ["desc.hip", "desc_dev.h"],
-                  "network": ["mlp.hip", "mlp_dev.h"],
-                  "fwd_network": ["fused.hip", "desc_dev.h", "mlp_dev.h"],
-                  "neighbor": ["nbr.hip"], "force_gather": ["md.hip"], "integrate": ["md.hip"]}
+KERNEL_SOURCES = {"desc_fwd": ["desc.hip", "desc_dev.h", "aenet_internal.h"],
+                  "desc_bwd": ["desc.hip", "desc_dev.h", "aenet_internal.h"],
+                  "network": ["mlp.hip", "mlp_dev.h", "aenet_internal.h"],
+                  "fwd_network": ["fused.hip", "desc_dev.h", "mlp_dev.h", "aenet_internal.h"],
+                  "neighbor": ["nbr.hip", "aenet_internal.h"], "force_gather": ["md.hip", "aenet_internal.h"],
+                  "integrate": ["md.hip", "aenet_internal.h"]}
 
 
 def algorithmic_flops(kernel, nr_order, na_order, n_r, n_a, widths, factorised=False):

@@ -290,25 +290,42 @@ __global__ __launch_bounds__(1024) void k_final_sum(int m, const double* part, d
   if (threadIdx.x == 0) *out = s[0];
 }
 
-// The outputs of an MD call in two launches: per chunk of kRedChunk atoms
-// the partial sums of E_i (row 0) and of the kinetic energies (row 1), with
-// the same chunks and tree as k_partial_sum, while the same threads write
-// the atoms' wrapped positions, velocities and (if F_out) forces to the
-// caller's order; then k_final_sum2 adds each row's partials.  Nothing is
+// The outputs of an MD call in two launches: every thread writes one atom's
+// wrapped position, velocity and (if F_out) force to the caller's order, and
+// the first m blocks form, per chunk of kRedChunk atoms, the partial sums of
+// E_i (row 0) and of the kinetic energies (row 1) with the same chunks and
+// tree as k_partial_sum; then k_final_sum2 adds each row's partials.  Nothing is
 // written to the caller when the call's status words hold an error or a
 // retry (flags[0]) or the state the call continued from was stale
 // (flags[9]): the call is then redone or fails with its outputs untouched.
 __device__ inline bool md_outputs_blocked(const int* flags) { return (flags[0] | flags[9]) != 0; }
 
-__global__ __launch_bounds__(256) void k_md_outputs(int n, const int* perm, const double* E, const double* pos,
-                                                    const double* vel, const double* F, const double* mass,
-                                                    const int* species, const int* seg, const BoxInfo* boxes,
-                                                    int px, int py, int pz, const int* flags, double* part,
-                                                    double* pos_out, double* vel_out, double* F_out) {
+__global__ __launch_bounds__(256) void k_md_outputs(int n, int m, const int* perm, const double* E,
+                                                    const double* pos, const double* vel, const double* F,
+                                                    const double* mass, const int* species, const int* seg,
+                                                    const BoxInfo* boxes, int px, int py, int pz, const int* flags,
+                                                    double* part, double* pos_out, double* vel_out,
+                                                    double* F_out) {
   if (md_outputs_blocked(flags)) return;
+  // the caller-order outputs: one atom per thread over the whole grid
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) {
+    const int pb[3] = {px, py, pz};
+    const size_t o = (size_t)perm[q];
+    const BoxInfo b = boxes[seg[q]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double x = pos[3 * q + a];
+      if (pb[a]) x = wrap_coord(x, b.L[a]);
+      pos_out[3 * o + a] = x;
+      vel_out[3 * o + a] = vel[3 * q + a];
+      if (F_out) F_out[3 * o + a] = F[3 * q + a];
+    }
+  }
+  // the partial sums: block b < m takes chunk b
+  if ((int)blockIdx.x >= m) return;
   __shared__ double s_e[256], s_k[256];
   const int64_t base = (int64_t)blockIdx.x * kRedChunk;
-  const int pb[3] = {px, py, pz};
   double ae = 0.0, ak = 0.0;
   for (int k = threadIdx.x; k < kRedChunk; k += 256) {
     const int64_t p = base + k;
@@ -316,22 +333,6 @@ __global__ __launch_bounds__(256) void k_md_outputs(int n, const int* perm, cons
       ae += E[p];
       const double vx = vel[3 * p], vy = vel[3 * p + 1], vz = vel[3 * p + 2];
       ak += 0.5 * mass[species[p]] * (vx * vx + vy * vy + vz * vz) / kKappa;
-      const size_t o = (size_t)perm[p];
-      const BoxInfo b = boxes[seg[p]];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double x = pos[3 * p + a];
-        if (pb[a]) x = wrap_coord(x, b.L[a]);
-        pos_out[3 * o + a] = x;
-      }
-      vel_out[3 * o] = vx;
-      vel_out[3 * o + 1] = vy;
-      vel_out[3 * o + 2] = vz;
-      if (F_out) {
-        F_out[3 * o] = F[3 * p];
-        F_out[3 * o + 1] = F[3 * p + 1];
-        F_out[3 * o + 2] = F[3 * p + 2];
-      }
     }
   }
   s_e[threadIdx.x] = ae;
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(256) void k_md_outputs(int n, const int* perm, cons
   }
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s_e[0];
-    part[gridDim.x + blockIdx.x] = s_k[0];
+    part[m + blockIdx.x] = s_k[0];
   }
 }
 
@@ -513,9 +514,10 @@ void launch_md_outputs(int n, const int* perm, const double* E, const double* po
                        const BoxInfo* boxes, const int pbc[3], const int* flags, double* partials, double* e_pot,
                        double* e_kin, double* pos_out, double* vel_out, double* F_out, hipStream_t s) {
   const int m = reduce_blocks(n);
+  const int grid = std::max(m, nblk(n, 256));
   if (m > 0)
-    hipLaunchKernelGGL(k_md_outputs, dim3(m), dim3(256), 0, s, n, perm, E, pos, vel, F, mass, species, seg, boxes,
-                       pbc[0], pbc[1], pbc[2], flags, partials, pos_out, vel_out, F_out);
+    hipLaunchKernelGGL(k_md_outputs, dim3(grid), dim3(256), 0, s, n, m, perm, E, pos, vel, F, mass, species, seg,
+                       boxes, pbc[0], pbc[1], pbc[2], flags, partials, pos_out, vel_out, F_out);
   hipLaunchKernelGGL(k_final_sum2, dim3(2), dim3(1024), 0, s, m, partials, flags, e_pot, e_kin);
 }
 
