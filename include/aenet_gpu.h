@@ -230,9 +230,16 @@ aenet_status aenet_descriptors(aenet_ctx* ctx, int64_t n, const double* pos,
  * context since that could change them (energy/force, descriptor or training
  * calls, new parameters or capacities): then the forces and neighbour list of
  * that call's end are taken over (the velocities are always read, so a
- * thermostat may rescale them between calls).  e_pot/e_kin (may be NULL)
- * receive the final potential and kinetic energy (eV); forces (may be NULL)
- * the final forces.  State lives on the device for the whole call. */
+ * thermostat may rescale them between calls).  That comparison runs on the
+ * device while the call goes on as if it held; if the positions differ, the
+ * steps done meanwhile are discarded (nothing of them reaches the outputs)
+ * and the call starts over from its inputs, so a caller that changes the
+ * positions between calls gets the same result at the cost of up to
+ * rebuild_every discarded steps.  e_pot/e_kin (may be NULL) receive the final
+ * potential and kinetic energy (eV); forces (may be NULL) the final forces.
+ * On an error (non-finite input or result, overlapping atoms) pos, vel,
+ * e_pot, e_kin and forces are left as they were.  State lives on the device
+ * for the whole call. */
 aenet_status aenet_md_step(aenet_ctx* ctx, int64_t n, double* pos, double* vel,
                            const int32_t* species, const double box[3], const uint8_t pbc[3],
                            double dt_ps, int n_steps, double* e_pot, double* e_kin,
