@@ -237,7 +237,7 @@ aenet_status aenet_descriptors(aenet_ctx* ctx, int64_t n, const double* pos,
  * positions between calls gets the same result at the cost of up to
  * rebuild_every discarded steps.  e_pot/e_kin (may be NULL) receive the final
  * potential and kinetic energy (eV); forces (may be NULL) the final forces.
- * On an error (non-finite input or result, overlapping atoms) pos, vel,
+ * On an error (a non-finite input, overlapping atoms, ...) pos, vel,
  * e_pot, e_kin and forces are left as they were.  State lives on the device
  * for the whole call. */
 aenet_status aenet_md_step(aenet_ctx* ctx, int64_t n, double* pos, double* vel,
