@@ -231,11 +231,13 @@ aenet_status aenet_descriptors(aenet_ctx* ctx, int64_t n, const double* pos,
  * calls, new parameters or capacities): then the forces and neighbour list of
  * that call's end are taken over (the velocities are always read, so a
  * thermostat may rescale them between calls).  That comparison runs on the
- * device while the call goes on as if it held; if the positions differ, the
- * steps done meanwhile are discarded (nothing of them reaches the outputs)
- * and the call starts over from its inputs, so a caller that changes the
- * positions between calls gets the same result at the cost of up to
- * rebuild_every discarded steps.  e_pot/e_kin (may be NULL) receive the final
+ * device.  When aenet_md_step_dev is handed the very buffer its previous call
+ * wrote, the call goes on as if the comparison held; if the positions
+ * differ, the steps done meanwhile are discarded (nothing of them reaches
+ * the outputs) and the call starts over from its inputs, so a caller that
+ * edits that buffer between calls gets the same result at the cost of up to
+ * rebuild_every discarded steps.  Otherwise the comparison is read before
+ * the first step.  e_pot/e_kin (may be NULL) receive the final
  * potential and kinetic energy (eV); forces (may be NULL) the final forces.
  * On an error (a non-finite input, overlapping atoms, ...) pos, vel,
  * e_pot, e_kin and forces are left as they were.  State lives on the device

@@ -119,6 +119,7 @@ struct aenet_ctx {
   // positions, forces at them, the neighbour rows and their reference
   // positions; anything else that uses the buffers clears it
   bool md_state = false;
+  const double* md_pos_out = nullptr;  // the position buffer the last md_step call wrote
   // non-NULL during a no-allocation call: ensure() carves buffers from this
   // region instead of allocating
   Arena* arena = nullptr;
@@ -1503,7 +1504,7 @@ aenet_status aenet_descriptors(aenet_ctx* c, int64_t n, const double* pos, const
 
 static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, const int32_t* species,
                             const double box[3], const uint8_t pbc[3], double dt, int n_steps,
-                            double* e_pot, double* e_kin, double* forces, hipStream_t s) {
+                            double* e_pot, double* e_kin, double* forces, hipStream_t s, bool may_speculate) {
   if (!c->have_mass) return fail(c, AENET_E_INVALID, "molecular dynamics needs mass_amu in the model");
   if (!(dt > 0) || n_steps < 0) return fail(c, AENET_E_INVALID, "dt must be > 0 and n_steps >= 0");
   const int64_t off[2] = {0, n};
@@ -1538,17 +1539,29 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   // Positions the caller hands back unchanged (bitwise what the last call
   // wrote) continue from the kept device state: its forces, rows and list
   // reference stay valid, so neither a build nor a force evaluation is
-  // needed before the first step.  The comparison runs on the device and the
-  // call goes on as if it held (no wait here); its result is read with the
-  // first chunk's status words, and if the state was stale (flags[9]) that
-  // chunk, which wrote nothing to the caller, is discarded and the call
-  // starts over from the caller's positions and velocities.
-  bool speculative = resume;
-  if (resume)
+  // needed before the first step.  The comparison runs on the device.  When
+  // the caller passes the very buffer the last call wrote (a device caller
+  // stepping on in chunks) the call goes on as if it held, without waiting:
+  // the result is read with the first chunk's status words, and if the state
+  // was stale (flags[9]) that chunk, which wrote nothing to the caller, is
+  // discarded and the call starts over from the caller's positions and
+  // velocities.  Otherwise the result is read before the first step.
+  bool speculative = resume && may_speculate && pos == c->md_pos_out;
+  if (resume) {
     launch_same_wrapped(N, c->d_perm.as<int>(), c->d_pos.as<double>(), c->d_seg.as<int>(),
                         c->d_boxes.as<BoxInfo>(), c->pbc, pos, flags + 9, s);
-  else
+    if (!speculative) {
+      int hf[10];
+      TRY(read_flags(c, s, hf, 10));
+      if (hf[0] & kFlagNonFinite) return fail(c, AENET_E_NONFINITE, "non-finite position or velocity");
+      if (hf[9] != 0) {
+        HIP_TRY(c, hipMemsetAsync(c->d_flags.p, 0, 16 * sizeof(int), s));
+        TRY(fresh_start());
+      }
+    }
+  } else {
     TRY(fresh_start());
+  }
   const double half_dt = 0.5 * dt;
   const double hs2 = 0.25 * c->skin * c->skin;
   const int K = std::max(1, c->rebuild_every);
@@ -1673,6 +1686,7 @@ static aenet_status md_core(aenet_ctx* c, int64_t n, double* pos, double* vel, c
   c->stats.n_rebuilds += dev_builds;
   c->counters_clean = true;
   c->md_state = true;
+  c->md_pos_out = pos;
   return AENET_OK;
 }
 
@@ -1683,7 +1697,7 @@ aenet_status aenet_md_step_dev(aenet_ctx* c, int64_t n, double* pos, double* vel
   TRY(check_ctx(c));
   if (n < 0 || !box || (n > 0 && (!pos || !vel))) return fail(c, AENET_E_INVALID, "bad arguments");
   return md_core(c, n, pos, vel, species, box, pbc, dt_ps, n_steps, e_pot, e_kin, forces,
-                 pick_stream(c, stream));
+                 pick_stream(c, stream), true);
 }
 
 aenet_status aenet_md_step(aenet_ctx* c, int64_t n, double* pos, double* vel,
@@ -1707,7 +1721,7 @@ aenet_status aenet_md_step(aenet_ctx* c, int64_t n, double* pos, double* vel,
   }
   double* dE = c->h_E.as<double>();
   TRY(md_core(c, n, c->h_pos.as<double>(), c->h_vel.as<double>(), species, box, pbc, dt_ps, n_steps,
-              dE, dE + 1, forces ? c->h_F.as<double>() : nullptr, s));
+              dE, dE + 1, forces ? c->h_F.as<double>() : nullptr, s, false));
   double e2[2] = {0, 0};
   HIP_TRY(c, hipMemcpyAsync(e2, dE, 16, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));

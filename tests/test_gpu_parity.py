@@ -479,6 +479,44 @@ def test_md_continuation_detects_changed_state(A):
     ctx.close()
 
 
+def test_md_continuation_dev_buffer_changed_in_place(A):
+    """A device caller that edits the position buffer the last call wrote:
+    the call goes on as if the state were kept, finds it stale with the
+    first chunk's status words, discards that chunk and starts over; the
+    result is what a fresh context gives from the same inputs (several
+    chunks, and zero steps)."""
+    import torch
+    m = I.load_model("water64")
+    s = I.make_system("water64")
+    dev = torch.device("cuda:0")
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 6)
+    dt = 5e-4
+    n = len(s.pos)
+    ctx = A.Context(m, "fp64", skin=0.3)
+    ctx.set_rebuild_every(3)
+    pos = torch.from_numpy(s.pos.copy()).to(dev)
+    vel = torch.from_numpy(v.copy()).to(dev)
+    ep = torch.zeros(1, dtype=torch.float64, device=dev)
+    ek = torch.zeros(1, dtype=torch.float64, device=dev)
+    F = torch.zeros(n, 3, dtype=torch.float64, device=dev)
+    ctx.md_step_dev(pos, vel, s.species, s.box, s.pbc, dt, 4, ep, ek, F)
+    for steps in (8, 0):
+        pos[7] += torch.tensor([0.02, 0.01, -0.04], dtype=torch.float64, device=dev)
+        p_in, v_in = pos.cpu().numpy(), vel.cpu().numpy()
+        ctx.md_step_dev(pos, vel, s.species, s.box, s.pbc, dt, steps, ep, ek, F)
+        torch.cuda.synchronize()
+        ref = A.Context(m, "fp64", skin=0.3)
+        q, w, e0, k0, G = ref.md_step(p_in, v_in, s.species, s.box, s.pbc, dt, steps)
+        ref.close()
+        p1, v1, F1 = pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy()
+        dp = float(np.abs((p1 - q + s.box / 2) % s.box - s.box / 2).max())
+        print(f"{steps} steps: dpos {dp:.2e} dE {abs(ep.item() - e0) / abs(e0):.2e}")
+        assert dp <= 1e-10 and np.abs(v1 - w).max() <= 1e-8 * np.abs(w).max()
+        assert abs(ep.item() - e0) <= 1e-10 * abs(e0) and abs(ek.item() - k0) <= 1e-10 * abs(k0)
+        np.testing.assert_allclose(F1, G, rtol=0, atol=1e-10 * np.abs(G).max())
+    ctx.close()
+
+
 def test_md_continuation_error_leaves_outputs(A):
     """A device call that would continue from the kept state but gets a
     non-finite velocity fails with AENET_E_NONFINITE and writes nothing to
