@@ -18,7 +18,8 @@
 //
 // One lane per atom: the (N_a + 1)^2 sums of both channels live in its
 // registers, and the lane walks the atom's angular entries (the front part of
-// its neighbour row), one per iteration, the next one's loads issued ahead.
+// its neighbour row), one per iteration, the loads of the next two issued
+// ahead.
 //   forward:  the sums, then the 2 (N_a + 1) angular components of G; the
 //             sums are kept for the force pass;
 //   backward: dE/dA = 2 N_lm h_l A (h_l = sum_a C[a][l] dE/dG_ang,a), then per
@@ -127,12 +128,20 @@ __global__ __launch_bounds__(64) void k_ang_sh_fwd(DescParams p) {
 #pragma unroll
   for (int k = 0; k < NH; ++k) A[k] = B[k] = R(0);
   R D = R(0), Dw = R(0);
-  // an empty row reads slot 0 (whatever it holds) with weight 0
+  // The entries' two dependent loads (row word, then the neighbour's
+  // position) run two and one entries ahead of their use, so that no
+  // iteration waits on a load it issued itself; slots past the end repeat
+  // the last entry (an empty row reads slot 0, whatever it holds, with
+  // weight 0).
+  const int last = na > 0 ? na - 1 : 0;
   NbrLoad nx = load_nbr(p, row[0]);
+  uint32_t wnext = row[min(1, last)];
   for (int e = 0; e < na; ++e) {
-    const NbrLoad nn = load_nbr(p, row[e + 1 < na ? e + 1 : e]);
+    const uint32_t wafter = row[min(e + 2, last)];
+    const NbrLoad nn = load_nbr(p, wnext);
     const AngEntry<R> a = ang_entry<R>(nx, b, xi0, xi1, xi2, ra2, pi_2ra, true);
     nx = nn;
+    wnext = wafter;
     const R f = a.f, wf = a.w * a.f;
     D += f * f;
     Dw += wf * wf;
@@ -268,18 +277,26 @@ __global__ __launch_bounds__(64) void k_ang_sh_bwd(DescParams p) {
       }
   }
   R* out = reinterpret_cast<R*>(p.gang) + (size_t)i * p.cap_ang * 3;
+  // loads two and one entries ahead, as in the forward pass
+  const int last = na > 0 ? na - 1 : 0;
   NbrLoad nx = load_nbr(p, row[0]);
+  uint32_t wnext = row[min(1, last)];
   for (int e = 0; e < na; ++e) {
-    const NbrLoad nn = load_nbr(p, row[e + 1 < na ? e + 1 : e]);
+    const uint32_t wafter = row[min(e + 2, last)];
+    const NbrLoad nn = load_nbr(p, wnext);
     const AngEntry<R> a = ang_entry<R>(nx, b, xi0, xi1, xi2, ra2, pi_2ra, true);
     nx = nn;
+    wnext = wafter;
     // V = sum q Y and the gradient G = sum q grad Y of the functions as
     // polynomials in (x, y, z): d/dx (x+iy)^m = m (x+iy)^(m-1),
     // d/dy (x+iy)^m = i m (x+iy)^(m-1), dQ_lm/dz = Q_l,m+1
+    // V and the gradient are summed per column m (independent chains; one
+    // chain through all (N_a + 1)^2 terms would serialise the column loop)
     R V = R(0), gx = R(0), gy = R(0), gz = R(0);
     R wr = R(1), wi = R(0), pr = R(0), pi = R(0);  // (x+iy)^m and (x+iy)^(m-1)
 #pragma unroll
     for (int m = 0; m <= NA; ++m) {
+      R Vm = R(0), gxm = R(0), gym = R(0), gzm = R(0);
       if (m > 0) {
         pr = wr;
         pi = wi;
@@ -312,14 +329,18 @@ __global__ __launch_bounds__(64) void k_ang_sh_bwd(DescParams p) {
         const R qc = qt[ci(l, m)] + a.w * qw[ci(l, m)];
         const R qs = m > 0 ? qt[si(l, m)] + a.w * qw[si(l, m)] : R(0);
         const R cw = qc * wr + qs * wi;
-        V += q * cw;
-        gz += u * cw;
+        Vm += q * cw;
+        gzm += u * cw;
         if (m > 0) {
           const R qm = q * R(m);
-          gx += qm * (qc * pr + qs * pi);
-          gy += qm * (qs * pr - qc * pi);
+          gxm += qm * (qc * pr + qs * pi);
+          gym += qm * (qs * pr - qc * pi);
         }
       }
+      V += Vm;
+      gx += gxm;
+      gy += gym;
+      gz += gzm;
     }
     // d/dd of f(r) Y(d/r) = f' Y u + (f / r) (grad Y - (u . grad Y) u),
     // minus the diagonal terms 2 f f' (H + w^2 Hw) u
