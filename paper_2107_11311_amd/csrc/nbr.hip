@@ -246,16 +246,12 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
       const int s0 = code % 3 - 1, s1 = (code / 3) % 3 - 1, s2 = code / 9 - 1;
       const bool self = (q == i) && code == 13;
       if (!self) {
-        // displacement computed from the lower-index atom, so that the entry
-        // and its reverse agree bit for bit on r^2
-        const bool spos = s2 > 0 || (s2 == 0 && (s1 > 0 || (s1 == 0 && s0 > 0)));
-        const bool iq = (i < q) || (i == q && spos);
-        const size_t ia = iq ? (size_t)i : (size_t)q;
-        const size_t ib = iq ? (size_t)q : (size_t)i;
-        const double sg = iq ? 1.0 : -1.0;
-        const double d0 = p.pos[3 * ib] + sg * (double)s0 * b.L[0] - p.pos[3 * ia];
-        const double d1 = p.pos[3 * ib + 1] + sg * (double)s1 * b.L[1] - p.pos[3 * ia + 1];
-        const double d2 = p.pos[3 * ib + 2] + sg * (double)s2 * b.L[2] - p.pos[3 * ia + 2];
+        // d = (x_q - x_i) + s L: the reverse entry's (x_i - x_q) - s L is its
+        // exact negative (rounding is symmetric), so both agree bit for bit
+        // on r^2
+        const double d0 = (p.pos[3 * (size_t)q] - p.pos[3 * (size_t)i]) + (double)s0 * b.L[0];
+        const double d1 = (p.pos[3 * (size_t)q + 1] - p.pos[3 * (size_t)i + 1]) + (double)s1 * b.L[1];
+        const double d2 = (p.pos[3 * (size_t)q + 2] - p.pos[3 * (size_t)i + 2]) + (double)s2 * b.L[2];
         const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
         if (r2 == 0.0) atomicOr(p.flags, kFlagOverlap);
         ang = r2 < p.r_ang2;
@@ -512,14 +508,11 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
       const int q = (int)(key & kAtomMask);
       const double qx = s_pos[tt], qy = s_pos[tp + tt], qz = s_pos[2 * tp + tt];
       const double sx = s_shift[k_cell][0], sy = s_shift[k_cell][1], sz = s_shift[k_cell][2];
-      // displacement from the lower-index atom (image shifts counted from
-      // it), so that an entry and its reverse agree bit for bit on r^2
-      // (bitwise operators: no short-circuit branches)
-      const bool pshift = (sz > 0.0) | ((sz == 0.0) & ((sy > 0.0) | ((sy == 0.0) & (sx > 0.0))));
-      const bool iq = (i < q) | ((i == q) & pshift);
-      const double d0 = iq ? (qx + sx) - xi0 : (xi0 - sx) - qx;
-      const double d1 = iq ? (qy + sy) - xi1 : (xi1 - sy) - qy;
-      const double d2 = iq ? (qz + sz) - xi2 : (xi2 - sz) - qz;
+      // d = (x_q - x_i) + s: the reverse entry's (x_i - x_q) - s is its exact
+      // negative (rounding is symmetric), so both agree bit for bit on r^2
+      const double d0 = (qx - xi0) + sx;
+      const double d1 = (qy - xi1) + sy;
+      const double d2 = (qz - xi2) + sz;
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
       const bool self = q == i && k_cell == 13;
       const bool ok = in && !self;
