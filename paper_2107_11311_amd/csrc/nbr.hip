@@ -234,45 +234,68 @@ __global__ __launch_bounds__(256) void k_rows(NbrParams p) {
   uint32_t* row = p.nbr + (size_t)(active ? i : 0) * p.cap;
   uint32_t* rad_e = s_rad + (size_t)wv * p.cap;
   int cnt_a = 0, cnt_r = 0;
-  int k_cell = 0;  // stencil cell of this lane's candidate (candidates advance monotonically)
-  for (int base = 0; base < total; base += 64) {
-    const int t = base + lane;
-    bool ang = false, rad = false;
-    uint32_t entry = 0;
-    if (t < total) {
-      while (k_cell < 26 && t >= s_pref[wv][k_cell + 1]) ++k_cell;
-      const int q = p.cell_atoms[s_start[wv][k_cell] + (t - s_pref[wv][k_cell])];
+  if (total > 0) {  // (an inactive wave has no candidates)
+    const double xi0 = p.pos[3 * (size_t)i], xi1 = p.pos[3 * (size_t)i + 1], xi2 = p.pos[3 * (size_t)i + 2];
+    // Candidate t of the stream (clamped to it): its atom and stencil cell.
+    // Each lane's candidates of the next two chunks are in flight while one
+    // is tested (the atom index two chunks ahead, its position one chunk
+    // ahead); stencil cells advance monotonically with t.
+    int kf = 0;
+    auto cand = [&](int t, int& kc) {
+      const int tt = min(t, total - 1);
+      while (kf < 26 && tt >= s_pref[wv][kf + 1]) ++kf;
+      kc = kf;
+      return p.cell_atoms[s_start[wv][kf] + (tt - s_pref[wv][kf])];
+    };
+    int k0, k1;
+    int q0 = cand(lane, k0);
+    int q1 = cand(lane + 64, k1);
+    double x0[3] = {p.pos[3 * (size_t)q0], p.pos[3 * (size_t)q0 + 1], p.pos[3 * (size_t)q0 + 2]};
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + lane;
+      int k2;
+      const int q2 = cand(t + 128, k2);
+      const double x1[3] = {p.pos[3 * (size_t)q1], p.pos[3 * (size_t)q1 + 1], p.pos[3 * (size_t)q1 + 2]};
+      const int q = q0, k_cell = k0;
+      bool ang = false, rad = false;
+      uint32_t entry = 0;
       const int code = s_code[wv][k_cell];
       const int s0 = code % 3 - 1, s1 = (code / 3) % 3 - 1, s2 = code / 9 - 1;
       const bool self = (q == i) && code == 13;
-      if (!self) {
+      if (t < total && !self) {
         // d = (x_q - x_i) + s L: the reverse entry's (x_i - x_q) - s L is its
         // exact negative (rounding is symmetric), so both agree bit for bit
         // on r^2
-        const double d0 = (p.pos[3 * (size_t)q] - p.pos[3 * (size_t)i]) + (double)s0 * b.L[0];
-        const double d1 = (p.pos[3 * (size_t)q + 1] - p.pos[3 * (size_t)i + 1]) + (double)s1 * b.L[1];
-        const double d2 = (p.pos[3 * (size_t)q + 2] - p.pos[3 * (size_t)i + 2]) + (double)s2 * b.L[2];
+        const double d0 = (x0[0] - xi0) + (double)s0 * b.L[0];
+        const double d1 = (x0[1] - xi1) + (double)s1 * b.L[1];
+        const double d2 = (x0[2] - xi2) + (double)s2 * b.L[2];
         const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
         if (r2 == 0.0) atomicOr(p.flags, kFlagOverlap);
         ang = r2 < p.r_ang2;
         rad = !ang && r2 < p.r_list2;
         entry = (uint32_t)q | ((uint32_t)code << kImgBits);
       }
+      const uint64_t below = (1ull << lane) - 1ull;
+      const uint64_t ma = __ballot(ang), mr = __ballot(rad);
+      if (ang) {
+        const int at = cnt_a + __popcll(ma & below);
+        if (at < p.cap) row[at] = entry;
+        atomicAdd(&s_na[wv][k_cell], 1);
+      }
+      if (rad) {
+        const int at = cnt_r + __popcll(mr & below);
+        if (at < p.cap) rad_e[at] = entry;
+        atomicAdd(&s_nr[wv][k_cell], 1);
+      }
+      cnt_a += __popcll(ma);
+      cnt_r += __popcll(mr);
+      q0 = q1;
+      k0 = k1;
+      q1 = q2;
+      k1 = k2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x0[c] = x1[c];
     }
-    const uint64_t below = (1ull << lane) - 1ull;
-    const uint64_t ma = __ballot(ang), mr = __ballot(rad);
-    if (ang) {
-      const int at = cnt_a + __popcll(ma & below);
-      if (at < p.cap) row[at] = entry;
-      atomicAdd(&s_na[wv][k_cell], 1);
-    }
-    if (rad) {
-      const int at = cnt_r + __popcll(mr & below);
-      if (at < p.cap) rad_e[at] = entry;
-      atomicAdd(&s_nr[wv][k_cell], 1);
-    }
-    cnt_a += __popcll(ma);
-    cnt_r += __popcll(mr);
   }
   __syncthreads();
   // append the radial-only entries after the angular ones
