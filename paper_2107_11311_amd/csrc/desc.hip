@@ -35,11 +35,13 @@ __global__ __launch_bounds__(256, 3) void k_desc_fwd(DescParams p) {
 }
 
 // ------------------------------------------------------------------ backward
-// LDS of the force pass (elements of R): ten arrays of cap_ang entries, the
-// compaction index (cap_ang ints), then the per-species series coefficients
+// LDS of the force pass (elements of R): twelve arrays of cap_ang entries,
+// the compaction index (cap_ang ints), then the per-species series
+// coefficients
+constexpr int kBwdArrays = 12;
 template <typename R>
 __host__ __device__ constexpr size_t bwd_coef_offset(int ca) {
-  return (size_t)ca * 10 + ((size_t)ca * sizeof(int) + sizeof(R) - 1) / sizeof(R);
+  return (size_t)ca * kBwdArrays + ((size_t)ca * sizeof(int) + sizeof(R) - 1) / sizeof(R);
 }
 
 // dE_i / d d_e for every entry e of atom i, stored at the slot of the reverse
@@ -75,7 +77,9 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
   R* gx = ri + ca;
   R* gy = gx + ca;
   R* gz = gy + ca;
-  int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)ca * 10);
+  R* s1a = gz + ca;  // crowded shells: the sums s1, s2 of each entry (below)
+  R* s2a = s1a + ca;
+  int* kidx = reinterpret_cast<int*>(reinterpret_cast<R*>(smem) + (size_t)ca * kBwdArrays);
   // radial series coefficients of each species s (NR + 1 per species); with
   // AEXT the angular arrays are not needed and the table starts the LDS
   R* s_c = reinterpret_cast<R*>(smem) + (AEXT ? 0 : bwd_coef_offset<R>(ca));
@@ -208,26 +212,71 @@ __global__ __launch_bounds__(256, 5) void k_desc_bwd(DescParams p) {
         gz[e] = cb * vz + ca_ * kz;
       }
     } else {
-      // crowded shells: each lane owns entries k = l, l + 64, ... and sums
-      // over all partners j != k (every pair is evaluated from both ends)
-      for (int k = l; k < nv; k += 64) {
-        const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], fpk = fp[k], wk = ws[k], rik = ri[k];
-        R ax = 0, ay = 0, az = 0;
-        for (int j = 0; j < nv; ++j) {
-          const R mj = j != k ? R(1) : R(0);
-          const R jx = ux[j], jy = uy[j], jz = uz[j];
+      // Crowded shells: the same rotation over all nv entries, lane l taking
+      // entries l, l + 64, ... in turn.  Its own entry's sums stay in
+      // registers; the partner's are added into LDS (V into gx, gy, gz, s1
+      // and s2 into s1a, s2a), in place: at a step t every entry is the
+      // partner of exactly one entry, so the additions of one step never
+      // meet; the steps are ordered by a fence (the lanes of the wavefront
+      // exchange values through LDS).
+      auto lds_step = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      };
+      for (int k = l; k < nv; k += 64) gx[k] = gy[k] = gz[k] = s1a[k] = s2a[k] = R(0);
+      __syncthreads();
+      const int T = nv >> 1;
+      for (int base = 0; base < nv; base += 64) {
+        const int e = base + l;
+        const bool own = e < nv;
+        const int k = own ? e : 0;
+        const R kx = ux[k], ky = uy[k], kz = uz[k], fk = fs[k], wk = ws[k];
+        R vx = 0, vy = 0, vz = 0, s1 = 0, s2 = 0;
+        for (int t = 1; t <= T; ++t) {
+          int m = e + t;
+          if (m >= nv) m -= nv;
+          const bool go = own && (2 * t != nv || e < t);
+          if (!own) m = k;
+          const R wgt = go ? R(1) : R(0);
+          const R jx = ux[m], jy = uy[m], jz = uz[m], fm = fs[m];
           const R c = jx * kx + jy * ky + jz * kz;
           R A, B;
-          cheb_series_d<R, NA>(ga, gw, ws[j] * wk, c, &A, &B);
-          const R fj = fs[j] * mj;
-          const R cb = B * fj * fk * rik, cak = A * fj * fpk;
-          ax += cb * (jx - c * kx) + cak * kx;
-          ay += cb * (jy - c * ky) + cak * ky;
-          az += cb * (jz - c * kz) + cak * kz;
+          cheb_series_d<R, NA>(ga, gw, ws[m] * wk, c, &A, &B);
+          A *= wgt;
+          B *= wgt;
+          const R bj = B * fm;
+          vx += bj * jx;
+          vy += bj * jy;
+          vz += bj * jz;
+          s1 += bj * c;
+          s2 += A * fm;
+          if (go) {
+            const R bk = B * fk;
+            gx[m] += bk * kx;
+            gy[m] += bk * ky;
+            gz[m] += bk * kz;
+            s1a[m] += bk * c;
+            s2a[m] += A * fk;
+          }
+          lds_step();
         }
-        gx[k] = R(2) * ax;
-        gy[k] = R(2) * ay;
-        gz[k] = R(2) * az;
+        if (own) {
+          gx[e] += vx;
+          gy[e] += vy;
+          gz[e] += vz;
+          s1a[e] += s1;
+          s2a[e] += s2;
+        }
+        lds_step();
+      }
+      __syncthreads();
+      for (int k = l; k < nv; k += 64) {
+        const R cb = R(2) * fs[k] * ri[k], ca_ = R(2) * fp[k] * s2a[k] - cb * s1a[k];
+        const R vxk = gx[k], vyk = gy[k], vzk = gz[k];
+        gx[k] = cb * vxk + ca_ * ux[k];
+        gy[k] = cb * vyk + ca_ * uy[k];
+        gz[k] = cb * vzk + ca_ * uz[k];
       }
     }
   }
@@ -558,7 +607,7 @@ __global__ __launch_bounds__(256) void k_desc_jvp(DescParams p) {
 enum Kind { FWD = 0, BWD = 1, JVP = 2 };
 
 // LDS words (of type R) per angular entry, plus int words
-constexpr int lds_words(int kind) { return kind == FWD ? 5 : (kind == BWD ? 10 : 11); }
+constexpr int lds_words(int kind) { return kind == FWD ? 5 : (kind == BWD ? kBwdArrays : 11); }
 
 template <typename R, int NR, int NA, int LPA>
 void launch_kind(int kind, const DescParams& p, hipStream_t s, bool ang) {
