@@ -97,6 +97,48 @@ def test_mixed_periodicity(A, orc):
     check_ef(A, orc, small_model(nr=5, na=3, rr=4.5, ra=3.5), s)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degenerate_systems(A, orc, precision):
+    """The degenerate cases of the method, against the oracle: an isolated
+    atom and one atom in the smallest periodic box allowed (no neighbours:
+    G = 0, the energy is the network's value at the shifted origin and the
+    force is exactly zero); an open dimer (radial terms only, one angular
+    neighbour each and so no pairs; the two forces exact negatives); a pair
+    at exactly the radial cutoff (f_c(R) = 0: no contribution); and a
+    collinear trimer (cos theta = -1 at the centre, the end of the
+    Chebyshev domain)."""
+    m = small_model(nr=5, na=3, rr=4.5, ra=3.5)
+    rl = max(m.radial_cutoff, m.angular_cutoff) + 0.5
+    open_box = np.array([60.0, 60.0, 60.0])
+    no_pbc = np.zeros(3, dtype=np.uint8)
+    cases = {
+        "isolated": I.System(np.array([[30.0, 30.0, 30.0]]), np.array([0], np.int32), open_box, no_pbc),
+        "periodic_single": I.System(np.array([[1.0, 2.0, 3.0]]), np.array([1], np.int32),
+                                    np.array([rl, rl, rl]), np.ones(3, dtype=np.uint8)),
+        "dimer": I.System(np.array([[30.0, 30.0, 30.0], [31.2, 30.9, 30.4]]), np.array([0, 1], np.int32),
+                          open_box, no_pbc),
+        "at_cutoff": I.System(np.array([[30.0, 30.0, 30.0], [30.0 + m.radial_cutoff, 30.0, 30.0],
+                                        [30.0, 31.1, 30.0]]), np.array([0, 1, 1], np.int32), open_box, no_pbc),
+        "collinear": I.System(np.array([[28.6, 30.0, 30.0], [30.0, 30.0, 30.0], [31.3, 30.0, 30.0]]),
+                              np.array([1, 0, 1], np.int32), open_box, no_pbc),
+    }
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for name, sy in cases.items():
+        ctx = A.Context(m, precision, skin=0.5)
+        E, Ea, F = ctx.energy_forces(sy.pos, sy.species, sy.box, sy.pbc)
+        ctx.close()
+        E0, Ea0, F0 = orc.energy_forces(m, sy.pos, sy.species, sy.box, sy.pbc)
+        fs = max(float(np.abs(F0).max()), 1.0)
+        print(f"{name} {precision}: E {E:.12f} oracle {E0:.12f} max|dF| {np.abs(F - F0).max():.2e}")
+        assert abs(E - E0) <= tol * max(abs(E0), 1.0), name
+        assert np.abs(Ea - Ea0).max() <= tol * max(float(np.abs(Ea0).max()), 1.0), name
+        assert np.abs(F - F0).max() <= tol * fs, name
+        if name in ("isolated", "periodic_single"):
+            assert np.all(F == 0.0), name
+        if name == "dimer":
+            assert np.array_equal(F[0], -F[1]), name
+
+
 def test_skin_does_not_change_results(A, orc):
     s = I.make_system("water64")
     m = I.load_model("water64")
