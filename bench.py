@@ -614,8 +614,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how the path would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (it would shard by "
+              "spatial domains with halo exchange, which is not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.student:
         run_student(args)
