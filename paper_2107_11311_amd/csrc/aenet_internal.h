@@ -96,11 +96,13 @@ struct NbrParams {
 };
 constexpr int kSegWords = 56;  // 2 row parts x 28 segment boundaries
 constexpr int kRevPending = -2;  // rev values <= this are unresolved (rank, k)
-constexpr int kCellAtomsMax = 64;  // atoms per cell the per-cell row kernel handles
-constexpr int kRowWaves = 16;      // wavefronts per block of the per-cell row kernel
-// LDS bytes of the per-cell row kernel for a candidate capacity tp
+constexpr int kCellAtomsMax = 128;  // atoms per cell the per-cell row kernel handles
+constexpr int kRowWaves = 16;       // wavefronts per block of the per-cell row kernel
+// LDS bytes of the per-cell row kernel for a candidate capacity tp: key,
+// FP32 position and the two row parts' masks of every candidate, and each
+// wavefront's staging row
 inline size_t cell_rows_lds(int tp, int cap) {
-  return (size_t)tp * (4 + 24 + 2 * (kCellAtomsMax / 32) * 4) + (size_t)kRowWaves * cap * 4;
+  return (size_t)tp * (4 + 12 + 2 * (kCellAtomsMax / 32) * 4) + (size_t)kRowWaves * cap * 4;
 }
 void launch_build_neighbors(const NbrParams& p, hipStream_t s);
 void launch_set_int(int* dst, int value, hipStream_t s);

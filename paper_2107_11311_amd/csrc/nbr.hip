@@ -403,12 +403,16 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
   }
   extern __shared__ __align__(16) unsigned char smem[];
   const int tp = p.tp;
-  double* s_pos = reinterpret_cast<double*>(smem);                          // [3][tp] (x, y, z planes: unit-stride lanes)
+  // candidate positions in FP32 (x, y, z planes: unit-stride lanes): they
+  // only decide list membership, where the skin leaves a margin far above
+  // their rounding, and an entry's displacement stays the exact negative of
+  // its reverse's
+  float* s_pos = reinterpret_cast<float*>(smem);                            // [3][tp]
   uint32_t* s_key = reinterpret_cast<uint32_t*>(s_pos + 3 * (size_t)tp);      // [tp] atom | stencil cell << kImgBits
   uint32_t* s_mask = s_key + tp;                                              // [tp][2][kMaskWords]
   uint32_t* s_rad = s_mask + (size_t)tp * 2 * kMaskWords;                     // [waves][cap]
   __shared__ int s_start[27], s_cnt[27], s_code[27], s_pref[28];
-  __shared__ double s_shift[27][3];                             // image shift s L of each stencil cell
+  __shared__ float s_shift[27][3];                              // image shift s L of each stencil cell
   __shared__ int s_sa[kRowWaves][28], s_sr[kRowWaves][28];      // segment starts of the row being built
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c = blockIdx.x;
@@ -432,7 +436,7 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
         w[a] = u;
         out |= (u < 0 || u >= b.nc[a]);
       }
-      s_shift[tid][a] = (double)sh[a] * b.L[a];
+      s_shift[tid][a] = (float)((double)sh[a] * b.L[a]);
     }
     const int cell = out ? 0 : b.cell_base + (w[2] * b.nc[1] + w[1]) * b.nc[0] + w[0];
     if (p.binned) {
@@ -470,38 +474,69 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
   }
   if (ncen == 0) return;
   // candidates: each stencil cell's atoms sorted by index (one wavefront per
-  // cell, a bitonic network across its lanes), so the scatter's atomic order
-  // does not reach the rows
+  // cell, a bitonic network across its lanes; element j = lane + 64 h in
+  // v[h], the second half only for cells of more than 64 atoms), so the
+  // scatter's atomic order does not reach the rows
   const int* cell_src = p.binned ? p.bin_atoms : p.cell_atoms;
   for (int k = wv; k < 27; k += kRowWaves) {
     const int cnt = s_cnt[k];
-    uint32_t v = lane < cnt ? (uint32_t)cell_src[s_start[k] + lane] : 0xffffffffu;
+    uint32_t v[2];
 #pragma unroll
-    for (int size = 2; size <= 64; size <<= 1) {
+    for (int h = 0; h < 2; ++h)
+      v[h] = lane + 64 * h < cnt ? (uint32_t)cell_src[s_start[k] + lane + 64 * h] : 0xffffffffu;
+    if (cnt <= 64) {  // (uniform over the wavefront)
 #pragma unroll
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, stride, 64);
-        const bool up = (lane & size) == 0, lower = (lane & stride) == 0;
-        v = (lower == up) ? min(v, o) : max(v, o);
+      for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          const uint32_t o = (uint32_t)__shfl_xor((int)v[0], stride, 64);
+          const bool up = (lane & size) == 0, lower = (lane & stride) == 0;
+          v[0] = (lower == up) ? min(v[0], o) : max(v[0], o);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          if (stride == 64) {  // elements j and j + 64 (size 128: ascending)
+            const uint32_t lo = min(v[0], v[1]), hi = max(v[0], v[1]);
+            v[0] = lo;
+            v[1] = hi;
+          } else {
+            const bool lower = (lane & stride) == 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const uint32_t o = (uint32_t)__shfl_xor((int)v[h], stride, 64);
+              const bool up = size == 128 || (((lane + 64 * h) & size) == 0);
+              v[h] = (lower == up) ? min(v[h], o) : max(v[h], o);
+            }
+          }
+        }
       }
     }
-    if (lane < cnt) {
-      const int t = s_pref[k] + lane;
-      s_key[t] = v | ((uint32_t)k << kImgBits);
-      double x[3];
-      for (int a = 0; a < 3; ++a) {
-        x[a] = p.pos[3 * (size_t)v + a];
-        // binned: the positions were last wrapped at the previous build; the
-        // block of the atom's own cell stores the wrapped position and the
-        // skin-test reference (other blocks may read either value: wrapping
-        // is idempotent)
-        if (p.binned && p.pbc[a]) x[a] = wrap_coord(x[a], b.L[a]);
-        s_pos[(size_t)a * tp + t] = x[a];
-      }
-      if (p.binned && k == 13) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = lane + 64 * h;
+      if (j < cnt) {
+        const uint32_t a_ = v[h];
+        const int t = s_pref[k] + j;
+        s_key[t] = a_ | ((uint32_t)k << kImgBits);
+        double x[3];
         for (int a = 0; a < 3; ++a) {
-          p.pos[3 * (size_t)v + a] = x[a];
-          p.pos_ref[3 * (size_t)v + a] = x[a];
+          x[a] = p.pos[3 * (size_t)a_ + a];
+          // binned: the positions were last wrapped at the previous build; the
+          // block of the atom's own cell stores the wrapped position and the
+          // skin-test reference (other blocks may read either value: wrapping
+          // is idempotent)
+          if (p.binned && p.pbc[a]) x[a] = wrap_coord(x[a], b.L[a]);
+          s_pos[(size_t)a * tp + t] = (float)x[a];
+        }
+        if (p.binned && k == 13) {
+          for (int a = 0; a < 3; ++a) {
+            p.pos[3 * (size_t)a_ + a] = x[a];
+            p.pos_ref[3 * (size_t)a_ + a] = x[a];
+          }
         }
       }
     }
@@ -513,9 +548,14 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
   // wavefront per atom; the radial-only entries are staged as (slot, stencil)
   const int c0 = s_pref[13];
   uint32_t* rad_t = s_rad + (size_t)wv * p.cap;
+  // the FP32 radii carry a relative margin of 1e-4 in r^2 (about 20 times
+  // the rounding of r^2 from FP32 coordinates below 1000 A), so no pair
+  // within the list radius in FP64 is left out; the few pairs just beyond it
+  // that enter contribute nothing
+  const float r_ang2f = (float)(p.r_ang2 * (1.0 + 1e-4)), r_list2f = (float)(p.r_list2 * (1.0 + 1e-4));
   for (int ai = wv; ai < ncen; ai += kRowWaves) {
     const int i = (int)(s_key[c0 + ai] & kAtomMask);
-    const double xi0 = s_pos[c0 + ai], xi1 = s_pos[tp + c0 + ai], xi2 = s_pos[2 * tp + c0 + ai];
+    const float xi0 = s_pos[c0 + ai], xi1 = s_pos[tp + c0 + ai], xi2 = s_pos[2 * tp + c0 + ai];
     uint32_t* row = p.nbr + (size_t)i * p.cap;
     int* slot = p.rev + (size_t)i * p.cap;  // (candidate slot, stencil cell) of each entry, then (rank, cell)
     int cnt_a = 0, cnt_r = 0;
@@ -529,19 +569,18 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
       const uint32_t key = s_key[tt];
       k_cell = (int)(key >> kImgBits);
       const int q = (int)(key & kAtomMask);
-      const double qx = s_pos[tt], qy = s_pos[tp + tt], qz = s_pos[2 * tp + tt];
-      const double sx = s_shift[k_cell][0], sy = s_shift[k_cell][1], sz = s_shift[k_cell][2];
+      const float qx = s_pos[tt], qy = s_pos[tp + tt], qz = s_pos[2 * tp + tt];
       // d = (x_q - x_i) + s: the reverse entry's (x_i - x_q) - s is its exact
       // negative (rounding is symmetric), so both agree bit for bit on r^2
-      const double d0 = (qx - xi0) + sx;
-      const double d1 = (qy - xi1) + sy;
-      const double d2 = (qz - xi2) + sz;
-      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const float d0 = (qx - xi0) + s_shift[k_cell][0];
+      const float d1 = (qy - xi1) + s_shift[k_cell][1];
+      const float d2 = (qz - xi2) + s_shift[k_cell][2];
+      const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
       const bool self = q == i && k_cell == 13;
       const bool ok = in && !self;
-      if (ok && r2 == 0.0) atomicOr(p.flags, kFlagOverlap);
-      const bool ang = ok && r2 < p.r_ang2;
-      const bool rad = ok && !ang && r2 < p.r_list2;
+      if (ok && r2 == 0.0f) atomicOr(p.flags, kFlagOverlap);
+      const bool ang = ok && r2 < r_ang2f;
+      const bool rad = ok && !ang && r2 < r_list2f;
       const uint64_t below = (1ull << lane) - 1ull;
       const uint64_t ma = __ballot(ang), mr = __ballot(rad);
       const int pa = cnt_a + __popcll(ma & below), pr = cnt_r + __popcll(mr & below);

@@ -88,17 +88,25 @@ def _dense_lisio(L, seed):
     return I.amorphous_box(n, counts, L, seed)
 
 
-def test_lisio_dense_md_per_atom_path(A, orc):
+@pytest.mark.parametrize("L,path", [(17.0, "cell"), (18.0, "cell_wide"), (19.0, "atom")])
+def test_lisio_dense_md(A, orc, L, path):
     """MD at the 120k workload's density, orders and cutoffs (18 / 8.0 A, 6 /
-    6.5 A) on a 17 A box: about 59 atoms per neighbour-list cell, so the list
-    is built by the per-atom kernels inside md_step, and about 111 angular
-    neighbours, so the force pass takes its crowded-shell path.  12 steps of
-    1 fs with a build forced every 4 steps and rows that start too short (a
-    capacity retry), against the oracle's velocity Verlet, element by element."""
+    6.5 A) in boxes of 2 x 2 x 2 list cells: about 59 atoms per cell at
+    L = 17 A (the per-cell row kernel), 70 at 18 A (the per-cell kernel with
+    its cells sorted in two halves of 64) and 83 at 19 A (more than the
+    per-cell kernel is planned for: the per-atom row kernels and the reverse
+    search), each inside md_step, with about 111 angular neighbours, so the
+    force pass takes its crowded-shell path.  12 steps of 1 fs with a build
+    forced every 4 steps and rows that start too short (a capacity retry),
+    against the oracle's velocity Verlet, element by element."""
     m = I.load_model("lisio120k")
-    s = _dense_lisio(17.0, 4242)
+    s = _dense_lisio(L, 4242)
     n = len(s.pos)
-    assert n / 8 > 42  # 2 x 2 x 2 cells of >= 8.5 A
+    per_cell = n / 8  # 2 x 2 x 2 cells of >= 8.5 A
+    # the host plans the per-cell kernel while 1.5 x the mean cell count + 8
+    # stays within its 128 atoms
+    assert {"cell": per_cell < 64, "cell_wide": 64 < per_cell and 1.5 * per_cell + 8 <= 128,
+            "atom": 1.5 * per_cell + 8 > 128}[path], per_cell
     v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 17)
     ctx = A.Context(m, "fp64", skin=0.5)
     ctx.set_rebuild_every(4)
@@ -109,7 +117,7 @@ def test_lisio_dense_md_per_atom_path(A, orc):
     dp = float(np.abs((p1 - p0 + s.box / 2) % s.box - s.box / 2).max())
     dv = float(np.abs(v1 - v0).max() / np.abs(v0).max())
     dF = float(np.abs(F - F0).max() / np.abs(F0).max())
-    print(f"lisio dense n={n}: dpos {dp:.2e} dvel {dv:.2e} max|dF|/max|F| {dF:.2e} rel dEpot "
+    print(f"lisio dense {path} n={n}: dpos {dp:.2e} dvel {dv:.2e} max|dF|/max|F| {dF:.2e} rel dEpot "
           f"{abs(ep - ep0) / abs(ep0):.2e}; rows {st['max_neighbors']} / angular {st['max_angular']}, "
           f"builds {st['n_rebuilds']}, capacity retries {st['n_capacity_retries']}")
     assert st["max_angular"] > 64 and st["n_capacity_retries"] >= 1 and st["n_rebuilds"] >= 4
