@@ -424,6 +424,57 @@ def test_capacity_retry_md_cell_bins(A):
     assert abs(ep1 + ek1 - ep0 - ek0) < 1e-10 * abs(ep0 + ek0)
 
 
+def _filling_cell_system():
+    """272 O atoms in a 10.5 A periodic box of 2 x 2 x 2 list cells (5.25 A
+    at R_list = 5.0 A): 120 on a grid in cell (0, 0, 0), 20 in each other
+    cell, and 12 just beyond the face x = 5.25 A of cell (0, 0, 0), moving
+    into it at 30 A/ps.  The mean cell count plans the per-cell row kernel;
+    cell (0, 0, 0) passes its 128 atoms about ten steps in."""
+    g = np.random.default_rng(21)
+    L = 10.5
+    c = L / 2
+    a, b = c / 5, c / 3
+    pts = [(a * (i + 0.5), a * (j + 0.5), a * (k + 0.5)) for i in range(5) for j in range(5) for k in range(5)][:120]
+    for cx in range(2):
+        for cy in range(2):
+            for cz in range(2):
+                if cx == cy == cz == 0:
+                    continue
+                pts += [(cx * c + b * (i + 0.5), cy * c + b * (j + 0.5), cz * c + b * (k + 0.5))
+                        for i in range(3) for j in range(3) for k in range(3)][:20]
+    n0 = len(pts)
+    pts += [(c + 0.12, 0.6 + 1.2 * j, 0.7 + 1.6 * k) for j in range(4) for k in range(3)]
+    pos = np.array(pts) + g.uniform(-0.05, 0.05, size=(len(pts), 3))
+    return I.System(pos, np.ones(len(pts), np.int32), np.array([L, L, L]), np.ones(3, dtype=np.uint8)), n0
+
+
+def test_md_cell_bin_overflow_falls_back(A, orc):
+    """A list cell that fills beyond the per-cell row kernel's 128 atoms
+    inside an MD chunk (the integrator's cell bins overflow at a build): the
+    chunk is redone from its start on the per-atom row kernels, and the run
+    ends where the oracle's velocity Verlet does."""
+    m = small_model(nr=5, na=3, rr=4.5, ra=3.5)
+    s, n0 = _filling_cell_system()
+    v = I.maxwell_boltzmann(m.masses[s.species], 300.0, 5)
+    v[n0:, 0] = -30.0
+    ctx = A.Context(m, "fp64", skin=0.5)
+    ctx.set_rebuild_every(5)
+    p1, v1, ep, ek, F = ctx.md_step(s.pos, v, s.species, s.box, s.pbc, 5e-4, 20)
+    st = ctx.stats()
+    ctx.close()
+    p0, v0, ep0, ek0, F0 = orc.md_vv(m, s.pos, v, s.species, m.masses, s.box, s.pbc, 5e-4, 20)
+    in0 = int(np.all(p0 % s.box < s.box / 2, axis=1).sum())
+    dp = float(np.abs((p1 - p0 + s.box / 2) % s.box - s.box / 2).max())
+    dv = float(np.abs(v1 - v0).max() / np.abs(v0).max())
+    dF = float(np.abs(F - F0).max() / np.abs(F0).max())
+    print(f"cell (0,0,0) ends with {in0} atoms; retries {st['n_capacity_retries']}, builds {st['n_rebuilds']}; "
+          f"dpos {dp:.2e} dvel {dv:.2e} max|dF|/max|F| {dF:.2e}")
+    assert in0 > 128
+    assert st["n_capacity_retries"] >= 1
+    assert dp <= 1e-9 and dv <= 1e-9 and dF <= 1e-9
+    assert abs(ep + ek - ep0 - ek0) <= 1e-10 * abs(ep0 + ek0)
+
+
 def test_md_resume_is_bitwise(A):
     """100 steps == 50 steps + (positions, velocities) handed back + 50 steps."""
     m = I.load_model("water64")
