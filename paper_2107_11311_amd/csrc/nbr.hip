@@ -548,11 +548,17 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
   // wavefront per atom; the radial-only entries are staged as (slot, stencil)
   const int c0 = s_pref[13];
   uint32_t* rad_t = s_rad + (size_t)wv * p.cap;
-  // the FP32 radii carry a relative margin of 1e-4 in r^2 (about 20 times
-  // the rounding of r^2 from FP32 coordinates below 1000 A), so no pair
-  // within the list radius in FP64 is left out; the few pairs just beyond it
-  // that enter contribute nothing
-  const float r_ang2f = (float)(p.r_ang2 * (1.0 + 1e-4)), r_list2f = (float)(p.r_list2 * (1.0 + 1e-4));
+  // The FP32 radii carry a margin d well above the FP32 rounding of the
+  // displacements (coordinates up to the largest box edge Lm lose at most
+  // 2^-24 Lm each; d = max(2^-20 Lm, 5e-5 R)), so no pair within the list
+  // radius in FP64 is left out and the skin keeps its guarantee; the few
+  // pairs just beyond it that enter contribute nothing
+  const double lm = fmax(b.L[0], fmax(b.L[1], b.L[2]));
+  auto padded = [&](double r2) {
+    const double r = sqrt(r2), d = fmax(0x1p-20 * lm, 5e-5 * r);
+    return (float)((r + d) * (r + d));
+  };
+  const float r_ang2f = padded(p.r_ang2), r_list2f = padded(p.r_list2);
   for (int ai = wv; ai < ncen; ai += kRowWaves) {
     const int i = (int)(s_key[c0 + ai] & kAtomMask);
     const float xi0 = s_pos[c0 + ai], xi1 = s_pos[tp + c0 + ai], xi2 = s_pos[2 * tp + c0 + ai];
