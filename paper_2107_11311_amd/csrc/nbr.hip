@@ -584,7 +584,23 @@ __global__ __launch_bounds__(64 * kRowWaves) __attribute__((amdgpu_num_sgpr(80))
       const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
       const bool self = q == i && k_cell == 13;
       const bool ok = in && !self;
-      if (ok && r2 == 0.0f) atomicOr(p.flags, kFlagOverlap);
+      if (ok && r2 == 0.0f) {
+        // coincident in FP32: overlapping only if coincident in FP64 too
+        // (the atoms' wrapped coordinates and the cell's image shift)
+        const int code = s_code[k_cell];
+        double e2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          double xq = p.pos[3 * (size_t)q + a], xa = p.pos[3 * (size_t)i + a];
+          if (p.pbc[a]) {
+            xq = wrap_coord(xq, b.L[a]);
+            xa = wrap_coord(xa, b.L[a]);
+          }
+          const int sh = (a == 0 ? code % 3 : a == 1 ? (code / 3) % 3 : code / 9) - 1;
+          const double d = (xq - xa) + (double)sh * b.L[a];
+          e2 += d * d;
+        }
+        if (e2 == 0.0) atomicOr(p.flags, kFlagOverlap);
+      }
       const bool ang = ok && r2 < r_ang2f;
       const bool rad = ok && !ang && r2 < r_list2f;
       const uint64_t below = (1ull << lane) - 1ull;

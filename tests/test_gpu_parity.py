@@ -202,6 +202,21 @@ def test_error_paths(A):
     # the context still works after errors
     E, _, _ = ctx.energy_forces(s.pos, s.species, s.box, s.pbc)
     assert np.isfinite(E)
+    # two atoms 1e-9 A apart are distinct (no overlap error), also where the
+    # per-cell list kernel sees them coincide in FP32 (27 atoms per cell here)
+    w = I.water_box(256, 71)
+    c2 = A.Context(small_model(nr=5, na=3, rr=4.5, ra=3.5), "fp64", skin=0.5)
+    for base in (c2, ctx):
+        sy = w if base is c2 else s
+        p = sy.pos.copy()
+        p[7] = p[8] + np.array([1e-9, 0.0, 0.0])
+        E, _, F = base.energy_forces(p, sy.species, sy.box, sy.pbc)
+        assert np.isfinite(E) and np.all(np.isfinite(F))
+        p[7] = p[8]
+        with pytest.raises(A.AenetError) as e:
+            base.energy_forces(p, sy.species, sy.box, sy.pbc)
+        assert e.value.code == A.AENET_E_OVERLAP
+    c2.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
